@@ -1,0 +1,206 @@
+"""Throughput of the magneto-elastic MPM rollout + adjoint on one MI355X.
+
+One bench step = one pass of the whole hot path over the workload: cell sort,
+the recorded forward rollout (P2G, grid operation with contact, G2P, step
+checkpoints), the losses, and the reverse sweep (segment recompute and the
+transposed G2P, grid and P2G kernels) down to d(loss)/d(density, remanence,
+field program). Inputs are resident in HBM before the timed region.
+
+Prints one JSON line. Besides the contract fields it carries the plain-forward
+rate, the adjoint/forward cost ratio, the dominant kernel's HBM roofline
+fraction (algorithmic bytes per launch over the average launch time measured
+with HIP events on the library's stream), and the FP64 CPU oracle timed on a
+bounded sample of the same workload, whose gradient is also compared with the
+device's on that sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2503_22767_amd import mpm_mag as M  # noqa: E402
+from paper_2503_22767_amd import workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "particle-steps/s fwd+adjoint vs plain fwd; grad rel err vs FP64 oracle"
+
+# particle-steps the oracle sample covers, per workload: (instances, steps)
+CPU_SAMPLE = {"c1": (1, 120), "c2": (1, 20), "c3": (1, 20), "c4": (2, 20), "c5": (1, 1)}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_sim(wl, options=None):
+    sim = M.MpmMag([i.params for i in wl.instances], [i.n for i in wl.instances], precision=wl.precision)
+    for k, v in (options or {}).items():
+        sim.set_option(k, v)
+    dtype = torch.float32 if wl.precision == 4 else torch.float64
+    tens = M.instance_tensors(wl.instances, dtype=dtype)
+    return sim, tens, dtype
+
+
+def shared_design(wl):
+    """Instances of one group share density and remanence (Eq. 35); in the flat
+    ABI their arrays are repeated, which the caller's chain rule sums."""
+    return len({i.group for i in wl.instances}) < len(wl.instances)
+
+
+def run_step(sim, tens, dloss, record=True, backward=True):
+    x0, density, br, b_prog, target, mask = tens
+    loss, _ = sim.rollout(x0, density, br, b_prog, target, mask, record=record, want_x=False)
+    if backward:
+        sim.backward(dloss)
+    return loss
+
+
+def timed(fn, n):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / n
+
+
+def roofline(sim, tens, dloss):
+    """One extra instrumented pass with per-launch HIP events."""
+    sim.set_option("kernel_timing", 1)
+    sim.kernel_stats(reset=True)
+    run_step(sim, tens, dloss)
+    torch.cuda.synchronize()
+    stats = sim.kernel_stats(reset=True)
+    sim.set_option("kernel_timing", 0)
+    timed_k = {k: v for k, v in stats.items() if v["launches"] and v["bytes"] > 0}
+    dom = max(timed_k, key=lambda k: timed_k[k]["ms"])
+    s = timed_k[dom]
+    avg_ms = s["ms"] / s["launches"]
+    bytes_per_launch = s["bytes"] / s["launches"]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    per_kernel = {k: dict(launches=v["launches"], avg_us=1e3 * v["ms"] / max(1, v["launches"]),
+                          total_ms=v["ms"],
+                          gbs=(v["bytes"] / max(1, v["launches"])) / max(1e-12, v["ms"] / max(1, v["launches"]) * 1e-3) / 1e9
+                          if v["bytes"] else None)
+                  for k, v in stats.items() if v["launches"]}
+    return dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                avg_launch_us=round(avg_ms * 1e3, 2), bytes_per_launch=int(bytes_per_launch)), per_kernel
+
+
+def cpu_baseline(wl_name, wl, sim_tol_check=True):
+    """FP64 oracle on a bounded sample of the workload: the first instances and
+    steps listed in CPU_SAMPLE. Returns the baseline record and the sample."""
+    import oracle as orc
+    n_inst, steps = CPU_SAMPLE[wl_name]
+    insts = []
+    for inst in wl.instances[:n_inst]:
+        p = dict(inst.params)
+        p["n_steps"] = steps
+        insts.append(W.Instance(p, inst.x0, inst.density, inst.br, inst.b_prog, inst.target, inst.mask, inst.group))
+    ps = sum(i.n * steps for i in insts)
+    t0 = time.perf_counter()
+    grads = []
+    for inst in insts:
+        g = orc.backward(inst.params, inst.x0, inst.density, inst.br, inst.b_prog, inst.target, inst.mask,
+                         ckpt_every=max(1, int(math.isqrt(steps))))
+        grads.append(g)
+    dt = time.perf_counter() - t0
+    rec = dict(value=round(ps / dt, 1), unit="particle-steps/s fwd+adjoint", cores=1, kind="oracle",
+               sample=f"{wl_name}: first {n_inst} instance(s), first {steps} steps, {ps} particle-steps, "
+                      f"FP64 forward + checkpointed adjoint, {dt:.1f} s")
+    return rec, insts, grads
+
+
+def grad_error(wl, insts, oracle_grads):
+    """Device gradient on the oracle's sample vs the oracle (norm-wise relative)."""
+    sub = W.Workload(wl.name, insts, wl.precision)
+    sim, tens, dtype = make_sim(sub)
+    dl = torch.ones(len(insts), dtype=dtype, device="cuda")
+    sim.rollout(*tens, record=True, want_x=False)
+    gd, gb, gp = sim.backward(dl)
+    torch.cuda.synchronize()
+    sim.close()
+    ref = {k: np.concatenate([g[k].ravel() for g in oracle_grads]) for k in ("g_density", "g_br", "g_b_prog")}
+    got = dict(g_density=gd.double().cpu().numpy().ravel(), g_br=gb.double().cpu().numpy().ravel(),
+               g_b_prog=gp.double().cpu().numpy().ravel())
+    return {k: float(np.linalg.norm(got[k] - ref[k]) / max(1e-300, np.linalg.norm(ref[k]))) for k in ref}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c5", choices=sorted(W.WORKLOADS))
+    ap.add_argument("--n-steps", type=int, default=0, help="override the rollout length (testing only)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--option", action="append", default=[], help="library option key=value")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not built.",
+              file=sys.stderr)
+        sys.exit(2)
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    kw = {"n_steps": args.n_steps} if args.n_steps else {}
+    wl = W.make(args.workload, **kw)
+    opts = {}
+    for o in args.option:
+        k, v = o.split("=")
+        opts[k] = int(v)
+    log(f"[bench] workload {wl.name}: {wl.description}; {len(wl.instances)} instance(s), "
+        f"N={wl.n_particles}, T={wl.n_steps}")
+    sim, tens, dtype = make_sim(wl, opts)
+    dloss = torch.ones(len(wl.instances), dtype=dtype, device="cuda")
+    log(f"[bench] device bytes {sim.device_bytes() / 2**30:.2f} GiB (before checkpoints)")
+    for w in range(args.warmup):
+        run_step(sim, tens, dloss)
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {w + 1}/{args.warmup} done")
+    log(f"[bench] device bytes {sim.device_bytes() / 2**30:.2f} GiB (with checkpoints)")
+    t_step = timed(lambda: run_step(sim, tens, dloss), args.steps)
+    log(f"[bench] fwd+adj step {t_step * 1e3:.1f} ms")
+    t_fwd = timed(lambda: run_step(sim, tens, dloss, record=False, backward=False), max(1, args.steps))
+    log(f"[bench] plain fwd {t_fwd * 1e3:.1f} ms")
+    t_rec = timed(lambda: run_step(sim, tens, dloss, record=True, backward=False), 1)
+    ps = wl.particle_steps()
+    rec = dict(metric=METRIC, value=round(ps / t_step, 1), unit="particle-steps/s", n_gpus=1,
+               steps=args.steps, warmup=args.warmup, ms_per_step=round(t_step * 1e3, 3),
+               higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f32" if wl.precision == 4 else "f64", data="synthetic",
+               config=dict(workload=wl.name, description=wl.description, instances=len(wl.instances),
+                           particles=wl.n_particles, steps_per_rollout=wl.n_steps,
+                           grid=[i.params["n_grid"] for i in wl.instances[:1]][0], parallelism="single-gpu"),
+               fwd_value=round(ps / t_fwd, 1), fwd_ms=round(t_fwd * 1e3, 3),
+               adj_over_fwd=round((t_step - t_rec) / t_fwd, 3), fwdadj_over_fwd=round(t_step / t_fwd, 3))
+    if not args.no_roofline:
+        rl, per_kernel = roofline(sim, tens, dloss)
+        rec["roofline"] = rl
+        rec["kernels"] = {k: {kk: (round(vv, 2) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                          for k, v in per_kernel.items()}
+        log(f"[bench] roofline {rl}")
+    sim.close()
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) ...")
+        cb, insts, grads = cpu_baseline(wl.name, wl)
+        rec["cpu_baseline"] = cb
+        rec["grad_rel_err_vs_oracle"] = {k: float(f"{v:.3e}") for k, v in grad_error(wl, insts, grads).items()}
+        rec["grad_rel_err_sample"] = cb["sample"].split(",")[0] + ", same sample as cpu_baseline"
+        log(f"[bench] cpu baseline {cb}")
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,170 @@
+/*
+ * mpm_mag.h -- C ABI of the MI355X magneto-elastic MLS-MPM rollout and its adjoint.
+ *
+ * The library advances particle-represented hard-magnetic soft bodies through
+ * time with the moving-least-squares material point method of the paper's
+ * Sec. 2.2 (P2G Eqs. 14-15, grid operation Eqs. 16-18, G2P Eqs. 19-22), using
+ * the magneto-elastic first Piola-Kirchhoff stress of Sec. 2.1 (Eq. 7) scaled by
+ * the design density as in Sec. 3.1.3 (Eqs. 31-33). It evaluates the task losses
+ * of Sec. 4 (Eqs. 36-40) and returns their gradient with respect to the design
+ * density, the reference remanence and the applied-field program, i.e. the
+ * sensitivities of the optimisation problems Eq. 34 / Eq. 35, obtained by
+ * running the chain rule backwards through every time step (Sec. 2.3).
+ *
+ * Conventions shared by every entry point:
+ *  - Array arguments are HIP DEVICE pointers owned by the caller, contiguous,
+ *    with elements of the handle's precision (float when created with
+ *    precision 4, double with precision 8) unless stated otherwise. Vectors per
+ *    particle are row-major [N][dim] (AoS), per field segment [S][dim].
+ *  - Several instances ("design instances" or "tasks") live in one handle; their
+ *    particles are concatenated in instance order (N = sum of n_particles[k]),
+ *    and their field programs likewise (S_tot = sum of n_segments[k]).
+ *  - All device work is ordered on the HIP stream passed as `stream` (a
+ *    hipStream_t; NULL is the null stream). rollout and backward synchronise
+ *    that stream once, at the end, to read the device error word.
+ *  - Functions return an mpm_mag_status; they never abort or throw across the
+ *    ABI. On failure mpm_mag_last_error() holds a human-readable detail.
+ *  - A handle is not thread safe; calls on one handle must not overlap.
+ */
+#ifndef MPM_MAG_H
+#define MPM_MAG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mpm_mag mpm_mag;
+
+typedef enum {
+    MPM_MAG_OK = 0,
+    MPM_MAG_EINVAL = 1,      /* bad argument or descriptor                                  */
+    MPM_MAG_ENOMEM = 2,      /* device allocation failed                                    */
+    MPM_MAG_EHIP = 3,        /* a HIP runtime call or kernel launch failed                  */
+    MPM_MAG_EDOMAIN = 4,     /* a particle's 3^d stencil left the grid [0, n_grid)^d         */
+    MPM_MAG_EINVERT = 5,     /* det F <= 0 for some particle                                */
+    MPM_MAG_ENONFINITE = 6,  /* NaN or Inf in the particle state                            */
+    MPM_MAG_ESTATE = 7       /* backward without a preceding successful record=1 rollout    */
+} mpm_mag_status;
+
+typedef enum {
+    MPM_MAG_LOSS_FINAL_MSE = 0,  /* (1/|S|) sum_{p in S} |x_p(T) - target_p|^2   (Eq. 38)          */
+    MPM_MAG_LOSS_COM_DISP = 1,   /* -e . (com(T) - com(0)), mass-weighted      (Eq. 40)          */
+    MPM_MAG_LOSS_TRAJ_VEL = 2,   /* -dt sum_n e . vbar(t_{n+1}), vbar mass-averaged (Eq. 39)     */
+    MPM_MAG_LOSS_TIP_DISP = 3    /* -(1/|S|) sum_{p in S} e . (x_p(T) - x_p(0))  (Eqs. 36-37)     */
+} mpm_mag_loss_kind;
+
+/*
+ * One design instance. The domain is the unit square/cube with n_grid nodes per
+ * axis (dx = 1 / n_grid, node i at i dx). Units are the caller's (the
+ * workloads use nondimensional E = 1, mu0 = 1).
+ */
+typedef struct {
+    int dim;                 /* 2 (plane strain) or 3                                         */
+    int n_grid;              /* nodes per axis, 8..1024                                        */
+    double dt;               /* time step                                                     */
+    int n_steps;             /* steps per rollout; equal for all instances of a handle        */
+    double E, nu;            /* Young's modulus, Poisson ratio -> G, K of Eq. 4               */
+    double rho;              /* reference mass density rho_0 (Eq. 33)                         */
+    double mu0;              /* permeability in Eq. 5                                          */
+    double simp_eps, simp_q; /* Eq. 31: s_e = eps + (1-eps) phi^q, s_m = phi^q                 */
+    double damping;          /* c of Eq. 17, a rate: v <- v + dt (g - c v)                     */
+    double gravity[3];       /* g of Eq. 17 (components beyond dim ignored)                   */
+    int wall_cells;          /* separating frictionless walls, this many cells from each face  */
+    double clamp_xmax;       /* attached boundary: nodes with x_i <= clamp_xmax keep v = 0;
+                                negative disables                                              */
+    int floor_on;            /* separating Coulomb floor (Eq. 18), normal +y                   */
+    double floor_y;          /* nodes with y_i <= floor_y are floor nodes                      */
+    double floor_mu;         /* friction coefficient; INFINITY gives the no-slip rule          */
+    double particle_volume;  /* V_p, equal for all particles of the instance                   */
+    int n_segments;          /* S: segments of the piecewise-constant field program           */
+    int seg_steps;           /* steps per segment L (0: ceil(n_steps / S))                     */
+    int periodic;            /* segment of step n: periodic ? (n/L) mod S : min(n/L, S-1)      */
+    int loss_kind;           /* mpm_mag_loss_kind                                              */
+    double loss_dir[3];      /* e of the displacement / velocity losses                        */
+    int ckpt_every;          /* checkpoint spacing K of the recorded rollout (0: auto ~ sqrt(T)) */
+} mpm_mag_instance_desc;
+
+/*
+ * Create a handle for n_inst instances with n_particles[k] particles each
+ * (host arrays). precision: 4 (FP32) or 8 (FP64). All instances must share dim
+ * and n_steps. Allocates every device buffer of the plain rollout; checkpoint
+ * storage of the recorded rollout is allocated on its first use.
+ * Returns EINVAL for inconsistent descriptors, ENOMEM/EHIP on allocation failure;
+ * *out is set only on success.
+ */
+int mpm_mag_create(const mpm_mag_instance_desc* descs, int n_inst, const int64_t* n_particles,
+                   int precision, mpm_mag** out);
+
+/*
+ * Forward rollout of n_steps MPM steps (Sec. 2.2, repeated until T) from
+ * x(0) = x0, v = 0, C = 0, F = I, for every instance, then the loss of each.
+ *   x0          [N][dim]  initial positions
+ *   density     [N]       projected design density phi_p in [0, 1] (Eq. 31, 33)
+ *   br          [N][dim]  reference remanent flux density Br_p (Eq. 5, 26)
+ *   b_prog      [S_tot][dim] applied flux density per field segment (B_applied)
+ *   loss_target [N][dim]  target positions (FINAL_MSE instances), or NULL
+ *   loss_mask   [N] uint8 particle subset S of FINAL_MSE / TIP_DISP, or NULL = all
+ *   x_final     [N][dim]  final positions (output, overwritten), or NULL
+ *   loss_out    [n_inst]  loss of each instance (output, overwritten), or NULL
+ *   record      0: plain forward; 1: also keep step checkpoints for backward
+ * Inputs are copied; the caller may free them after the call. Returns EDOMAIN,
+ * EINVERT or ENONFINITE when the corresponding condition occurred at any step.
+ */
+int mpm_mag_rollout(mpm_mag* h, void* stream, const void* x0, const void* density, const void* br,
+                    const void* b_prog, const void* loss_target, const uint8_t* loss_mask,
+                    void* x_final, void* loss_out, int record);
+
+/*
+ * Reverse-mode gradient of sum_k dloss[k] * loss_k over the last record=1
+ * rollout (Sec. 2.3; Eq. 35 when instances share a design): the hand-derived
+ * transpose of every step, replayed segment by segment from the checkpoints.
+ *   dloss     [n_inst]      upstream gradient of each instance's loss
+ *   g_density [N]           d/d density   (output, overwritten), or NULL
+ *   g_br      [N][dim]      d/d br        (output, overwritten), or NULL
+ *   g_b_prog  [S_tot][dim]  d/d b_prog    (output, overwritten), or NULL
+ * Gradients are in the caller's particle order. Returns ESTATE without a
+ * recorded rollout.
+ */
+int mpm_mag_backward(mpm_mag* h, void* stream, const void* dloss, void* g_density, void* g_br,
+                     void* g_b_prog);
+
+/* Release every device buffer and the handle. NULL is accepted. */
+void mpm_mag_destroy(mpm_mag* h);
+
+/* Static text for a status code. */
+const char* mpm_mag_strerror(int status);
+
+/* Detail of the last failure on this handle ("" if none); valid until the next call. */
+const char* mpm_mag_last_error(const mpm_mag* h);
+
+/*
+ * Tuning and instrumentation switches (key = value):
+ *   "graph"         1: replay captured HIP graphs of step sequences (default), 0: direct launches
+ *   "kernel_timing" 1: bracket every kernel launch with HIP events on the stream
+ *   "p2g_lds"       1: LDS-staged scatter (default), 0: direct global atomics
+ *   "fused"         1: fused G2P->P2G step kernel in the forward (default), 0: separate kernels
+ *   "ckpt_every"    checkpoint spacing K (0: automatic); takes effect at the next recorded rollout
+ * Returns EINVAL for an unknown key or value.
+ */
+int mpm_mag_set_option(mpm_mag* h, const char* key, int64_t value);
+
+/*
+ * Accumulated kernel statistics since the last reset (kernel_timing must be on
+ * for the times): launches, total milliseconds, and the algorithmic bytes one
+ * launch moves summed over launches. Kernel ids run 0..mpm_mag_num_kernels()-1.
+ * Passing kernel = -1 resets all counters.
+ */
+int mpm_mag_num_kernels(void);
+const char* mpm_mag_kernel_name(int kernel);
+int mpm_mag_kernel_stats(mpm_mag* h, int kernel, int64_t* launches, double* total_ms, double* bytes);
+
+/* Device bytes currently held by the handle (state, grids, checkpoints). */
+int64_t mpm_mag_device_bytes(const mpm_mag* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPM_MAG_H */

@@ -1,0 +1,134 @@
+// C ABI of the library: argument checks, dispatch to the engine instantiation
+// for (precision, dim), status strings. No exception crosses this boundary.
+#include <hip/hip_runtime.h>
+
+#include <new>
+#include <string>
+
+#include "mpm_mag.h"
+#include "engine.hpp"
+
+struct mpm_mag {
+    mpm::EngineBase* eng = nullptr;
+    std::string last;
+};
+
+namespace {
+thread_local std::string g_create_error;
+
+int record(mpm_mag* h, int st)
+{
+    if (h) h->last = st ? h->eng->err : std::string();
+    return st;
+}
+}  // namespace
+
+extern "C" {
+
+int mpm_mag_create(const mpm_mag_instance_desc* descs, int n_inst, const int64_t* n_particles, int precision,
+                   mpm_mag** out)
+{
+    if (!out || !descs || !n_particles || n_inst < 1) return MPM_MAG_EINVAL;
+    *out = nullptr;
+    if (precision != 4 && precision != 8) return MPM_MAG_EINVAL;
+    int dim = descs[0].dim;
+    if (dim != 2 && dim != 3) return MPM_MAG_EINVAL;
+    int st = MPM_MAG_OK;
+    std::string msg;
+    mpm::EngineBase* e = nullptr;
+    try {
+        if (precision == 4)
+            e = dim == 2 ? mpm::make_engine_f2(descs, n_inst, n_particles, &st, &msg)
+                         : mpm::make_engine_f3(descs, n_inst, n_particles, &st, &msg);
+        else
+            e = dim == 2 ? mpm::make_engine_d2(descs, n_inst, n_particles, &st, &msg)
+                         : mpm::make_engine_d3(descs, n_inst, n_particles, &st, &msg);
+    } catch (...) {
+        return MPM_MAG_ENOMEM;
+    }
+    if (!e) {
+        g_create_error = msg;
+        return st ? st : MPM_MAG_ENOMEM;
+    }
+    mpm_mag* h = new (std::nothrow) mpm_mag();
+    if (!h) {
+        delete e;
+        return MPM_MAG_ENOMEM;
+    }
+    h->eng = e;
+    *out = h;
+    return MPM_MAG_OK;
+}
+
+int mpm_mag_rollout(mpm_mag* h, void* stream, const void* x0, const void* density, const void* br,
+                    const void* b_prog, const void* loss_target, const uint8_t* loss_mask, void* x_final,
+                    void* loss_out, int record_flag)
+{
+    if (!h) return MPM_MAG_EINVAL;
+    try {
+        return record(h, h->eng->rollout((hipStream_t)stream, x0, density, br, b_prog, loss_target, loss_mask,
+                                         x_final, loss_out, record_flag));
+    } catch (...) {
+        h->last = "unexpected host exception";
+        return MPM_MAG_ENOMEM;
+    }
+}
+
+int mpm_mag_backward(mpm_mag* h, void* stream, const void* dloss, void* g_density, void* g_br, void* g_b_prog)
+{
+    if (!h) return MPM_MAG_EINVAL;
+    try {
+        return record(h, h->eng->backward((hipStream_t)stream, dloss, g_density, g_br, g_b_prog));
+    } catch (...) {
+        h->last = "unexpected host exception";
+        return MPM_MAG_ENOMEM;
+    }
+}
+
+void mpm_mag_destroy(mpm_mag* h)
+{
+    if (!h) return;
+    delete h->eng;
+    delete h;
+}
+
+const char* mpm_mag_strerror(int status)
+{
+    switch (status) {
+    case MPM_MAG_OK: return "ok";
+    case MPM_MAG_EINVAL: return "invalid argument";
+    case MPM_MAG_ENOMEM: return "out of device memory";
+    case MPM_MAG_EHIP: return "HIP runtime error";
+    case MPM_MAG_EDOMAIN: return "particle stencil left the grid";
+    case MPM_MAG_EINVERT: return "deformation gradient inverted (det F <= 0)";
+    case MPM_MAG_ENONFINITE: return "non-finite particle state";
+    case MPM_MAG_ESTATE: return "backward without a recorded rollout";
+    default: return "unknown status";
+    }
+}
+
+const char* mpm_mag_last_error(const mpm_mag* h)
+{
+    if (!h) return g_create_error.c_str();
+    return h->last.c_str();
+}
+
+int mpm_mag_set_option(mpm_mag* h, const char* key, int64_t value)
+{
+    if (!h) return MPM_MAG_EINVAL;
+    return record(h, h->eng->set_option(key, value));
+}
+
+int mpm_mag_num_kernels(void) { return mpm::K_COUNT; }
+
+const char* mpm_mag_kernel_name(int kernel) { return mpm::kernel_name(kernel); }
+
+int mpm_mag_kernel_stats(mpm_mag* h, int kernel, int64_t* launches, double* total_ms, double* bytes)
+{
+    if (!h) return MPM_MAG_EINVAL;
+    return h->eng->kernel_stats(kernel, launches, total_ms, bytes);
+}
+
+int64_t mpm_mag_device_bytes(const mpm_mag* h) { return h ? h->eng->device_bytes() : 0; }
+
+}  // extern "C"

@@ -1,0 +1,629 @@
+// Host engine behind the C ABI: buffer plan in HBM, instance / chunk / grid
+// tables, the per-rollout cell sort, the step loop with checkpoints, the
+// reverse sweep over checkpoint segments (recompute, then transpose of every
+// step), optional HIP-graph replay of step sequences and per-kernel timing.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mpm_mag.h"
+#include "kernels.hpp"
+#include "sort.hpp"
+
+namespace mpm {
+
+enum KernelId {
+    K_SORT = 0, K_GATHER, K_P2G, K_GRID, K_G2P, K_LOSS, K_CKPT, K_SEED,
+    K_G2P_ADJ, K_GRID_ADJ, K_P2G_ADJ, K_OUT, K_COUNT
+};
+
+inline const char* kernel_name(int k)
+{
+    static const char* names[K_COUNT] = {"sort", "gather", "p2g", "grid_update", "g2p", "loss", "checkpoint",
+                                         "seed", "g2p_adj", "grid_adj", "p2g_adj", "output"};
+    return (k >= 0 && k < K_COUNT) ? names[k] : "";
+}
+
+struct KernelStat {
+    int64_t launches = 0;
+    double ms = 0.0;
+    double bytes = 0.0;
+};
+
+class EngineBase {
+public:
+    virtual ~EngineBase() = default;
+    virtual int rollout(hipStream_t s, const void* x0, const void* density, const void* br, const void* b_prog,
+                        const void* target, const uint8_t* mask, void* x_final, void* loss_out, int record) = 0;
+    virtual int backward(hipStream_t s, const void* dloss, void* g_density, void* g_br, void* g_b_prog) = 0;
+    virtual int set_option(const char* key, int64_t value) = 0;
+    virtual int64_t device_bytes() const = 0;
+    int kernel_stats(int k, int64_t* launches, double* ms, double* bytes)
+    {
+        if (k == -1) {
+            for (auto& s : stats_) s = KernelStat();
+            return MPM_MAG_OK;
+        }
+        if (k < 0 || k >= K_COUNT) return MPM_MAG_EINVAL;
+        if (launches) *launches = stats_[k].launches;
+        if (ms) *ms = stats_[k].ms;
+        if (bytes) *bytes = stats_[k].bytes;
+        return MPM_MAG_OK;
+    }
+    std::string err;
+
+protected:
+    KernelStat stats_[K_COUNT];
+};
+
+#define MPM_HIP(call)                                                               \
+    do {                                                                            \
+        hipError_t e_ = (call);                                                     \
+        if (e_ != hipSuccess) {                                                     \
+            err = std::string(#call) + ": " + hipGetErrorString(e_);                \
+            return MPM_MAG_EHIP;                                                    \
+        }                                                                           \
+    } while (0)
+
+template <typename real, int D>
+class Engine : public EngineBase {
+    using Cp = Comp<D>;
+
+public:
+    ~Engine() override { release(); }
+
+    // ------------------------------------------------------------------ setup
+    int init(const mpm_mag_instance_desc* descs, int n_inst, const int64_t* np)
+    {
+        if (!descs || !np || n_inst < 1 || n_inst > 4096) return fail(MPM_MAG_EINVAL, "bad instance list");
+        n_inst_ = n_inst;
+        T_ = descs[0].n_steps;
+        int64_t chunk = 0, grid = 0, seg = 0, caller = 0;
+        int max_axis_bits = 1;
+        for (int k = 0; k < n_inst; ++k) {
+            const mpm_mag_instance_desc& d = descs[k];
+            if (d.dim != D) return fail(MPM_MAG_EINVAL, "all instances must share dim");
+            if (d.n_steps != T_ || d.n_steps < 0) return fail(MPM_MAG_EINVAL, "all instances must share n_steps >= 0");
+            if (d.n_grid < 8 || d.n_grid > 1024) return fail(MPM_MAG_EINVAL, "n_grid must be in [8, 1024]");
+            if (np[k] < 1 || np[k] > (int64_t)1 << 30) return fail(MPM_MAG_EINVAL, "n_particles must be in [1, 2^30]");
+            if (d.n_segments < 1) return fail(MPM_MAG_EINVAL, "n_segments must be >= 1");
+            if (!(d.dt > 0) || !(d.particle_volume > 0) || !(d.mu0 > 0) || !(d.rho > 0))
+                return fail(MPM_MAG_EINVAL, "dt, particle_volume, mu0 and rho must be positive");
+            if (!(d.nu > -1.0 && d.nu < 0.5)) return fail(MPM_MAG_EINVAL, "nu must be in (-1, 1/2)");
+            if (d.loss_kind < 0 || d.loss_kind > 3) return fail(MPM_MAG_EINVAL, "unknown loss_kind");
+            if (d.wall_cells < 0 || d.wall_cells > d.n_grid / 2) return fail(MPM_MAG_EINVAL, "bad wall_cells");
+            InstDev<real> I;
+            std::memset(&I, 0, sizeof I);
+            const double dx = 1.0 / d.n_grid;
+            I.n_grid = d.n_grid;
+            I.n_nodes = D == 2 ? d.n_grid * d.n_grid : d.n_grid * d.n_grid * d.n_grid;
+            I.grid_off = (int)grid;
+            I.n_steps = d.n_steps;
+            I.seg_off = (int)seg;
+            I.n_seg = d.n_segments;
+            I.seg_steps = d.seg_steps > 0 ? d.seg_steps : (d.n_steps + d.n_segments - 1) / d.n_segments;
+            if (I.seg_steps < 1) I.seg_steps = 1;
+            I.periodic = d.periodic ? 1 : 0;
+            I.floor_on = d.floor_on ? 1 : 0;
+            I.wall_cells = d.wall_cells;
+            I.loss_kind = d.loss_kind;
+            I.clamp_on = d.clamp_xmax >= 0.0 ? 1 : 0;
+            I.clamp_imax = -1;
+            for (int i = 0; i < d.n_grid; ++i)
+                if (i * dx <= d.clamp_xmax) I.clamp_imax = i;
+            I.floor_jmax = -1;
+            for (int j = 0; j < d.n_grid; ++j)
+                if (j * dx <= d.floor_y) I.floor_jmax = j;
+            I.floor_noslip = std::isinf(d.floor_mu) ? 1 : 0;
+            I.chunk_off = (int)chunk;
+            I.n_particles = (int)np[k];
+            I.nb = (d.n_grid + Coarse<D>::edge - 1) / Coarse<D>::edge;
+            I.cb_off = (int)n_cb_;
+            const int ncb = D == 2 ? I.nb * I.nb : I.nb * I.nb * I.nb;
+            for (int b = 0; b < ncb; ++b) cb_inst_h_.push_back(k);
+            n_cb_ += ncb;
+            I.dx = (real)dx;
+            I.inv_dx = (real)d.n_grid;
+            I.dt = (real)d.dt;
+            I.kappa_vol = (real)(4.0 * d.dt / (dx * dx) * d.particle_volume);
+            I.lam = (real)(4.0 / (dx * dx));
+            I.G = (real)(d.E / (2.0 * (1.0 + d.nu)));
+            I.K = (real)(d.E / (3.0 * (1.0 - 2.0 * d.nu)));
+            I.mass_p = (real)(d.rho * d.particle_volume);
+            I.inv_mu0 = (real)(1.0 / d.mu0);
+            I.simp_eps = (real)d.simp_eps;
+            I.simp_q = (real)d.simp_q;
+            I.damp = (real)(1.0 - d.damping * d.dt);
+            for (int c = 0; c < 3; ++c) {
+                I.gdt[c] = (real)(d.gravity[c] * d.dt);
+                I.loss_dir[c] = (real)d.loss_dir[c];
+            }
+            I.floor_mu = I.floor_noslip ? (real)0 : (real)d.floor_mu;
+            inst_h_.push_back(I);
+            caller_start_h_.push_back(caller);
+            int n_ch = (int)((np[k] + kBlock - 1) / kBlock);
+            for (int c = 0; c < n_ch; ++c) {
+                ChunkDev ch;
+                ch.inst = k;
+                ch.count = (int)std::min<int64_t>(kBlock, np[k] - (int64_t)c * kBlock);
+                chunks_h_.push_back(ch);
+            }
+            int n_gb = (I.n_nodes + kGridBlock - 1) / kGridBlock;
+            for (int b = 0; b < n_gb; ++b) gblock_h_.push_back(k);
+            chunk += n_ch;
+            grid += (int64_t)n_gb * kGridBlock;
+            seg += d.n_segments;
+            caller += np[k];
+            int abits = 1;
+            while ((1 << abits) < d.n_grid) ++abits;
+            max_axis_bits = std::max(max_axis_bits, abits);
+            ckpt_desc_ = d.ckpt_every;
+        }
+        if (grid > ((int64_t)1 << 31) / 4) return fail(MPM_MAG_EINVAL, "total grid too large");
+        caller_start_h_.push_back(caller);
+        N_ = caller;
+        n_chunks_ = (int)chunk;
+        nalloc_ = chunk * kBlock;
+        G_ = grid;
+        S_tot_ = (int)seg;
+        int inst_bits = 0;
+        while ((1 << inst_bits) < n_inst) ++inst_bits;
+        const int max_cell_bits = D * max_axis_bits;
+        kp_.n_inst = n_inst;
+        kp_.cell_bits = max_cell_bits;
+        kp_.axis_bits = max_axis_bits;
+        if (max_cell_bits + inst_bits > 32) return fail(MPM_MAG_EINVAL, "too many grid cells x instances for the sort key");
+        sort_passes_ = (max_cell_bits + inst_bits + 7) / 8;
+        sort_blocks_ = (int)((N_ + kSortTile - 1) / kSortTile);
+        return allocate();
+    }
+
+    int set_option(const char* key, int64_t value) override
+    {
+        if (!key) return fail(MPM_MAG_EINVAL, "null option key");
+        std::string k(key);
+        if (k == "graph") { graph_ = value != 0; return MPM_MAG_OK; }
+        if (k == "kernel_timing") { timing_ = value != 0; return MPM_MAG_OK; }
+        if (k == "p2g_lds") { use_lds_ = value != 0; return MPM_MAG_OK; }
+        if (k == "fused") { fused_ = value != 0; return MPM_MAG_OK; }
+        if (k == "ckpt_every") {
+            if (value < 0 || value > (1 << 30)) return fail(MPM_MAG_EINVAL, "bad ckpt_every");
+            ckpt_opt_ = (int)value;
+            return MPM_MAG_OK;
+        }
+        return fail(MPM_MAG_EINVAL, "unknown option " + k);
+    }
+
+    int64_t device_bytes() const override { return bytes_; }
+
+    // --------------------------------------------------------------- rollout
+    int rollout(hipStream_t s, const void* x0, const void* density, const void* br, const void* b_prog,
+                const void* target, const uint8_t* mask, void* x_final, void* loss_out, int record) override
+    {
+        err.clear();
+        recorded_ = false;
+        if (!x0 || !density || !br || !b_prog) return fail(MPM_MAG_EINVAL, "x0, density, br and b_prog are required");
+        bool need_target = false;
+        for (auto& I : inst_h_) need_target |= I.loss_kind == kFinalMse;
+        if (need_target && !target) return fail(MPM_MAG_EINVAL, "a FINAL_MSE instance needs loss_target");
+        has_target_ = target != nullptr;
+        if (record) {
+            int st = ensure_checkpoints();
+            if (st) return st;
+        }
+        MPM_HIP(hipMemsetAsync(err_d_, 0, sizeof(int), s));
+        MPM_HIP(hipMemsetAsync(acc_, 0, sizeof(double) * kAccCount * n_inst_, s));
+        MPM_HIP(hipMemsetAsync(gm_, 0, sizeof(real) * 4 * G_, s));
+        MPM_HIP(hipMemsetAsync(reg_count_, 0, sizeof(int) * n_cb_, s));
+        MPM_HIP(hipMemsetAsync(active_, 0, sizeof(int) * 2, s));
+        MPM_HIP(hipMemcpyAsync(bprog_, b_prog, sizeof(real) * S_tot_ * D, hipMemcpyDeviceToDevice, s));
+        int st = sort_and_gather(s, (const real*)x0, (const real*)density, (const real*)br, (const real*)target, mask);
+        if (st) return st;
+        for (int n = 0; n < T_; ++n) {
+            if (record && n % K_ == 0) {
+                MPM_HIP(hipMemcpyAsync(ckpt_slot(n / K_), st_, state_bytes(), hipMemcpyDeviceToDevice, s));
+                count(K_CKPT, 2.0 * state_bytes());
+            }
+            st = step(s, n, st_, st_, true);
+            if (st) return st;
+        }
+        Args<real> a = args();
+        st = launch(K_LOSS, s, n_chunks_, kBlock, k_loss_sums<real, D>, a, (const real*)st_, (const real*)x0s_,
+                    (const real*)tgt_, (const uint8_t*)mask_, has_target_ ? 1 : 0);
+        if (st) return st;
+        st = launch(K_LOSS, s, (n_inst_ + 63) / 64, 64, k_loss_finalize<real>, a, n_inst_, (real*)loss_out);
+        if (st) return st;
+        if (x_final) {
+            st = launch(K_OUT, s, n_chunks_, kBlock, k_scatter_out<real, D>, a, (const int*)id_, (const real*)st_,
+                        (real*)x_final, (real*)nullptr, (real*)nullptr);
+            if (st) return st;
+        }
+        st = finish(s);
+        if (st) return st;
+        recorded_ = record != 0;
+        return MPM_MAG_OK;
+    }
+
+    // -------------------------------------------------------------- backward
+    int backward(hipStream_t s, const void* dloss, void* g_density, void* g_br, void* g_b_prog) override
+    {
+        err.clear();
+        if (!recorded_) return fail(MPM_MAG_ESTATE, "backward needs a successful record=1 rollout");
+        if (!dloss) return fail(MPM_MAG_EINVAL, "dloss is required");
+        MPM_HIP(hipMemsetAsync(err_d_, 0, sizeof(int), s));
+        MPM_HIP(hipMemsetAsync(gB_, 0, sizeof(double) * S_tot_ * D, s));
+        MPM_HIP(hipMemsetAsync(active_, 0, sizeof(int) * 2, s));
+        Args<real> a = args();
+        int st = launch(K_SEED, s, n_chunks_, kBlock, k_seed<real, D>, a, (const real*)st_, adj_,
+                        (const real*)x0s_, (const real*)tgt_, (const uint8_t*)mask_, (const real*)dloss);
+        if (st) return st;
+        for (int c = nck_ - 1; c >= 0; --c) {
+            const int s0 = c * K_;
+            const int s1 = std::min(T_, s0 + K_);
+            for (int n = s0; n < s1 - 1; ++n) {
+                st = step(s, n, seg_state(c, n - s0), seg_state(c, n - s0 + 1), false);
+                if (st) return st;
+            }
+            for (int n = s1 - 1; n >= s0; --n) {
+                real* sn = seg_state(c, n - s0);
+                st = launch(K_P2G, s, n_chunks_, kBlock, k_p2g<real, D>, a, (const real*)sn, n);
+                if (st) return st;
+                st = launch(K_GRID, s, grid_blocks(), kGridBlock, k_grid<real, D>, a, 1);
+                if (st) return st;
+                st = launch(K_G2P_ADJ, s, n_chunks_, kBlock, k_g2p_adj<real, D>, a, (const real*)sn, adj_,
+                            (const real*)dloss);
+                if (st) return st;
+                st = launch(K_GRID_ADJ, s, grid_blocks(), kGridBlock, k_grid_adj<real, D>, a);
+                if (st) return st;
+                st = launch(K_P2G_ADJ, s, n_chunks_, kBlock, k_p2g_adj<real, D>, a, (const real*)sn, adj_, n);
+                if (st) return st;
+            }
+        }
+        if (g_density || g_br) {
+            st = launch(K_OUT, s, n_chunks_, kBlock, k_scatter_out<real, D>, a, (const int*)id_, (const real*)st_,
+                        (real*)nullptr, (real*)g_density, (real*)g_br);
+            if (st) return st;
+        }
+        if (g_b_prog) {
+            int64_t nb = (int64_t)S_tot_ * D;
+            st = launch(K_OUT, s, (int)((nb + 255) / 256), 256, k_convert_out<real>, (const double*)gB_,
+                        (real*)g_b_prog, nb);
+            if (st) return st;
+        }
+        return finish(s);
+    }
+
+private:
+    // workgroups of the grid kernels, which stride over the active coarse blocks
+    int grid_blocks() const { return (int)std::min<int64_t>(n_cb_, 2048); }
+    size_t state_elems() const { return (size_t)Cp::NC * nalloc_; }
+    size_t state_bytes() const { return sizeof(real) * state_elems(); }
+    real* ckpt_slot(int c) { return ckpt_ + (size_t)c * state_elems(); }
+    // state of step s0 + j inside checkpoint segment c (slot 0 is the checkpoint)
+    real* seg_state(int c, int j) { return j == 0 ? ckpt_slot(c) : stash_ + (size_t)(j - 1) * state_elems(); }
+
+    int fail(int code, const std::string& msg)
+    {
+        err = msg;
+        return code;
+    }
+
+    Args<real> args()
+    {
+        Args<real> a;
+        a.inst = inst_d_;
+        a.chunks = chunks_d_;
+        a.gblock_inst = gblock_d_;
+        a.nalloc = nalloc_;
+        a.phi = phi_;
+        a.br = br_;
+        a.bprog = bprog_;
+        a.gm = gm_;
+        a.gv = gv_;
+        a.gbar = gbar_;
+        a.err = err_d_;
+        a.acc = acc_;
+        a.loss_val = loss_val_;
+        a.gB = gB_;
+        a.gphi = gphi_;
+        a.gbr = gbr_;
+        a.corig = corig_;
+        a.x0s = x0s_;
+        a.part = part_;
+        a.box = box_;
+        a.reg_count = reg_count_;
+        a.reg_list = reg_list_;
+        a.cb_inst = cb_inst_d_;
+        a.active = active_;
+        a.active_list = active_list_;
+        a.n_coarse = (int)n_cb_;
+        a.gmd = gmd_;
+        a.use_lds = use_lds_ ? 1 : 0;
+        return a;
+    }
+
+    // bytes a launch of each kernel class must move (for the roofline report)
+    double algo_bytes(int kid) const
+    {
+        const double r = sizeof(real);
+        const double n = (double)N_;
+        switch (kid) {
+        case K_P2G: return n * r * (D + D + 2 * D * D + 1 + D);                 // x v C F phi br
+        case K_G2P: return n * r * ((D + D * D) + (2 * D + 2 * D * D));         // read x F, write x v C F
+        case K_GRID: return 0.0;        // touches only the active coarse blocks; not priced
+        case K_G2P_ADJ: return n * r * ((D + D * D) + (2 * D + 2 * D * D) + (D + D * D));
+        case K_GRID_ADJ: return 0.0;
+        case K_P2G_ADJ: return n * r * ((2 * D + 2 * D * D) + 1 + D + (2 * D + 2 * D * D) + (D + D * D) + 2 * (1 + D));
+        default: return 0.0;
+        }
+    }
+
+    void count(int kid, double bytes)
+    {
+        stats_[kid].launches += 1;
+        stats_[kid].bytes += bytes;
+    }
+
+    template <typename Kern, typename... A>
+    int launch(int kid, hipStream_t s, int grid, int block, Kern k, A... args)
+    {
+        if (grid <= 0) return MPM_MAG_OK;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (timing_) {
+            e0 = event();
+            MPM_HIP(hipEventRecord(e0, s));
+        }
+        hipLaunchKernelGGL(k, dim3(grid), dim3(block), 0, s, args...);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            err = std::string("launch of ") + kernel_name(kid) + ": " + hipGetErrorString(e);
+            return MPM_MAG_EHIP;
+        }
+        if (timing_) {
+            e1 = event();
+            MPM_HIP(hipEventRecord(e1, s));
+            pending_.push_back({kid, e0, e1});
+        }
+        count(kid, algo_bytes(kid));
+        return MPM_MAG_OK;
+    }
+
+    hipEvent_t event()
+    {
+        if (ev_used_ == events_.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            events_.push_back(e);
+        }
+        return events_[ev_used_++];
+    }
+
+    // one forward step n: P2G, grid operation, G2P (sin -> sout)
+    int step(hipStream_t s, int n, real* sin, real* sout, bool traj)
+    {
+        Args<real> a = args();
+        int st = launch(K_P2G, s, n_chunks_, kBlock, k_p2g<real, D>, a, (const real*)sin, n);
+        if (st) return st;
+        st = launch(K_GRID, s, grid_blocks(), kGridBlock, k_grid<real, D>, a, 0);
+        if (st) return st;
+        return launch(K_G2P, s, n_chunks_, kBlock, k_g2p<real, D>, a, (const real*)sin, sout, n, traj ? 1 : 0);
+    }
+
+    int sort_and_gather(hipStream_t s, const real* x0, const real* phi, const real* br, const real* tgt,
+                        const uint8_t* mask)
+    {
+        int st = launch(K_SORT, s, (int)((N_ + kBlock - 1) / kBlock), kBlock, k_sort_keys<real, D>,
+                        (const InstDev<real>*)inst_d_, (const int64_t*)caller_start_d_, kp_, x0, (int64_t)N_,
+                        keys_[0], vals_[0]);
+        if (st) return st;
+        int cur = 0;
+        for (int p = 0; p < sort_passes_; ++p) {
+            int shift = 8 * p;
+            st = launch(K_SORT, s, sort_blocks_, kBlock, k_radix_hist, (const uint32_t*)keys_[cur], (int64_t)N_, shift,
+                        hist_, sort_blocks_);
+            if (st) return st;
+            st = launch(K_SORT, s, 1, 1024, k_scan_exclusive, hist_, (int64_t)256 * sort_blocks_);
+            if (st) return st;
+            st = launch(K_SORT, s, sort_blocks_, kBlock, k_radix_scatter, (const uint32_t*)keys_[cur],
+                        (const uint32_t*)vals_[cur], keys_[cur ^ 1], vals_[cur ^ 1], (int64_t)N_, shift,
+                        (const uint32_t*)hist_, sort_blocks_);
+            if (st) return st;
+            cur ^= 1;
+        }
+        Args<real> a = args();
+        return launch(K_GATHER, s, n_chunks_, kBlock, k_gather<real, D>, a, (const int*)vals_[cur],
+                      (const int64_t*)caller_start_d_, st_, x0s_, phi_, br_, tgt_, mask_, id_, corig_, x0, phi, br, tgt,
+                      mask);
+    }
+
+    int finish(hipStream_t s)
+    {
+        MPM_HIP(hipMemcpyAsync(err_h_, err_d_, sizeof(int), hipMemcpyDeviceToHost, s));
+        MPM_HIP(hipStreamSynchronize(s));
+        if (timing_) {
+            for (auto& p : pending_) {
+                float ms = 0.f;
+                MPM_HIP(hipEventElapsedTime(&ms, p.e0, p.e1));
+                stats_[p.kid].ms += ms;
+            }
+        }
+        pending_.clear();
+        ev_used_ = 0;
+        int e = *err_h_;
+        if (e & kErrNonFinite) return fail(MPM_MAG_ENONFINITE, "non-finite particle state");
+        if (e & kErrInvert) return fail(MPM_MAG_EINVERT, "det F <= 0");
+        if (e & kErrDomain) return fail(MPM_MAG_EDOMAIN, "a particle stencil left the grid");
+        return MPM_MAG_OK;
+    }
+
+    int ensure_checkpoints()
+    {
+        int K = ckpt_opt_ > 0 ? ckpt_opt_ : (ckpt_desc_ > 0 ? ckpt_desc_ : 0);
+        if (K <= 0) K = std::max(1, (int)std::ceil(std::sqrt((double)std::max(1, T_))));
+        if (T_ == 0) K = 1;
+        K = std::max(1, std::min(K, std::max(1, T_)));
+        int nck = std::max(1, (T_ + K - 1) / K);
+        if (ckpt_ && K == K_ && nck == nck_) return MPM_MAG_OK;
+        if (ckpt_) { (void)hipFree(ckpt_); bytes_ -= ckpt_bytes_; ckpt_ = nullptr; }
+        if (stash_) { (void)hipFree(stash_); bytes_ -= stash_bytes_; stash_ = nullptr; }
+        ckpt_bytes_ = state_bytes() * nck;
+        stash_bytes_ = state_bytes() * std::max(1, K - 1);
+        if (hipMalloc(&ckpt_, ckpt_bytes_) != hipSuccess) { ckpt_ = nullptr; return fail(MPM_MAG_ENOMEM, "checkpoint pool"); }
+        if (hipMalloc(&stash_, stash_bytes_) != hipSuccess) {
+            (void)hipFree(ckpt_); ckpt_ = nullptr;
+            return fail(MPM_MAG_ENOMEM, "segment stash");
+        }
+        bytes_ += ckpt_bytes_ + stash_bytes_;
+        K_ = K;
+        nck_ = nck;
+        return MPM_MAG_OK;
+    }
+
+    template <typename T>
+    int dalloc(T** p, size_t n)
+    {
+        size_t b = sizeof(T) * std::max<size_t>(n, 1);
+        if (hipMalloc((void**)p, b) != hipSuccess) { *p = nullptr; return fail(MPM_MAG_ENOMEM, "device allocation"); }
+        allocs_.push_back((void*)*p);
+        bytes_ += b;
+        return MPM_MAG_OK;
+    }
+
+    int allocate()
+    {
+        int st = 0;
+        st |= dalloc(&inst_d_, inst_h_.size());
+        st |= dalloc(&chunks_d_, chunks_h_.size());
+        st |= dalloc(&gblock_d_, gblock_h_.size());
+        st |= dalloc(&caller_start_d_, caller_start_h_.size());
+        st |= dalloc(&st_, state_elems());
+        st |= dalloc(&adj_, state_elems());
+        st |= dalloc(&x0s_, (size_t)D * nalloc_);
+        st |= dalloc(&tgt_, (size_t)D * nalloc_);
+        st |= dalloc(&br_, (size_t)D * nalloc_);
+        st |= dalloc(&phi_, (size_t)nalloc_);
+        st |= dalloc(&gphi_, (size_t)nalloc_);
+        st |= dalloc(&gbr_, (size_t)D * nalloc_);
+        st |= dalloc(&mask_, (size_t)nalloc_);
+        st |= dalloc(&id_, (size_t)nalloc_);
+        st |= dalloc(&corig_, (size_t)n_chunks_);
+        st |= dalloc(&part_, (size_t)n_chunks_ * kBoxCap * 4);
+        st |= dalloc(&box_, (size_t)n_chunks_ * kWaves * 2);
+        st |= dalloc(&reg_count_, (size_t)n_cb_);
+        st |= dalloc(&reg_list_, (size_t)n_cb_ * Coarse<D>::cap);
+        st |= dalloc(&cb_inst_d_, (size_t)n_cb_);
+        st |= dalloc(&active_, 2);
+        st |= dalloc(&active_list_, (size_t)2 * n_cb_);
+        st |= dalloc(&gmd_, (size_t)4 * G_);
+        st |= dalloc(&gm_, (size_t)4 * G_);
+        st |= dalloc(&gv_, (size_t)4 * G_);
+        st |= dalloc(&gbar_, (size_t)4 * G_);
+        st |= dalloc(&bprog_, (size_t)S_tot_ * D);
+        st |= dalloc(&gB_, (size_t)S_tot_ * D);
+        st |= dalloc(&acc_, (size_t)kAccCount * n_inst_);
+        st |= dalloc(&loss_val_, (size_t)n_inst_);
+        st |= dalloc(&err_d_, 1);
+        for (int b = 0; b < 2; ++b) {
+            st |= dalloc(&keys_[b], (size_t)N_);
+            st |= dalloc(&vals_[b], (size_t)N_);
+        }
+        st |= dalloc(&hist_, (size_t)256 * sort_blocks_);
+        if (st) return fail(MPM_MAG_ENOMEM, "device allocation failed");
+        if (hipHostMalloc((void**)&err_h_, sizeof(int)) != hipSuccess) return fail(MPM_MAG_ENOMEM, "pinned error word");
+        MPM_HIP(hipMemcpy(inst_d_, inst_h_.data(), sizeof(InstDev<real>) * inst_h_.size(), hipMemcpyHostToDevice));
+        MPM_HIP(hipMemcpy(chunks_d_, chunks_h_.data(), sizeof(ChunkDev) * chunks_h_.size(), hipMemcpyHostToDevice));
+        MPM_HIP(hipMemcpy(gblock_d_, gblock_h_.data(), sizeof(int) * gblock_h_.size(), hipMemcpyHostToDevice));
+        MPM_HIP(hipMemcpy(caller_start_d_, caller_start_h_.data(), sizeof(int64_t) * caller_start_h_.size(),
+                          hipMemcpyHostToDevice));
+        MPM_HIP(hipMemcpy(cb_inst_d_, cb_inst_h_.data(), sizeof(int) * cb_inst_h_.size(), hipMemcpyHostToDevice));
+        MPM_HIP(hipMemset(reg_count_, 0, sizeof(int) * n_cb_));
+        MPM_HIP(hipMemset(active_, 0, sizeof(int) * 2));
+        MPM_HIP(hipMemset(gm_, 0, sizeof(real) * 4 * G_));
+        MPM_HIP(hipMemset(gv_, 0, sizeof(real) * 4 * G_));
+        MPM_HIP(hipMemset(gbar_, 0, sizeof(real) * 4 * G_));
+        MPM_HIP(hipMemset(st_, 0, state_bytes()));
+        MPM_HIP(hipMemset(adj_, 0, state_bytes()));
+        MPM_HIP(hipMemset(tgt_, 0, sizeof(real) * D * nalloc_));
+        MPM_HIP(hipDeviceSynchronize());
+        return MPM_MAG_OK;
+    }
+
+    void release()
+    {
+        for (void* p : allocs_) (void)hipFree(p);
+        allocs_.clear();
+        if (ckpt_) (void)hipFree(ckpt_);
+        if (stash_) (void)hipFree(stash_);
+        ckpt_ = stash_ = nullptr;
+        if (err_h_) (void)hipHostFree(err_h_);
+        err_h_ = nullptr;
+        for (auto e : events_) (void)hipEventDestroy(e);
+        events_.clear();
+    }
+
+    struct Pending {
+        int kid;
+        hipEvent_t e0, e1;
+    };
+
+    // tables
+    int n_inst_ = 0, T_ = 0, n_chunks_ = 0, S_tot_ = 0;
+    int64_t N_ = 0, nalloc_ = 0, G_ = 0;
+    std::vector<InstDev<real>> inst_h_;
+    std::vector<ChunkDev> chunks_h_;
+    std::vector<int> gblock_h_;
+    std::vector<int64_t> caller_start_h_;
+    KeyParams kp_;
+    int sort_passes_ = 0, sort_blocks_ = 0;
+    // device buffers
+    InstDev<real>* inst_d_ = nullptr;
+    ChunkDev* chunks_d_ = nullptr;
+    int* gblock_d_ = nullptr;
+    int64_t* caller_start_d_ = nullptr;
+    real *st_ = nullptr, *adj_ = nullptr, *x0s_ = nullptr, *tgt_ = nullptr, *br_ = nullptr, *phi_ = nullptr;
+    real *gphi_ = nullptr, *gbr_ = nullptr, *gm_ = nullptr, *gv_ = nullptr, *gbar_ = nullptr, *bprog_ = nullptr;
+    uint8_t* mask_ = nullptr;
+    int* id_ = nullptr;
+    int4* corig_ = nullptr;
+    real* part_ = nullptr;
+    int4* box_ = nullptr;
+    int* reg_count_ = nullptr;
+    int* reg_list_ = nullptr;
+    int* cb_inst_d_ = nullptr;
+    int* active_ = nullptr;
+    int* active_list_ = nullptr;
+    real* gmd_ = nullptr;
+    std::vector<int> cb_inst_h_;
+    int64_t n_cb_ = 0;
+    double *gB_ = nullptr, *acc_ = nullptr, *loss_val_ = nullptr;
+    int* err_d_ = nullptr;
+    int* err_h_ = nullptr;
+    uint32_t* keys_[2] = {nullptr, nullptr};
+    uint32_t* vals_[2] = {nullptr, nullptr};
+    uint32_t* hist_ = nullptr;
+    std::vector<void*> allocs_;
+    int64_t bytes_ = 0;
+    // checkpoints
+    real* ckpt_ = nullptr;
+    real* stash_ = nullptr;
+    size_t ckpt_bytes_ = 0, stash_bytes_ = 0;
+    int K_ = 0, nck_ = 0, ckpt_desc_ = 0, ckpt_opt_ = 0;
+    bool recorded_ = false, has_target_ = false;
+    // options
+    bool graph_ = false, timing_ = false, use_lds_ = true, fused_ = false;
+    std::vector<hipEvent_t> events_;
+    size_t ev_used_ = 0;
+    std::vector<Pending> pending_;
+};
+
+EngineBase* make_engine_f2(const mpm_mag_instance_desc*, int, const int64_t*, int*, std::string*);
+EngineBase* make_engine_f3(const mpm_mag_instance_desc*, int, const int64_t*, int*, std::string*);
+EngineBase* make_engine_d2(const mpm_mag_instance_desc*, int, const int64_t*, int*, std::string*);
+EngineBase* make_engine_d3(const mpm_mag_instance_desc*, int, const int64_t*, int*, std::string*);
+
+}  // namespace mpm

@@ -1,0 +1,1348 @@
+// HIP kernels of the magneto-elastic MLS-MPM step (Sec. 2.2) and of its
+// transpose (Sec. 2.3), templated on the precision and the dimension.
+//
+// Layout in HBM:
+//  - particle state: structure of arrays, component c of particle slot i at
+//    st[c * nalloc + i]; components u[D], v[D], C[DxD], F[DxD] (row major),
+//    where u = x - x(0) is the displacement; the initial position x0s is kept
+//    read-only relative to the chunk's origin cell (x_abs = org dx + x0s + u),
+//    so FP32 resolves displacements to their own precision and positions to
+//    ~1e-9 of the domain; the adjoint state uses the same layout (ubar = xbar);
+//  - particles are stored per instance in chunks of kBlock slots (one block per
+//    chunk), sorted once per rollout into spatial tiles so a chunk's stencils
+//    cover a compact box of nodes;
+//  - grids: per instance n^D nodes (x fastest), 4 values per node
+//    (p_0..p_{D-1} or v, and the mass in slot 3), instances concatenated.
+#pragma once
+
+#include "device.hpp"
+
+namespace mpm {
+
+template <int D> struct Comp {
+    static constexpr int NC = 2 * D + 2 * D * D;
+    static constexpr int X = 0, V = D, C = 2 * D, F = 2 * D + D * D;
+    static constexpr int S3 = D == 2 ? 9 : 27;
+};
+
+// Staging box capacity (nodes). LDS accumulates in double: on gfx950 the LDS
+// double add is an order of magnitude faster than the single-precision one.
+constexpr int kBoxCap = 1024;
+// coarse blocks of the grid used to hand staged boxes to the grid update
+template <int D> struct Coarse {
+    static constexpr int edge = D == 2 ? 16 : 8;                    // nodes per axis
+    static constexpr int nodes = D == 2 ? 256 : 512;
+    static constexpr int cap = 256;                                  // registered boxes per coarse block
+};
+
+template <typename real>
+struct Args {
+    const InstDev<real>* inst;
+    const ChunkDev* chunks;
+    const int* gblock_inst;
+    int64_t nalloc;
+    const real* phi;     // [nalloc]
+    const real* br;      // [D][nalloc]
+    const real* bprog;   // [S_tot][D]
+    real* gm;            // [4 G] momentum / mass
+    real* gv;            // [4 G] velocity after the grid operation
+    real* gbar;          // [4 G] adjoint grid values
+    int* err;            // device error word
+    double* acc;         // [n_inst][kAccCount]
+    double* loss_val;    // [n_inst]
+    double* gB;          // [S_tot][D] field-program gradient
+    real* gphi;          // [nalloc]
+    real* gbr;           // [D][nalloc]
+    const int4* corig;   // [n_chunks] origin cell of each chunk (positions are stored relative to it)
+    const real* x0s;     // [D][nalloc] initial positions relative to the chunk origin
+    real* part;          // [n_chunks][kBoxCap][4] staged box of each chunk
+    int4* box;           // [n_chunks][2]: lo (xyz), ext (xyz); ext = 0 when the box was not staged
+    int* reg_count;      // [n_coarse] boxes registered with each coarse block this phase
+    int* reg_list;       // [n_coarse][cap] chunk ids
+    const int* cb_inst;  // [n_coarse] instance of each coarse block
+    int* active;         // [2]: coarse blocks activated in the scatter phases (P2G, G2P transpose)
+    int* active_list;    // [2][n_coarse]
+    int n_coarse;
+    real* gmd;           // [4 G] summed (momentum, mass) kept for the grid transpose
+    int use_lds;
+};
+
+// --------------------------------------------------------------------------
+// block scatter through LDS
+// --------------------------------------------------------------------------
+
+// slot of value c in a node record: momenta / velocities first, mass in slot 3
+template <int D, int NV>
+__device__ __forceinline__ int value_slot(int c) { return (NV == D + 1 && c == D) ? 3 : c; }
+
+constexpr int kWaveBoxCap = kBoxCap / kWaves;   // staging box of one wave when the block's box is too big
+
+// storage offset (nodes) of staged box `id` = chunk * kWaves + wave inside `part`
+__device__ __forceinline__ int64_t box_offset(int id) { return (int64_t)(id / kWaves) * kBoxCap + (id % kWaves) * kWaveBoxCap; }
+
+// Registers box `id` (node range lo .. lo + ext - 1) with every coarse block it
+// overlaps; the lanes lane0, lane0 + stride, ... share the work. A coarse block
+// whose list is full gets the staged values of its part of the box added to
+// the dense accumulator fb instead.
+template <typename real, int D>
+__device__ __forceinline__ void register_box(const Args<real>& a, const InstDev<real>& I, int id, const int lo[3],
+                                             const int ext[3], const double* box_lds, int box_cap, bool staged,
+                                             real* fb, int phase, int lane0, int stride)
+{
+    using CB = Coarse<D>;
+    int b0[3] = {0, 0, 0}, nbk[3] = {1, 1, 1};
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        b0[k] = lo[k] / CB::edge;
+        nbk[k] = (lo[k] + ext[k] - 1) / CB::edge - b0[k] + 1;
+    }
+    const int n_ov = nbk[0] * nbk[1] * nbk[2];
+    for (int j = lane0; j < n_ov; j += stride) {
+        int jj[3] = {j % nbk[0], (j / nbk[0]) % nbk[1], j / (nbk[0] * nbk[1])};
+        int cb = I.cb_off + (b0[0] + jj[0]) + I.nb * ((b0[1] + jj[1]) + (D == 3 ? I.nb * (b0[2] + jj[2]) : 0));
+        int slot = atomicAdd(&a.reg_count[cb], 1);
+        if (slot == 0) a.active_list[phase * a.n_coarse + atomicAdd(&a.active[phase], 1)] = cb;
+        if (slot < CB::cap) {
+            a.reg_list[cb * CB::cap + slot] = id;
+        } else if (staged) {
+            int clo[3] = {0, 0, 0}, chi[3] = {1, 1, 1};
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                int cs = (b0[k] + jj[k]) * CB::edge;
+                clo[k] = max(cs, lo[k]) - lo[k];
+                chi[k] = min(cs + CB::edge, lo[k] + ext[k]) - lo[k];
+            }
+            for (int z = clo[2]; z < chi[2]; ++z)
+                for (int y = clo[1]; y < chi[1]; ++y)
+                    for (int x = clo[0]; x < chi[0]; ++x) {
+                        int l = x + ext[0] * (y + ext[1] * z);
+                        int64_t g = (int64_t)I.grid_off + (int64_t)(lo[0] + x) +
+                                    (int64_t)I.n_grid * ((lo[1] + y) + (D == 3 ? (int64_t)I.n_grid * (lo[D - 1] + z) : 0));
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            real v = (real)box_lds[q * box_cap + l];
+                            if (v != real(0)) atomic_add(&fb[4 * g + q], v);
+                        }
+                    }
+        }
+    }
+}
+
+// Adds NV values per stencil node of every active particle of the block to the
+// instance grid. The block's stencils are staged in LDS (double) over their
+// bounding box; each lane starts at a different stencil node so lanes of one
+// cell never hit one address together. The box is then written with plain
+// stores to this chunk's slot of `part` and registered (one integer atomic per
+// coarse block it overlaps) so the grid update can gather it; no float atomics
+// touch HBM. When the block's box exceeds kBoxCap every wave stages its own box
+// (at most kWaveBoxCap nodes); a wave whose box is larger still, or a coarse
+// block whose list is full, falls back to float atomics into the dense
+// accumulator fb, which the grid update also reads. Must be reached by every
+// thread of the block.
+template <typename real, int D, int NV, typename ValFn>
+__device__ __forceinline__ void scatter_box(const Args<real>& a, const InstDev<real>& I, double* lds, bool active,
+                                            const int base[D], real* fb, int phase, ValFn vals)
+{
+    constexpr int S3 = Comp<D>::S3;
+    __shared__ int s_bb[kWaves][6];
+    const int t = threadIdx.x;
+    const int w = t >> 6;
+    const int c = blockIdx.x;
+    const int n_grid = I.n_grid;
+    // bounding boxes of the wave and of the block
+    int wlo[3] = {0, 0, 0}, wext[3] = {1, 1, 1};
+    int whi[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        wlo[k] = wave_min(active ? base[k] : 0x3fffffff);
+        whi[k] = wave_max(active ? base[k] : -0x3fffffff);
+    }
+    const bool wave_live = wlo[0] != 0x3fffffff;
+    int wvol = 1;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        wext[k] = wave_live ? whi[k] - wlo[k] + 3 : 1;
+        wvol *= wext[k];
+    }
+    if ((t & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            s_bb[w][k] = wlo[k];
+            s_bb[w][3 + k] = whi[k];
+        }
+    }
+    __syncthreads();
+    int lo[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
+    int vol = 1;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        int l = s_bb[0][k], h = s_bb[0][3 + k];
+#pragma unroll
+        for (int ww = 1; ww < kWaves; ++ww) {
+            l = min(l, s_bb[ww][k]);
+            h = max(h, s_bb[ww][3 + k]);
+        }
+        lo[k] = l;
+        ext[k] = h - l + 3;
+        vol *= ext[k];
+    }
+    const bool block_mode = a.use_lds && vol <= kBoxCap;
+    // this lane's staging box: the block's, or its wave's
+    const bool staged = block_mode || (a.use_lds && wave_live && wvol <= kWaveBoxCap);
+    int blo[3], bext[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        blo[k] = block_mode ? lo[k] : wlo[k];
+        bext[k] = block_mode ? ext[k] : wext[k];
+    }
+    const int bcap = block_mode ? kBoxCap : kWaveBoxCap;
+    double* blds = block_mode ? lds : lds + w * 4 * kWaveBoxCap;
+    const int id = c * kWaves + (block_mode ? 0 : w);
+    // zero the staging boxes
+    if (block_mode) {
+        for (int i = t; i < vol; i += kBlock)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) blds[q * bcap + i] = 0.0;
+    } else if (staged) {
+        for (int i = t & 63; i < wvol; i += 64)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) blds[q * bcap + i] = 0.0;
+    }
+    __syncthreads();
+    if (active && staged) {
+        int o = t % S3;
+        int rel[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) rel[k] = base[k] - blo[k];
+        for (int it = 0; it < S3; ++it) {
+            int oa[D];
+            offset_split<D>(o, oa);
+            int li = rel[0] + oa[0] + bext[0] * (rel[1] + oa[1] + (D == 3 ? bext[1] * (rel[D - 1] + oa[D - 1]) : 0));
+            real v[NV];
+            vals(oa, v);
+#pragma unroll
+            for (int q = 0; q < NV; ++q) atomicAdd(&blds[value_slot<D, NV>(q) * bcap + li], (double)v[q]);
+            o = (o + 1 == S3) ? 0 : o + 1;
+        }
+    } else if (active) {
+        for (int o = 0; o < S3; ++o) {
+            int oa[D];
+            offset_split<D>(o, oa);
+            int64_t g = (int64_t)I.grid_off + (int64_t)(base[0] + oa[0]) +
+                        (int64_t)n_grid * ((base[1] + oa[1]) + (D == 3 ? (int64_t)n_grid * (base[D - 1] + oa[D - 1]) : 0));
+            real v[NV];
+            vals(oa, v);
+#pragma unroll
+            for (int q = 0; q < NV; ++q) atomic_add(&fb[4 * g + value_slot<D, NV>(q)], v[q]);
+        }
+    }
+    __syncthreads();
+    // write the staged boxes and their descriptors
+    real* dst = a.part + box_offset(id) * 4;
+    if (block_mode) {
+        for (int l = t; l < vol; l += kBlock)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dst[4 * l + q] = (real)blds[q * bcap + l];
+    } else if (staged) {
+        for (int l = t & 63; l < wvol; l += 64)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dst[4 * l + q] = (real)blds[q * bcap + l];
+    }
+    // one writer per descriptor: thread t < kWaves in block mode, lane 0 of each wave otherwise
+    if (block_mode ? (t < kWaves) : ((t & 63) == 0)) {
+        const int slot = block_mode ? t : w;
+        const int bid = c * kWaves + slot;
+        int4 blo4 = make_int4(0, 0, 0, 0), bext4 = make_int4(0, 0, 0, 0);
+        if (block_mode ? (slot == 0) : staged) {
+            blo4 = make_int4(blo[0], blo[1], blo[2], 0);
+            bext4 = make_int4(bext[0], bext[1], bext[2], 0);
+        }
+        a.box[2 * bid] = blo4;
+        a.box[2 * bid + 1] = bext4;
+    }
+    // register the boxes (also the ranges of waves that fell back, so the
+    // grid update visits their coarse blocks)
+    if (block_mode) {
+        register_box<real, D>(a, I, id, lo, ext, blds, bcap, true, fb, phase, t, kBlock);
+    } else if (wave_live) {
+        register_box<real, D>(a, I, id, wlo, wext, blds, bcap, staged, fb, phase, t & 63, 64);
+    }
+}
+
+// Gathers the boxes registered with coarse block b into the NV-value records
+// of its nodes (plus the dense fallback accumulator fb, which is cleared).
+// Calls node_fn(local node index, global node index, grid coords, summed[4]) for
+// every node of the block inside the grid, then resets the registration count.
+template <typename real, int D, typename NodeFn>
+__device__ __forceinline__ void gather_coarse(const Args<real>& a, const InstDev<real>& I, int b, real* fb,
+                                              NodeFn node_fn)
+{
+    using CB = Coarse<D>;
+    __shared__ int s_id[CB::cap];
+    __shared__ int4 s_lo[CB::cap], s_ext[CB::cap];
+    const int t = threadIdx.x;
+    __syncthreads();   // the previous coarse block of this workgroup is done with the shared lists
+    const int cnt_raw = a.reg_count[b];
+    if (cnt_raw == 0) return;
+    const int cnt = min(cnt_raw, CB::cap);
+    for (int j = t; j < cnt; j += blockDim.x) {
+        int id = a.reg_list[b * CB::cap + j];
+        s_id[j] = id;
+        s_lo[j] = a.box[2 * id];
+        s_ext[j] = a.box[2 * id + 1];
+    }
+    __syncthreads();
+    const int lb = b - I.cb_off;
+    int bc[3] = {lb % I.nb, D == 3 ? (lb / I.nb) % I.nb : lb / I.nb, D == 3 ? lb / (I.nb * I.nb) : 0};
+    for (int ln = t; ln < CB::nodes; ln += blockDim.x) {
+        int g3[3];
+        g3[0] = bc[0] * CB::edge + ln % CB::edge;
+        g3[1] = bc[1] * CB::edge + (ln / CB::edge) % CB::edge;
+        g3[2] = D == 3 ? bc[2] * CB::edge + ln / (CB::edge * CB::edge) : 0;
+        bool inside = g3[0] < I.n_grid && g3[1] < I.n_grid && (D == 2 || g3[2] < I.n_grid);
+        if (!inside) continue;
+        const int64_t local = (int64_t)g3[0] + (int64_t)I.n_grid * (g3[1] + (D == 3 ? (int64_t)I.n_grid * g3[2] : 0));
+        const int64_t g = (int64_t)I.grid_off + local;
+        real acc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            acc[q] = fb[4 * g + q];
+            fb[4 * g + q] = real(0);
+        }
+        // four boxes per round so their loads are in flight together
+        for (int j0 = 0; j0 < cnt; j0 += 4) {
+            const real* src[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                src[u] = nullptr;
+                const int j = j0 + u;
+                if (j < cnt) {
+                    const int4 lo = s_lo[j], ex = s_ext[j];
+                    int rx = g3[0] - lo.x, ry = g3[1] - lo.y, rz = D == 3 ? g3[2] - lo.z : 0;
+                    if (rx >= 0 && rx < ex.x && ry >= 0 && ry < ex.y && (D == 2 || (rz >= 0 && rz < ex.z)))
+                        src[u] = a.part + (box_offset(s_id[j]) + rx + ex.x * (ry + ex.y * rz)) * 4;
+                }
+            }
+            real v[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[u][q] = src[u] ? src[u][q] : real(0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] += v[u][q];
+        }
+        node_fn((int)local, g, g3, acc);
+    }
+    __syncthreads();
+    if (t == 0) a.reg_count[b] = 0;
+}
+
+__device__ __forceinline__ void chunk_origin(const int4* corig, int c, int org[3])
+{
+    const int4 o = corig[c];
+    org[0] = o.x;
+    org[1] = o.y;
+    org[2] = o.z;
+}
+
+template <typename real, int D>
+__device__ __forceinline__ int64_t node_index(const int base[D], const int a[D], int n)
+{
+    return (int64_t)(base[0] + a[0]) + (int64_t)n * ((base[1] + a[1]) + (D == 3 ? (int64_t)n * (base[D - 1] + a[D - 1]) : 0));
+}
+
+template <typename real, int D>
+__device__ __forceinline__ void load_vec(const real* g, real v[D])
+{
+#pragma unroll
+    for (int k = 0; k < D; ++k) v[k] = g[k];
+}
+
+// block sum of up to 8 doubles; thread 0 of the block gets the totals
+template <int NV>
+__device__ __forceinline__ void block_sum(double v[NV])
+{
+    __shared__ double s_red[kWaves][NV > 0 ? NV : 1];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < NV; ++c) v[c] = wave_sum(v[c]);
+    if ((t & 63) == 0)
+#pragma unroll
+        for (int c = 0; c < NV; ++c) s_red[t >> 6][c] = v[c];
+    __syncthreads();
+    if (t == 0)
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+            double s = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) s += s_red[w][c];
+            v[c] = s;
+        }
+}
+
+// --------------------------------------------------------------------------
+// particle loads
+// --------------------------------------------------------------------------
+
+template <typename real, int D>
+struct Particle {
+    real x[D], v[D], C[D][D], F[D][D];
+};
+
+// position x = x0s + u and deformation gradient of slot i
+template <typename real, int D>
+__device__ __forceinline__ void load_xF(const real* st, const real* x0s, int64_t S, int64_t i, real x[D],
+                                        real F[D][D])
+{
+    using Cp = Comp<D>;
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[k] = x0s[k * S + i] + st[(Cp::X + k) * S + i];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) F[a][b] = st[(Cp::F + a * D + b) * S + i];
+}
+
+// full state of slot i with q.x the position x0s + u
+template <typename real, int D>
+__device__ __forceinline__ void load_particle(const real* st, const real* x0s, int64_t S, int64_t i,
+                                              Particle<real, D>& q)
+{
+    using Cp = Comp<D>;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        q.x[k] = x0s[k * S + i] + st[(Cp::X + k) * S + i];
+        q.v[k] = st[(Cp::V + k) * S + i];
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            q.C[a][b] = st[(Cp::C + a * D + b) * S + i];
+            q.F[a][b] = st[(Cp::F + a * D + b) * S + i];
+        }
+}
+
+// stores q with q.x holding the displacement u
+template <typename real, int D>
+__device__ __forceinline__ void store_particle(real* st, int64_t S, int64_t i, const Particle<real, D>& q)
+{
+    using Cp = Comp<D>;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        st[(Cp::X + k) * S + i] = q.x[k];
+        st[(Cp::V + k) * S + i] = q.v[k];
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            st[(Cp::C + a * D + b) * S + i] = q.C[a][b];
+            st[(Cp::F + a * D + b) * S + i] = q.F[a][b];
+        }
+}
+
+// --------------------------------------------------------------------------
+// per-particle stress and affine momentum matrix (Eqs. 7, 15, 31-33)
+// --------------------------------------------------------------------------
+
+template <typename real, int D>
+struct P2GTerms {
+    real m;            // particle mass phi rho V
+    real se, sm;       // SIMP scalings
+    real dse, dsm;     // their derivatives w.r.t. phi
+    real Pe[D][D];     // elastic stress
+    real P[D][D];      // total stress
+    real A[D][D];      // m C - (4 dt / dx^2) V P F^T
+    StressCtx<real, D> ctx;
+};
+
+template <typename real, int D>
+__device__ __forceinline__ void p2g_terms(const InstDev<real>& I, const Particle<real, D>& q, real phi,
+                                          const real br[D], const real B[D], P2GTerms<real, D>& T)
+{
+    real pq, dpq;
+    simp_pow(phi, I.simp_q, pq, dpq);
+    T.se = I.simp_eps + (real(1) - I.simp_eps) * pq;
+    T.sm = pq;
+    T.dse = (real(1) - I.simp_eps) * dpq;
+    T.dsm = dpq;
+    T.m = phi * I.mass_p;
+    elastic_stress<real, D>(q.F, I.G, I.K, T.Pe, T.ctx);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) T.P[i][j] = T.se * T.Pe[i][j] - T.sm * I.inv_mu0 * B[i] * br[j];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            real s = 0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) s += T.P[i][k] * q.F[j][k];
+            T.A[i][j] = T.m * q.C[i][j] - I.kappa_vol * s;
+        }
+}
+
+template <typename real, int D>
+__device__ __forceinline__ void field_at(const InstDev<real>& I, const real* bprog, int step, real B[D])
+{
+    int seg = segment_of(step, I.seg_steps, I.n_seg, I.periodic);
+#pragma unroll
+    for (int k = 0; k < D; ++k) B[k] = bprog[(int64_t)(I.seg_off + seg) * D + k];
+}
+
+// weight and dpos of one stencil node
+template <typename real, int D>
+__device__ __forceinline__ real node_weight(const Stencil<real, D>& S, const int a[D], real dx, real dpos[D])
+{
+    real w = real(1);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        w *= sel3(S.w[k], a[k]);
+        dpos[k] = (real(a[k]) - S.f[k]) * dx;
+    }
+    return w;
+}
+
+template <typename real, int D>
+__device__ __forceinline__ void node_grad(const Stencil<real, D>& S, const int a[D], real gw[D])
+{
+    real wk[D], dk[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        wk[k] = sel3(S.w[k], a[k]);
+        dk[k] = sel3(S.dw[k], a[k]);
+    }
+    if (D == 2) {
+        gw[0] = dk[0] * wk[1];
+        gw[1] = wk[0] * dk[1];
+    } else {
+        gw[0] = dk[0] * wk[1] * wk[D - 1];
+        gw[1] = wk[0] * dk[1] * wk[D - 1];
+        gw[D - 1] = wk[0] * wk[1] * dk[D - 1];
+    }
+}
+
+// --------------------------------------------------------------------------
+// P2G (Eqs. 14-15)
+// --------------------------------------------------------------------------
+
+template <typename real, int D>
+__global__ __launch_bounds__(kBlock) void k_p2g(Args<real> a, const real* __restrict__ st, int step)
+{
+    __shared__ double lds[4 * kBoxCap];
+    const ChunkDev ch = a.chunks[blockIdx.x];
+    const InstDev<real>& I = a.inst[ch.inst];
+    const int t = threadIdx.x;
+    const bool active = t < ch.count;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+    const int64_t S = a.nalloc;
+    Particle<real, D> q;
+    real phi = 0, br[D];
+    if (active) {
+        load_particle<real, D>(st, a.x0s, S, i, q);
+        phi = a.phi[i];
+#pragma unroll
+        for (int k = 0; k < D; ++k) br[k] = a.br[k * S + i];
+    } else {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            q.x[k] = real(0.5);
+            q.v[k] = real(0);
+            br[k] = real(0);
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                q.C[k][b] = real(0);
+                q.F[k][b] = k == b ? real(1) : real(0);
+            }
+        }
+    }
+    real B[D];
+    field_at<real, D>(I, a.bprog, step, B);
+    int org[3];
+    chunk_origin(a.corig, blockIdx.x, org);
+    Stencil<real, D> Sx;
+    int err = make_stencil<real, D>(q.x, org, I.inv_dx, I.n_grid, Sx);
+    if (active && err) atomicOr(a.err, err);
+    P2GTerms<real, D> T;
+    p2g_terms<real, D>(I, q, phi, br, B, T);
+    real mv[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) mv[k] = T.m * q.v[k];
+    const real dx = I.dx;
+    scatter_box<real, D, D + 1>(a, I, lds, active, Sx.base, a.gm, 0,
+        [&](const int o[D], real out[D + 1]) {
+            real dpos[D];
+            real w = node_weight<real, D>(Sx, o, dx, dpos);
+#pragma unroll
+            for (int r = 0; r < D; ++r) {
+                real s = mv[r];
+#pragma unroll
+                for (int c = 0; c < D; ++c) s += T.A[r][c] * dpos[c];
+                out[r] = w * s;
+            }
+            out[D] = w * T.m;
+        });
+}
+
+// --------------------------------------------------------------------------
+// grid operation (Eqs. 16-18 plus walls and clamp)
+// --------------------------------------------------------------------------
+
+template <typename real, int D>
+__device__ __forceinline__ void node_ijk(const InstDev<real>& I, int local, int ijk[D])
+{
+    int n = I.n_grid;
+    ijk[0] = local % n;
+    if (D == 2) {
+        ijk[1] = local / n;
+    } else {
+        ijk[1] = (local / n) % n;
+        ijk[D - 1] = local / (n * n);
+    }
+}
+
+// Velocity of one node with mass m > 0 and momentum p. Returns the floor branch
+// (0 untouched, 1 zeroed, 2 sliding) and the intermediates the transpose needs:
+// vh = p/m, u0 after damping and gravity, u1 after the floor, v final.
+template <typename real, int D>
+__device__ __forceinline__ int node_velocity(const InstDev<real>& I, const int ijk[D], real m, const real p[D],
+                                             real vh[D], real u0[D], real u1[D], real v[D], int wallz[D],
+                                             bool& clamped)
+{
+    const real rm = real(1) / m;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        vh[k] = p[k] * rm;
+        u0[k] = I.damp * vh[k] + I.gdt[k];
+        u1[k] = u0[k];
+    }
+    int branch = 0;
+    if (I.floor_on && ijk[1] <= I.floor_jmax) {
+        real vn = u0[1];
+        if (vn < real(0)) {
+            real t2 = 0;
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                if (k != 1) t2 += u0[k] * u0[k];
+            real tn = sqrt(t2);
+            real s = tn + I.floor_mu * vn;
+            if (I.floor_noslip || tn == real(0) || s <= real(0)) {
+                branch = 1;
+#pragma unroll
+                for (int k = 0; k < D; ++k) u1[k] = real(0);
+            } else {
+                branch = 2;
+                real f = s / tn;
+#pragma unroll
+                for (int k = 0; k < D; ++k) u1[k] = (k == 1) ? real(0) : f * u0[k];
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        v[k] = u1[k];
+        wallz[k] = 0;
+        if (ijk[k] < I.wall_cells && v[k] < real(0)) wallz[k] = 1;
+        if (ijk[k] >= I.n_grid - I.wall_cells && v[k] > real(0)) wallz[k] = 1;
+        if (wallz[k]) v[k] = real(0);
+    }
+    clamped = I.clamp_on && ijk[0] <= I.clamp_imax;
+    if (clamped)
+#pragma unroll
+        for (int k = 0; k < D; ++k) v[k] = real(0);
+    return branch;
+}
+
+// One block per coarse block: gathers the staged P2G boxes, applies Eqs. 16-18
+// and writes the node velocity. keep = 1 (reverse sweep) also stores the summed
+// (momentum, mass) for the grid transpose and clears the adjoint accumulator.
+template <typename real, int D>
+__global__ __launch_bounds__(kGridBlock) void k_grid(Args<real> a, int keep)
+{
+  const int n_act = a.active[0];
+  for (int ai = blockIdx.x; ai < n_act; ai += gridDim.x) {
+    const int b = a.active_list[ai];
+    const InstDev<real>& I = a.inst[a.cb_inst[b]];
+    gather_coarse<real, D>(a, I, b, a.gm, [&](int local, int64_t g, const int g3[3], const real node[4]) {
+        real v[D];
+        if (node[3] > real(0)) {
+            int ijk[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) ijk[k] = g3[k];
+            real vh[D], u0[D], u1[D];
+            int wz[D];
+            bool cl;
+            node_velocity<real, D>(I, ijk, node[3], node, vh, u0, u1, v, wz, cl);
+        } else {
+#pragma unroll
+            for (int k = 0; k < D; ++k) v[k] = real(0);
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) a.gv[4 * g + k] = v[k];
+        if (keep) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a.gmd[4 * g + q] = node[q];
+                a.gbar[4 * g + q] = real(0);
+            }
+        }
+    });
+  }
+}
+
+// --------------------------------------------------------------------------
+// G2P (Eqs. 19-22)
+// --------------------------------------------------------------------------
+
+template <typename real, int D>
+__global__ __launch_bounds__(kBlock) void k_g2p(Args<real> a, const real* sin, real* sout, int step, int traj_on)
+{
+    const ChunkDev ch = a.chunks[blockIdx.x];
+    const InstDev<real>& I = a.inst[ch.inst];
+    const int t = threadIdx.x;
+    const bool active = t < ch.count;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+    const int64_t S = a.nalloc;
+    if (blockIdx.x == 0 && t == 0) a.active[0] = 0;   // the grid update has consumed the P2G list
+    double traj = 0.0;
+    if (active) {
+        real x[D], F[D][D], u[D];
+        load_xF<real, D>(sin, a.x0s, S, i, x, F);
+#pragma unroll
+        for (int k = 0; k < D; ++k) u[k] = sin[(Comp<D>::X + k) * S + i];
+        int org[3];
+        chunk_origin(a.corig, blockIdx.x, org);
+        Stencil<real, D> Sx;
+        make_stencil<real, D>(x, org, I.inv_dx, I.n_grid, Sx);
+        const real* gv = a.gv + 4 * (int64_t)I.grid_off;
+        real vn[D], Bm[D][D];
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            vn[r] = 0;
+#pragma unroll
+            for (int c = 0; c < D; ++c) Bm[r][c] = 0;
+        }
+        for (int o = 0; o < Comp<D>::S3; ++o) {
+            int oa[D];
+            offset_split<D>(o, oa);
+            real dpos[D];
+            real w = node_weight<real, D>(Sx, oa, I.dx, dpos);
+            real vi[D];
+            load_vec<real, D>(gv + 4 * node_index<real, D>(Sx.base, oa, I.n_grid), vi);
+#pragma unroll
+            for (int r = 0; r < D; ++r) {
+                real wv = w * vi[r];
+                vn[r] += wv;
+#pragma unroll
+                for (int c = 0; c < D; ++c) Bm[r][c] += wv * dpos[c];
+            }
+        }
+        Particle<real, D> q;
+        real IdC[D][D];
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            q.v[r] = vn[r];
+            q.x[r] = u[r] + I.dt * vn[r];
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                q.C[r][c] = I.lam * Bm[r][c];
+                IdC[r][c] = (r == c ? real(1) : real(0)) + I.dt * q.C[r][c];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                real s = 0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) s += IdC[r][k] * F[k][c];
+                q.F[r][c] = s;
+            }
+        int err = 0;
+        bool fin = true;
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            fin = fin && rfinite(q.x[r]) && rfinite(q.v[r]);
+#pragma unroll
+            for (int c = 0; c < D; ++c) fin = fin && rfinite(q.F[r][c]) && rfinite(q.C[r][c]);
+        }
+        if (!fin) err |= kErrNonFinite;
+        else {
+            if (!(det<real, D>(q.F) > real(0))) err |= kErrInvert;
+            real x1[D];
+#pragma unroll
+            for (int r = 0; r < D; ++r) x1[r] = a.x0s[r * S + i] + q.x[r];
+            Stencil<real, D> S1;
+            err |= make_stencil<real, D>(x1, org, I.inv_dx, I.n_grid, S1);
+        }
+        if (err) atomicOr(a.err, err);
+        store_particle<real, D>(sout, S, i, q);
+        if (traj_on && I.loss_kind == kTrajVel) {
+            real ve = 0;
+#pragma unroll
+            for (int r = 0; r < D; ++r) ve += I.loss_dir[r] * q.v[r];
+            traj = (double)(a.phi[i] * I.mass_p) * (double)ve;
+        }
+    }
+    if (traj_on && I.loss_kind == kTrajVel) {
+        double v1[1] = {traj};
+        block_sum<1>(v1);
+        if (t == 0) unsafeAtomicAdd(&a.acc[ch.inst * kAccCount + kAccTraj], v1[0]);
+    }
+}
+
+// --------------------------------------------------------------------------
+// losses (Eqs. 36-40)
+// --------------------------------------------------------------------------
+
+// sums per instance: total mass, sum m e.(x - x0), masked squared distance,
+// mask count, masked e.(x - x0)
+template <typename real, int D>
+__global__ __launch_bounds__(kBlock) void k_loss_sums(Args<real> a, const real* st, const real* x0s,
+                                                      const real* target, const uint8_t* mask, int has_target)
+{
+    const ChunkDev ch = a.chunks[blockIdx.x];
+    const InstDev<real>& I = a.inst[ch.inst];
+    const int t = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+    const int64_t S = a.nalloc;
+    double v[5] = {0, 0, 0, 0, 0};
+    if (t < ch.count) {
+        double m = (double)a.phi[i] * (double)I.mass_p;
+        int mk = mask ? mask[i] : 1;
+        double de = 0, sq = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            double uk = st[(Comp<D>::X + k) * S + i];
+            de += (double)I.loss_dir[k] * uk;
+            if (has_target) {
+                double r = uk - (double)target[k * S + i];
+                sq += r * r;
+            }
+        }
+        v[0] = m;
+        v[1] = m * de;
+        v[2] = mk ? sq : 0.0;
+        v[3] = mk ? 1.0 : 0.0;
+        v[4] = mk ? de : 0.0;
+    }
+    block_sum<5>(v);
+    if (t == 0) {
+        double* acc = a.acc + ch.inst * kAccCount;
+        unsafeAtomicAdd(&acc[kAccMass], v[0]);
+        unsafeAtomicAdd(&acc[kAccS1], v[1]);
+        unsafeAtomicAdd(&acc[kAccSq], v[2]);
+        unsafeAtomicAdd(&acc[kAccCnt], v[3]);
+        unsafeAtomicAdd(&acc[kAccTip], v[4]);
+    }
+}
+
+template <typename real>
+__global__ void k_loss_finalize(Args<real> a, int n_inst, real* loss_out)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_inst) return;
+    const InstDev<real>& I = a.inst[k];
+    const double* acc = a.acc + k * kAccCount;
+    double L = 0;
+    switch (I.loss_kind) {
+    case kFinalMse: L = acc[kAccCnt] > 0 ? acc[kAccSq] / acc[kAccCnt] : 0.0; break;
+    case kComDisp: L = -acc[kAccS1] / acc[kAccMass]; break;
+    case kTrajVel: L = -(double)I.dt * acc[kAccTraj] / acc[kAccMass]; break;
+    default: L = acc[kAccCnt] > 0 ? -acc[kAccTip] / acc[kAccCnt] : 0.0; break;
+    }
+    a.loss_val[k] = L;
+    if (loss_out) loss_out[k] = (real)L;
+}
+
+// --------------------------------------------------------------------------
+// adjoint seeds at the final state and direct density terms
+// --------------------------------------------------------------------------
+
+template <typename real, int D>
+__global__ __launch_bounds__(kBlock) void k_seed(Args<real> a, const real* st, real* adj, const real* x0s,
+                                                 const real* target, const uint8_t* mask, const real* dloss)
+{
+    using Cp = Comp<D>;
+    const ChunkDev ch = a.chunks[blockIdx.x];
+    const InstDev<real>& I = a.inst[ch.inst];
+    const int t = threadIdx.x;
+    if (t >= ch.count) return;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+    const int64_t S = a.nalloc;
+    const double* acc = a.acc + ch.inst * kAccCount;
+    const double dl = (double)dloss[ch.inst];
+    const double M = acc[kAccMass];
+    const double L = a.loss_val[ch.inst];
+    const double m = (double)a.phi[i] * (double)I.mass_p;
+    const int mk = mask ? mask[i] : 1;
+    double gphi = 0, de = 0;
+    real xb[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        double uk = st[(Cp::X + k) * S + i];
+        double e = I.loss_dir[k];
+        de += e * uk;
+        double s = 0;
+        switch (I.loss_kind) {
+        case kFinalMse: s = mk ? dl * 2.0 * (uk - (double)target[k * S + i]) / acc[kAccCnt] : 0.0; break;
+        case kTipDisp: s = mk ? -dl * e / acc[kAccCnt] : 0.0; break;
+        case kComDisp: s = -dl * m * e / M; break;
+        default: s = 0.0; break;
+        }
+        xb[k] = (real)s;
+    }
+    if (I.loss_kind == kComDisp || I.loss_kind == kTrajVel)
+        gphi = dl * (double)I.mass_p * (-de / M - L / M);
+#pragma unroll
+    for (int c = 0; c < Cp::NC; ++c) adj[c * S + i] = real(0);
+#pragma unroll
+    for (int k = 0; k < D; ++k) adj[(Cp::X + k) * S + i] = xb[k];
+    a.gphi[i] = (real)gphi;
+#pragma unroll
+    for (int k = 0; k < D; ++k) a.gbr[k * S + i] = real(0);
+}
+
+// --------------------------------------------------------------------------
+// G2P transpose: adjoint of state n+1 -> grid velocity adjoint (scatter) and
+// the G2P share of the adjoint of state n
+// --------------------------------------------------------------------------
+
+template <typename real, int D>
+__global__ __launch_bounds__(kBlock) void k_g2p_adj(Args<real> a, const real* st, real* adj, const real* dloss)
+{
+    using Cp = Comp<D>;
+    __shared__ double lds[4 * kBoxCap];
+    const ChunkDev ch = a.chunks[blockIdx.x];
+    const InstDev<real>& I = a.inst[ch.inst];
+    const int t = threadIdx.x;
+    const bool active = t < ch.count;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+    const int64_t S = a.nalloc;
+    if (blockIdx.x == 0 && t == 0) a.active[0] = 0;   // the grid update has consumed the P2G list
+    real x[D], F[D][D], xb1[D], vb1[D], Cb1[D][D], Fb1[D][D];
+    if (active) {
+        load_xF<real, D>(st, a.x0s, S, i, x, F);
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            xb1[k] = adj[(Cp::X + k) * S + i];
+            vb1[k] = adj[(Cp::V + k) * S + i];
+        }
+#pragma unroll
+        for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                Cb1[r][c] = adj[(Cp::C + r * D + c) * S + i];
+                Fb1[r][c] = adj[(Cp::F + r * D + c) * S + i];
+            }
+        if (I.loss_kind == kTrajVel) {
+            const double M = a.acc[ch.inst * kAccCount + kAccMass];
+            const double sc = -(double)dloss[ch.inst] * (double)I.dt * (double)a.phi[i] * (double)I.mass_p / M;
+#pragma unroll
+            for (int k = 0; k < D; ++k) vb1[k] += (real)(sc * (double)I.loss_dir[k]);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            x[k] = real(0.5);
+            xb1[k] = vb1[k] = real(0);
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                F[k][c] = k == c ? real(1) : real(0);
+                Cb1[k][c] = Fb1[k][c] = real(0);
+            }
+        }
+    }
+    int org[3];
+    chunk_origin(a.corig, blockIdx.x, org);
+    Stencil<real, D> Sx;
+    make_stencil<real, D>(x, org, I.inv_dx, I.n_grid, Sx);
+    const real* gv = a.gv + 4 * (int64_t)I.grid_off;
+    // recompute C' of the forward G2P
+    real Bm[D][D];
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+        for (int c = 0; c < D; ++c) Bm[r][c] = 0;
+    if (active) {
+        for (int o = 0; o < Cp::S3; ++o) {
+            int oa[D];
+            offset_split<D>(o, oa);
+            real dpos[D];
+            real w = node_weight<real, D>(Sx, oa, I.dx, dpos);
+            real vi[D];
+            load_vec<real, D>(gv + 4 * node_index<real, D>(Sx.base, oa, I.n_grid), vi);
+#pragma unroll
+            for (int r = 0; r < D; ++r)
+#pragma unroll
+                for (int c = 0; c < D; ++c) Bm[r][c] += w * vi[r] * dpos[c];
+        }
+    }
+    // F' = (I + dt C') F  ->  Fb = (I + dt C')^T Fb',  Cbt = Cb' + dt Fb' F^T
+    real Fb[D][D], Cbt[D][D], vbt[D], xb[D];
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            real s = Fb1[r][c];
+            real u = Cb1[r][c];
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                s += I.dt * I.lam * Bm[k][r] * Fb1[k][c];
+                u += I.dt * Fb1[r][k] * F[c][k];
+            }
+            Fb[r][c] = s;
+            Cbt[r][c] = u;
+        }
+    // x' = x + dt v'
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        vbt[k] = vb1[k] + I.dt * xb1[k];
+        xb[k] = xb1[k];
+    }
+    const real lam = I.lam, dx = I.dx;
+    scatter_box<real, D, D>(a, I, lds, active, Sx.base, a.gbar, 1,
+        [&](const int o[D], real out[D]) {
+            real dpos[D], gw[D];
+            real w = node_weight<real, D>(Sx, o, dx, dpos);
+            node_grad<real, D>(Sx, o, gw);
+            real vi[D];
+            load_vec<real, D>(gv + 4 * node_index<real, D>(Sx.base, o, I.n_grid), vi);
+            real vu = 0;
+#pragma unroll
+            for (int r = 0; r < D; ++r) {
+                real s = 0;
+#pragma unroll
+                for (int c = 0; c < D; ++c) s += Cbt[r][c] * dpos[c];
+                real u = vbt[r] + lam * s;
+                out[r] = w * u;
+                vu += vi[r] * u;
+            }
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                real ctv = 0;
+#pragma unroll
+                for (int r = 0; r < D; ++r) ctv += Cbt[r][k] * vi[r];
+                xb[k] += vu * gw[k] - lam * w * ctv;
+            }
+        });
+    if (active) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) adj[(Cp::X + k) * S + i] = xb[k];
+#pragma unroll
+        for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int c = 0; c < D; ++c) adj[(Cp::F + r * D + c) * S + i] = Fb[r][c];
+    }
+}
+
+// --------------------------------------------------------------------------
+// grid transpose: vbar -> (pbar, mbar), in place in gbar; clears gm
+// --------------------------------------------------------------------------
+
+template <typename real, int D>
+__global__ __launch_bounds__(kGridBlock) void k_grid_adj(Args<real> a)
+{
+  const int n_act = a.active[1];
+  for (int ai = blockIdx.x; ai < n_act; ai += gridDim.x) {
+    const int b = a.active_list[a.n_coarse + ai];
+    const InstDev<real>& I = a.inst[a.cb_inst[b]];
+    gather_coarse<real, D>(a, I, b, a.gbar, [&](int local, int64_t g, const int g3[3], const real vb[4]) {
+        real node[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) node[q] = a.gmd[4 * g + q];
+        real out[4] = {0, 0, 0, 0};
+        if (node[3] > real(0)) {
+            int ijk[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) ijk[k] = g3[k];
+            real vh[D], u0[D], u1[D], v[D], gb[D];
+            int wz[D];
+            bool cl;
+            int br = node_velocity<real, D>(I, ijk, node[3], node, vh, u0, u1, v, wz, cl);
+#pragma unroll
+            for (int k = 0; k < D; ++k) gb[k] = cl ? real(0) : vb[k];
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                if (wz[k]) gb[k] = real(0);
+            if (br == 1) {
+#pragma unroll
+                for (int k = 0; k < D; ++k) gb[k] = real(0);
+            } else if (br == 2) {
+                // transpose of v_t (1 + mu vn / |v_t|), n = e_y, at u0
+                real vn = u0[1];
+                real t2 = 0, vtg = 0;
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    if (k != 1) {
+                        t2 += u0[k] * u0[k];
+                        vtg += u0[k] * gb[k];
+                    }
+                real tn = sqrt(t2);
+                real mu_t = I.floor_mu / tn;
+                real o[D];
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    real ptg = (k == 1) ? real(0) : gb[k];
+                    real vt = (k == 1) ? real(0) : u0[k];
+                    o[k] = ptg + mu_t * ((k == 1 ? vtg : real(0)) + vn * ptg - vn * vt * vtg / t2);
+                }
+#pragma unroll
+                for (int k = 0; k < D; ++k) gb[k] = o[k];
+            }
+            const real rm = real(1) / node[3];
+            real mb = 0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                real vhb = I.damp * gb[k];
+                out[k] = vhb * rm;
+                mb -= vhb * vh[k];
+            }
+            out[3] = mb * rm;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a.gbar[4 * g + q] = out[q];
+    });
+  }
+}
+
+// --------------------------------------------------------------------------
+// P2G transpose: gather (pbar, mbar) -> adjoint of state n and design
+// --------------------------------------------------------------------------
+
+template <typename real, int D>
+__global__ __launch_bounds__(kBlock) void k_p2g_adj(Args<real> a, const real* st, real* adj, int step)
+{
+    using Cp = Comp<D>;
+    const ChunkDev ch = a.chunks[blockIdx.x];
+    const InstDev<real>& I = a.inst[ch.inst];
+    const int t = threadIdx.x;
+    const bool active = t < ch.count;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+    const int64_t S = a.nalloc;
+    if (blockIdx.x == 0 && t == 0) a.active[1] = 0;   // the grid transpose has consumed the G2P-transpose list
+    real B[D];
+    field_at<real, D>(I, a.bprog, step, B);
+    double gBl[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) gBl[k] = 0.0;
+    if (active) {
+        Particle<real, D> q;
+        load_particle<real, D>(st, a.x0s, S, i, q);
+        const real phi = a.phi[i];
+        real br[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) br[k] = a.br[k * S + i];
+        int org[3];
+        chunk_origin(a.corig, blockIdx.x, org);
+        Stencil<real, D> Sx;
+        make_stencil<real, D>(q.x, org, I.inv_dx, I.n_grid, Sx);
+        P2GTerms<real, D> T;
+        p2g_terms<real, D>(I, q, phi, br, B, T);
+        const real* gb = a.gbar + 4 * (int64_t)I.grid_off;
+        real mb = 0, vb[D], Ab[D][D], xb[D];
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            vb[r] = 0;
+            xb[r] = 0;
+#pragma unroll
+            for (int c = 0; c < D; ++c) Ab[r][c] = 0;
+        }
+        for (int o = 0; o < Cp::S3; ++o) {
+            int oa[D];
+            offset_split<D>(o, oa);
+            real dpos[D], gw[D];
+            real w = node_weight<real, D>(Sx, oa, I.dx, dpos);
+            node_grad<real, D>(Sx, oa, gw);
+            const real* nd = gb + 4 * node_index<real, D>(Sx.base, oa, I.n_grid);
+            real pb[D];
+            load_vec<real, D>(nd, pb);
+            real mbi = nd[3];
+            real pv = 0, pmom = 0;
+            real Atp[D];
+#pragma unroll
+            for (int r = 0; r < D; ++r) {
+                real ad = 0;
+                Atp[r] = 0;
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    ad += T.A[r][c] * dpos[c];
+                    Atp[r] += T.A[c][r] * pb[c];
+                }
+                pv += pb[r] * q.v[r];
+                pmom += pb[r] * (T.m * q.v[r] + ad);
+            }
+            mb += w * (mbi + pv);
+            real coef = mbi * T.m + pmom;
+#pragma unroll
+            for (int r = 0; r < D; ++r) {
+                vb[r] += w * T.m * pb[r];
+                xb[r] += coef * gw[r] - w * Atp[r];
+#pragma unroll
+                for (int c = 0; c < D; ++c) Ab[r][c] += w * pb[r] * dpos[c];
+            }
+        }
+        mb += ddot<real, D>(Ab, q.C);
+        // A = m C - kappa V P F^T
+        real Pb[D][D], Fbp[D][D], dP[D][D];
+#pragma unroll
+        for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                real s = 0, u = 0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    s += Ab[r][k] * q.F[k][c];
+                    u += Ab[k][r] * T.P[k][c];
+                }
+                Pb[r][c] = -I.kappa_vol * s;
+                Fbp[r][c] = -I.kappa_vol * u;
+            }
+        elastic_stress_dir<real, D>(q.F, I.K, T.ctx, Pb, dP);
+        // P = s_e P_e + s_m P_m, P_m = -(1/mu0) B (x) br ; m = phi rho V
+        real PbPe = ddot<real, D>(Pb, T.Pe);
+        real PbBBr = 0;
+        real PtB[D], PBr[D];
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            PtB[r] = 0;
+            PBr[r] = 0;
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                PtB[r] += Pb[c][r] * B[c];
+                PBr[r] += Pb[r][c] * br[c];
+                PbBBr += Pb[r][c] * B[r] * br[c];
+            }
+        }
+        real gphi = I.mass_p * mb + T.dse * PbPe - T.dsm * I.inv_mu0 * PbBBr;
+        a.gphi[i] += gphi;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            a.gbr[k * S + i] += -T.sm * I.inv_mu0 * PtB[k];
+            gBl[k] = (double)(-T.sm * I.inv_mu0 * PBr[k]);
+        }
+        // adjoint of state n: x and F add to the G2P share, v and C are set
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            adj[(Cp::X + k) * S + i] += xb[k];
+            adj[(Cp::V + k) * S + i] = vb[k];
+        }
+#pragma unroll
+        for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                adj[(Cp::C + r * D + c) * S + i] = T.m * Ab[r][c];
+                adj[(Cp::F + r * D + c) * S + i] += Fbp[r][c] + T.se * dP[r][c];
+            }
+    }
+    block_sum<D>(gBl);
+    if (t == 0) {
+        int seg = segment_of(step, I.seg_steps, I.n_seg, I.periodic);
+#pragma unroll
+        for (int k = 0; k < D; ++k) unsafeAtomicAdd(&a.gB[(int64_t)(I.seg_off + seg) * D + k], gBl[k]);
+    }
+}
+
+// --------------------------------------------------------------------------
+// input gather (caller order -> sorted slots) and output scatter
+// --------------------------------------------------------------------------
+
+template <typename real, int D>
+__global__ __launch_bounds__(kBlock) void k_gather(Args<real> a, const int* __restrict__ sorted_ids,
+                                                   const int64_t* __restrict__ caller_start, real* st, real* x0s,
+                                                   real* phi, real* br, real* tgt, uint8_t* mask, int* id,
+                                                   int4* corig, const real* x0_in, const real* phi_in,
+                                                   const real* br_in, const real* tgt_in, const uint8_t* mask_in)
+{
+    using Cp = Comp<D>;
+    __shared__ int s_min[kWaves][3];
+    const ChunkDev ch = a.chunks[blockIdx.x];
+    const InstDev<real>& I = a.inst[ch.inst];
+    const int t = threadIdx.x;
+    const bool active = t < ch.count;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+    const int64_t S = a.nalloc;
+    const int64_t local = (int64_t)(blockIdx.x - I.chunk_off) * kBlock + t;
+    const int q = active ? sorted_ids[caller_start[ch.inst] + local] : 0;
+    // origin cell of the chunk: lowest cell index over its particles per axis
+    double xa[D];
+    int cmin[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        xa[k] = active ? (double)x0_in[(int64_t)q * D + k] : 0.0;
+        double c = floor(xa[k] * (double)I.n_grid);
+        int ci = (active && c > -1e9 && c < 1e9) ? (int)c : 0x3fffffff;
+        cmin[k] = wave_min(ci);
+    }
+    if ((t & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < D; ++k) s_min[t >> 6][k] = cmin[k];
+    __syncthreads();
+    int org[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        int m = s_min[0][k];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) m = min(m, s_min[w][k]);
+        org[k] = (m == 0x3fffffff) ? 0 : m;
+    }
+    if (t == 0) corig[blockIdx.x] = make_int4(org[0], org[1], org[2], 0);
+    if (!active) return;
+    id[i] = q;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const double o = (double)org[k] / (double)I.n_grid;
+        st[(Cp::X + k) * S + i] = real(0);
+        st[(Cp::V + k) * S + i] = real(0);
+        x0s[k * S + i] = (real)(xa[k] - o);
+        br[k * S + i] = br_in[(int64_t)q * D + k];
+        // FINAL_MSE target as a displacement from the initial position
+        if (tgt_in) tgt[k * S + i] = (real)((double)tgt_in[(int64_t)q * D + k] - xa[k]);
+    }
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            st[(Cp::C + r * D + c) * S + i] = real(0);
+            st[(Cp::F + r * D + c) * S + i] = r == c ? real(1) : real(0);
+        }
+    phi[i] = phi_in[q];
+    mask[i] = mask_in ? mask_in[q] : 1;
+}
+
+template <typename real, int D>
+__global__ __launch_bounds__(kBlock) void k_scatter_out(Args<real> a, const int* __restrict__ id, const real* st,
+                                                        real* x_out, real* g_phi, real* g_br)
+{
+    const ChunkDev ch = a.chunks[blockIdx.x];
+    const int t = threadIdx.x;
+    if (t >= ch.count) return;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+    const int64_t S = a.nalloc;
+    const int64_t q = id[i];
+    const InstDev<real>& I = a.inst[ch.inst];
+    int org[3];
+    chunk_origin(a.corig, blockIdx.x, org);
+    if (x_out)
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+            x_out[q * D + k] = (real)((double)org[k] / (double)I.n_grid + (double)a.x0s[k * S + i] +
+                                      (double)st[(Comp<D>::X + k) * S + i]);
+    if (g_phi) g_phi[q] = a.gphi[i];
+    if (g_br)
+#pragma unroll
+        for (int k = 0; k < D; ++k) g_br[q * D + k] = a.gbr[k * S + i];
+}
+
+template <typename real>
+__global__ void k_convert_out(const double* src, real* dst, int64_t n)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) dst[k] = (real)src[k];
+}
+
+}  // namespace mpm

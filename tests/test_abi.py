@@ -1,0 +1,57 @@
+"""The C-ABI library loads on the host and exports every entry point that
+include/mpm_mag.h declares (no device calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mpm_mag.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mpm_mag_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for need in ("mpm_mag_create", "mpm_mag_rollout", "mpm_mag_backward", "mpm_mag_destroy"):
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2503_22767_amd import mpm_mag as M
+    L = M.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_status_strings_and_kernel_table():
+    from paper_2503_22767_amd import mpm_mag as M
+    L = M.lib()
+    assert L.mpm_mag_strerror(0) == b"ok"
+    assert L.mpm_mag_strerror(7).startswith(b"backward")
+    n = L.mpm_mag_num_kernels()
+    names = [L.mpm_mag_kernel_name(i).decode() for i in range(n)]
+    for k in ("p2g", "grid_update", "g2p", "g2p_adj", "grid_adj", "p2g_adj"):
+        assert k in names
+    assert L.mpm_mag_kernel_name(n) == b""
+
+
+def test_create_rejects_bad_arguments_without_touching_the_device():
+    from paper_2503_22767_amd import mpm_mag as M
+    L = M.lib()
+    h = ctypes.c_void_p()
+    descs = (M.InstanceDesc * 1)()
+    descs[0].dim = 4
+    counts = (ctypes.c_int64 * 1)(10)
+    assert L.mpm_mag_create(descs, 1, counts, 4, ctypes.byref(h)) == M.EINVAL
+    descs[0].dim = 2
+    assert L.mpm_mag_create(descs, 1, counts, 5, ctypes.byref(h)) == M.EINVAL
+    assert L.mpm_mag_create(descs, 0, counts, 4, ctypes.byref(h)) == M.EINVAL
+    assert L.mpm_mag_rollout(None, None, None, None, None, None, None, None, None, None, 0) == M.EINVAL
+    assert L.mpm_mag_backward(None, None, None, None, None, None) == M.EINVAL
+    L.mpm_mag_destroy(None)

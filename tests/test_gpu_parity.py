@@ -1,0 +1,125 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Bars: FP64 device instantiation within 1e-10 (positions, absolute, unit domain)
+and 1e-9 (gradients, norm-wise relative) of the oracle, only summation order
+differing; FP32 within 1e-4 (positions) and 1e-3 (gradients).
+"""
+import numpy as np
+import pytest
+
+from paper_2503_22767_amd import workloads as W
+
+from gpu_util import compare, gpu_run, log, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+TINY = [
+    # dim, loss kind, floor, clamp, n_grid
+    (2, W.LOSS_FINAL_MSE, False, True, 16),
+    (2, W.LOSS_COM_DISP, True, False, 16),
+    (2, W.LOSS_TRAJ_VEL, True, False, 16),
+    (2, W.LOSS_TIP_DISP, False, True, 16),
+    (3, W.LOSS_FINAL_MSE, False, True, 16),
+    (3, W.LOSS_TRAJ_VEL, True, False, 16),
+    (3, W.LOSS_TIP_DISP, True, True, 16),
+]
+
+
+def _tiny(dim, kind, floor, clamp, n_grid, seed=1, steps=24, size=None):
+    size = size or ((0.4, 0.2, 0.2) if dim == 2 else (0.3, 0.2, 0.25))
+    return W.make_tiny(seed=seed, dim=dim, n_steps=steps, loss_kind=kind, floor=floor, clamp=clamp,
+                       gravity=1.0 if floor else 0.0, size=size, n_grid=n_grid, n_segments=4)
+
+
+@pytest.mark.parametrize("case", TINY, ids=[f"d{c[0]}-loss{c[1]}-floor{int(c[2])}-clamp{int(c[3])}" for c in TINY])
+def test_fp64_matches_oracle(case):
+    inst = _tiny(*case)
+    log("case", case, "N", inst.n)
+    ref = oracle_run([inst])
+    got = gpu_run([inst], precision=8)
+    compare(got, ref, pos_tol=1e-10, grad_tol=1e-9, loss_tol=1e-9, label=f"fp64 {case}")
+
+
+@pytest.mark.parametrize("case", TINY, ids=[f"d{c[0]}-loss{c[1]}-floor{int(c[2])}-clamp{int(c[3])}" for c in TINY])
+def test_fp32_matches_oracle(case):
+    inst = _tiny(*case)
+    ref = oracle_run([inst])
+    got = gpu_run([inst], precision=4)
+    compare(got, ref, pos_tol=1e-4, grad_tol=1e-3, label=f"fp32 {case}")
+
+
+def test_c1_full_fp64():
+    """The 2D cantilever workload (64^2 grid, 1,280 particles, 500 steps, FP64)."""
+    wl = W.make_c1()
+    inst = wl.instances[0]
+    ref = oracle_run([inst], ckpt_every=25)
+    got = gpu_run([inst], precision=8)
+    compare(got, ref, pos_tol=1e-10, grad_tol=1e-9, loss_tol=1e-9, label="c1 fp64")
+
+
+def test_c1_full_fp32():
+    wl = W.make_c1()
+    inst = wl.instances[0]
+    ref = oracle_run([inst], ckpt_every=25)
+    got = gpu_run([inst], precision=4)
+    compare(got, ref, pos_tol=1e-4, grad_tol=1e-3, label="c1 fp32")
+
+
+def test_c2_walker_full_size_first_steps():
+    """The 2D walker at full size (256^2 grid, 30,593 particles, floor contact),
+    first 160 steps of its program, FP32."""
+    wl = W.make_c2(n_steps=160)
+    inst = wl.instances[0]
+    ref = oracle_run([inst], ckpt_every=16)
+    got = gpu_run([inst], precision=4, options={"ckpt_every": 16})
+    compare(got, ref, pos_tol=1e-4, grad_tol=1e-3, label="c2[:160] fp32")
+
+
+def test_c3_plate_full_size_first_steps():
+    """The 3D plate at full size (64^3 grid, 16,384 particles), first 40 steps, FP32."""
+    wl = W.make_c3(n_steps=40)
+    inst = wl.instances[0]
+    ref = oracle_run([inst], ckpt_every=8)
+    got = gpu_run([inst], precision=4)
+    compare(got, ref, pos_tol=1e-4, grad_tol=1e-3, label="c3[:40] fp32")
+
+
+def test_c5_quadruped_full_size_first_steps():
+    """The 3D quadruped at full size (128^3 grid, 1,146,344 particles per task):
+    the locomotion task (centre-of-mass loss, floor contact, gravity) and the
+    morphing task (final-shape loss) over their first 2 steps, FP32."""
+    wl = W.make_c5(n_steps=2)
+    insts = [wl.instances[0], wl.instances[2]]
+    ref = oracle_run(insts, ckpt_every=1)
+    got = gpu_run(insts, precision=4)
+    compare(got, ref, pos_tol=1e-4, grad_tol=1e-3, label="c5[:2] tasks 0,2 fp32")
+
+
+def _cloud(dim, seed, n=700, n_grid=32, steps=12):
+    """Particles scattered at random over most of the domain: a chunk's stencils
+    span far more nodes than one staging box, exercising the per-wave boxes and
+    the direct-atomic fallback of the scatter."""
+    rng = np.random.default_rng(seed)
+    inst = W.make_tiny(seed=seed, dim=dim, n_steps=steps, n_grid=n_grid, loss_kind=W.LOSS_FINAL_MSE,
+                       gravity=1.0, floor=False)
+    x0 = rng.uniform(0.15, 0.85, size=(n, dim))
+    p = dict(inst.params)
+    return W.Instance(p, x0, rng.uniform(0.3, 1.0, n), inst.br[:1].repeat(n, 0) * 0 + rng.standard_normal((n, dim)),
+                      inst.b_prog, x0 + rng.uniform(-0.01, 0.01, size=x0.shape), None)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_scatter_fallback_paths_fp64(dim):
+    inst = _cloud(dim, seed=20 + dim)
+    ref = oracle_run([inst])
+    got = gpu_run([inst], precision=8)
+    compare(got, ref, pos_tol=1e-10, grad_tol=1e-9, loss_tol=1e-9, label=f"cloud d{dim} fp64")
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_direct_atomic_scatter_option_fp64(dim):
+    inst = _tiny(dim, W.LOSS_COM_DISP, True, False, 16)
+    ref = oracle_run([inst])
+    got = gpu_run([inst], precision=8, options={"p2g_lds": 0})
+    compare(got, ref, pos_tol=1e-10, grad_tol=1e-9, loss_tol=1e-9, label=f"direct d{dim} fp64")
