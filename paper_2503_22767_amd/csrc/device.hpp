@@ -293,6 +293,15 @@ __device__ __forceinline__ int wave_max(int v)
     return v;
 }
 
+// origin cell of chunk c (particle positions are stored relative to it)
+__device__ __forceinline__ void chunk_origin(const int4* corig, int c, int org[3])
+{
+    const int4 o = corig[c];
+    org[0] = o.x;
+    org[1] = o.y;
+    org[2] = o.z;
+}
+
 // field segment of step n
 __device__ __forceinline__ int segment_of(int n, int L, int S, int periodic)
 {

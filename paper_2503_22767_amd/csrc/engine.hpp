@@ -265,22 +265,31 @@ public:
         for (int c = nck_ - 1; c >= 0; --c) {
             const int s0 = c * K_;
             const int s1 = std::min(T_, s0 + K_);
-            for (int n = s0; n < s1 - 1; ++n) {
-                st = step(s, n, seg_state(c, n - s0), seg_state(c, n - s0 + 1), false);
+            // recompute the segment, keeping every step's grid (sparse: only
+            // the active coarse blocks are written)
+            for (int n = s0; n < s1; ++n) {
+                const int j = n - s0;
+                st = launch(K_P2G, s, n_chunks_, kBlock, k_p2g<real, D>, a, (const real*)seg_state(c, j), n);
                 if (st) return st;
+                st = launch(K_GRID, s, grid_blocks(), kGridBlock, k_grid<real, D>, a, gv_slot(j), gm_slot(j));
+                if (st) return st;
+                if (n + 1 < s1) {
+                    st = launch(K_G2P, s, n_chunks_, kBlock, k_g2p<real, D>, a, (const real*)gv_slot(j),
+                                (const real*)seg_state(c, j), seg_state(c, j + 1), n, 0);
+                    if (st) return st;
+                }
             }
+            // transpose of every step, last first
             for (int n = s1 - 1; n >= s0; --n) {
-                real* sn = seg_state(c, n - s0);
-                st = launch(K_P2G, s, n_chunks_, kBlock, k_p2g<real, D>, a, (const real*)sn, n);
-                if (st) return st;
-                st = launch(K_GRID, s, grid_blocks(), kGridBlock, k_grid<real, D>, a, 1);
-                if (st) return st;
-                st = launch(K_G2P_ADJ, s, n_chunks_, kBlock, k_g2p_adj<real, D>, a, (const real*)sn, adj_,
+                const int j = n - s0;
+                const real* sn = seg_state(c, j);
+                st = launch(K_G2P_ADJ, s, n_chunks_, kBlock, k_g2p_adj<real, D>, a, (const real*)gv_slot(j), sn, adj_,
                             (const real*)dloss);
                 if (st) return st;
-                st = launch(K_GRID_ADJ, s, grid_blocks(), kGridBlock, k_grid_adj<real, D>, a);
+                st = launch(K_GRID_ADJ, s, grid_blocks(), kGridBlock, k_grid_adj<real, D>, a, (const real*)gm_slot(j),
+                            gpm_);
                 if (st) return st;
-                st = launch(K_P2G_ADJ, s, n_chunks_, kBlock, k_p2g_adj<real, D>, a, (const real*)sn, adj_, n);
+                st = launch(K_P2G_ADJ, s, n_chunks_, kBlock, k_p2g_adj<real, D>, a, (const real*)gpm_, sn, adj_, n);
                 if (st) return st;
             }
         }
@@ -306,6 +315,9 @@ private:
     real* ckpt_slot(int c) { return ckpt_ + (size_t)c * state_elems(); }
     // state of step s0 + j inside checkpoint segment c (slot 0 is the checkpoint)
     real* seg_state(int c, int j) { return j == 0 ? ckpt_slot(c) : stash_ + (size_t)(j - 1) * state_elems(); }
+    // grid velocity / (momentum, mass) of step s0 + j of the segment being reversed
+    real* gv_slot(int j) { return gstash_ + (size_t)(2 * j) * 4 * G_; }
+    real* gm_slot(int j) { return gstash_ + (size_t)(2 * j + 1) * 4 * G_; }
 
     int fail(int code, const std::string& msg)
     {
@@ -342,7 +354,7 @@ private:
         a.active = active_;
         a.active_list = active_list_;
         a.n_coarse = (int)n_cb_;
-        a.gmd = gmd_;
+
         a.use_lds = use_lds_ ? 1 : 0;
         return a;
     }
@@ -409,9 +421,10 @@ private:
         Args<real> a = args();
         int st = launch(K_P2G, s, n_chunks_, kBlock, k_p2g<real, D>, a, (const real*)sin, n);
         if (st) return st;
-        st = launch(K_GRID, s, grid_blocks(), kGridBlock, k_grid<real, D>, a, 0);
+        st = launch(K_GRID, s, grid_blocks(), kGridBlock, k_grid<real, D>, a, gv_, (real*)nullptr);
         if (st) return st;
-        return launch(K_G2P, s, n_chunks_, kBlock, k_g2p<real, D>, a, (const real*)sin, sout, n, traj ? 1 : 0);
+        return launch(K_G2P, s, n_chunks_, kBlock, k_g2p<real, D>, a, (const real*)gv_, (const real*)sin, sout, n,
+                      traj ? 1 : 0);
     }
 
     int sort_and_gather(hipStream_t s, const real* x0, const real* phi, const real* br, const real* tgt,
@@ -471,8 +484,12 @@ private:
         if (ckpt_ && K == K_ && nck == nck_) return MPM_MAG_OK;
         if (ckpt_) { (void)hipFree(ckpt_); bytes_ -= ckpt_bytes_; ckpt_ = nullptr; }
         if (stash_) { (void)hipFree(stash_); bytes_ -= stash_bytes_; stash_ = nullptr; }
+        if (gstash_) { (void)hipFree(gstash_); bytes_ -= gstash_bytes_; gstash_ = nullptr; }
         ckpt_bytes_ = state_bytes() * nck;
         stash_bytes_ = state_bytes() * std::max(1, K - 1);
+        gstash_bytes_ = sizeof(real) * (size_t)K * 2 * 4 * G_;
+        if (hipMalloc(&gstash_, gstash_bytes_) != hipSuccess) { gstash_ = nullptr; return fail(MPM_MAG_ENOMEM, "grid stash"); }
+        bytes_ += gstash_bytes_;
         if (hipMalloc(&ckpt_, ckpt_bytes_) != hipSuccess) { ckpt_ = nullptr; return fail(MPM_MAG_ENOMEM, "checkpoint pool"); }
         if (hipMalloc(&stash_, stash_bytes_) != hipSuccess) {
             (void)hipFree(ckpt_); ckpt_ = nullptr;
@@ -519,7 +536,7 @@ private:
         st |= dalloc(&cb_inst_d_, (size_t)n_cb_);
         st |= dalloc(&active_, 2);
         st |= dalloc(&active_list_, (size_t)2 * n_cb_);
-        st |= dalloc(&gmd_, (size_t)4 * G_);
+        st |= dalloc(&gpm_, (size_t)4 * G_);
         st |= dalloc(&gm_, (size_t)4 * G_);
         st |= dalloc(&gv_, (size_t)4 * G_);
         st |= dalloc(&gbar_, (size_t)4 * G_);
@@ -559,7 +576,8 @@ private:
         allocs_.clear();
         if (ckpt_) (void)hipFree(ckpt_);
         if (stash_) (void)hipFree(stash_);
-        ckpt_ = stash_ = nullptr;
+        if (gstash_) (void)hipFree(gstash_);
+        ckpt_ = stash_ = gstash_ = nullptr;
         if (err_h_) (void)hipHostFree(err_h_);
         err_h_ = nullptr;
         for (auto e : events_) (void)hipEventDestroy(e);
@@ -597,7 +615,9 @@ private:
     int* cb_inst_d_ = nullptr;
     int* active_ = nullptr;
     int* active_list_ = nullptr;
-    real* gmd_ = nullptr;
+    real* gpm_ = nullptr;      // (pbar, mbar) of the grid transpose
+    real* gstash_ = nullptr;   // per-step grid of the segment being reversed
+    size_t gstash_bytes_ = 0;
     std::vector<int> cb_inst_h_;
     int64_t n_cb_ = 0;
     double *gB_ = nullptr, *acc_ = nullptr, *loss_val_ = nullptr;

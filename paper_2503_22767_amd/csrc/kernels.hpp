@@ -25,15 +25,35 @@ template <int D> struct Comp {
     static constexpr int S3 = D == 2 ? 9 : 27;
 };
 
-// Staging box capacity (nodes). LDS accumulates in double: on gfx950 the LDS
-// double add is an order of magnitude faster than the single-precision one.
+// Staging box capacity (nodes).
 constexpr int kBoxCap = 1024;
+
+// LDS accumulator of the staged boxes. On gfx950 the single-precision LDS add
+// runs more than an order of magnitude slower than the integer and the
+// double-precision ones, so FP32 contributions are summed as 32-bit fixed point
+// (scaled per block so that 256 contributions of the block's largest magnitude
+// fit in 2^30: rounding comparable to FP32 summation, and order independent),
+// FP64 contributions in double.
+template <typename real> struct LdsAcc;
+template <> struct LdsAcc<float> {
+    using T = int;
+    static constexpr float range = 1073741824.0f / (float)kBlock;   // 2^30 / contributions per node
+    __device__ static T enc(float v, float s) { return __float2int_rn(v * s); }
+    __device__ static float dec(T a, float inv) { return (float)a * inv; }
+};
+template <> struct LdsAcc<double> {
+    using T = double;
+    static constexpr double range = 0.0;
+    __device__ static T enc(double v, double) { return v; }
+    __device__ static double dec(T a, double) { return a; }
+};
 // coarse blocks of the grid used to hand staged boxes to the grid update
 template <int D> struct Coarse {
     static constexpr int edge = D == 2 ? 16 : 8;                    // nodes per axis
     static constexpr int nodes = D == 2 ? 256 : 512;
     static constexpr int cap = 256;                                  // registered boxes per coarse block
 };
+static_assert(Coarse<2>::cap <= kGridBlock && Coarse<3>::cap <= kGridBlock, "grid scan assumes cap <= block");
 
 template <typename real>
 struct Args {
@@ -63,7 +83,6 @@ struct Args {
     int* active;         // [2]: coarse blocks activated in the scatter phases (P2G, G2P transpose)
     int* active_list;    // [2][n_coarse]
     int n_coarse;
-    real* gmd;           // [4 G] summed (momentum, mass) kept for the grid transpose
     int use_lds;
 };
 
@@ -86,8 +105,9 @@ __device__ __forceinline__ int64_t box_offset(int id) { return (int64_t)(id / kW
 // the dense accumulator fb instead.
 template <typename real, int D>
 __device__ __forceinline__ void register_box(const Args<real>& a, const InstDev<real>& I, int id, const int lo[3],
-                                             const int ext[3], const double* box_lds, int box_cap, bool staged,
-                                             real* fb, int phase, int lane0, int stride)
+                                             const int ext[3], const typename LdsAcc<real>::T* box_lds, int box_cap,
+                                             const real inv[4], bool staged, real* fb, int phase, int lane0,
+                                             int stride)
 {
     using CB = Coarse<D>;
     int b0[3] = {0, 0, 0}, nbk[3] = {1, 1, 1};
@@ -120,12 +140,49 @@ __device__ __forceinline__ void register_box(const Args<real>& a, const InstDev<
                                     (int64_t)I.n_grid * ((lo[1] + y) + (D == 3 ? (int64_t)I.n_grid * (lo[D - 1] + z) : 0));
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
-                            real v = (real)box_lds[q * box_cap + l];
+                            real v = LdsAcc<real>::dec(box_lds[q * box_cap + l], inv[q]);
                             if (v != real(0)) atomic_add(&fb[4 * g + q], v);
                         }
                     }
         }
     }
+}
+
+// Lanes of one 16-lane row that share a stencil base form contiguous segments
+// (particles are sorted along a Hilbert curve of their cells). seg_d = lane
+// distance to the start of its segment within the row. seg_row_sum adds, into
+// the last lane of each segment, the values of the whole segment (four DPP
+// shift-right steps, an exact sum for the fixed-point integers).
+__device__ __forceinline__ int dpp_shr(int v, int off)
+{
+    switch (off) {
+    case 1: return __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, true);
+    case 2: return __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, true);
+    case 4: return __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, true);
+    default: return __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, true);
+    }
+}
+
+__device__ __forceinline__ int seg_row_sum(int v, int seg_d)
+{
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+        int y = dpp_shr(v, off);
+        v = seg_d >= off ? v + y : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ double seg_row_sum(double v, int seg_d)
+{
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+        int lo = dpp_shr(__double2loint(v), off);
+        int hi = dpp_shr(__double2hiint(v), off);
+        double y = __hiloint2double(hi, lo);
+        v = seg_d >= off ? v + y : v;
+    }
+    return v;
 }
 
 // Adds NV values per stencil node of every active particle of the block to the
@@ -140,11 +197,15 @@ __device__ __forceinline__ void register_box(const Args<real>& a, const InstDev<
 // accumulator fb, which the grid update also reads. Must be reached by every
 // thread of the block.
 template <typename real, int D, int NV, typename ValFn>
-__device__ __forceinline__ void scatter_box(const Args<real>& a, const InstDev<real>& I, double* lds, bool active,
-                                            const int base[D], real* fb, int phase, ValFn vals)
+__device__ __forceinline__ void scatter_box(const Args<real>& a, const InstDev<real>& I,
+                                            typename LdsAcc<real>::T* lds, bool active, const int base[D],
+                                            const real bound[NV], real* fb, int phase, ValFn vals)
 {
+    using Acc = LdsAcc<real>;
+    using acc_t = typename Acc::T;
     constexpr int S3 = Comp<D>::S3;
     __shared__ int s_bb[kWaves][6];
+    __shared__ float s_bmax[kWaves][4];
     const int t = threadIdx.x;
     const int w = t >> 6;
     const int c = blockIdx.x;
@@ -164,14 +225,42 @@ __device__ __forceinline__ void scatter_box(const Args<real>& a, const InstDev<r
         wext[k] = wave_live ? whi[k] - wlo[k] + 3 : 1;
         wvol *= wext[k];
     }
+    float bmax[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        float v = active ? (float)fabs(bound[q]) : 0.0f;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+        bmax[q] = v;
+    }
     if ((t & 63) == 0) {
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             s_bb[w][k] = wlo[k];
             s_bb[w][3 + k] = whi[k];
         }
+#pragma unroll
+        for (int q = 0; q < NV; ++q) s_bmax[w][q] = bmax[q];
     }
     __syncthreads();
+    // fixed-point scales of the value slots (FP32 build)
+    real scl[4], inv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        scl[q] = real(1);
+        inv[q] = real(1);
+    }
+    if (Acc::range > 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            float m = s_bmax[0][q];
+#pragma unroll
+            for (int ww = 1; ww < kWaves; ++ww) m = fmaxf(m, s_bmax[ww][q]);
+            const int sl = value_slot<D, NV>(q);
+            scl[sl] = m > 0.0f ? (real)(Acc::range / m) : real(0);
+            inv[sl] = m > 0.0f ? (real)(m / Acc::range) : real(0);
+        }
+    }
     int lo[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
     int vol = 1;
 #pragma unroll
@@ -196,33 +285,58 @@ __device__ __forceinline__ void scatter_box(const Args<real>& a, const InstDev<r
         bext[k] = block_mode ? ext[k] : wext[k];
     }
     const int bcap = block_mode ? kBoxCap : kWaveBoxCap;
-    double* blds = block_mode ? lds : lds + w * 4 * kWaveBoxCap;
+    acc_t* blds = block_mode ? lds : lds + w * 4 * kWaveBoxCap;
     const int id = c * kWaves + (block_mode ? 0 : w);
     // zero the staging boxes
     if (block_mode) {
         for (int i = t; i < vol; i += kBlock)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) blds[q * bcap + i] = 0.0;
+            for (int q = 0; q < 4; ++q) blds[q * bcap + i] = acc_t(0);
     } else if (staged) {
         for (int i = t & 63; i < wvol; i += 64)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) blds[q * bcap + i] = 0.0;
+            for (int q = 0; q < 4; ++q) blds[q * bcap + i] = acc_t(0);
     }
     __syncthreads();
-    if (active && staged) {
-        int o = t % S3;
+    // segments of lanes sharing a stencil base within each 16-lane row
+    int seg_d, seg_tail;
+    {
+        const int lane = t & 63;
+        const int key = active ? (base[0] + n_grid * (base[1] + (D == 3 ? n_grid * base[D - 1] : 0))) : -1 - lane;
+        const int prev = __shfl_up(key, 1, 64);
+        const bool head = (lane & 15) == 0 || prev != key;
+        const uint64_t H = __ballot(head);
+        const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+        seg_d = lane - (63 - __clzll(H & upto));
+        seg_tail = (lane & 15) == 15 || ((H >> (lane + 1)) & 1ull);
+    }
+    if (staged) {
         int rel[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) rel[k] = base[k] - blo[k];
-        for (int it = 0; it < S3; ++it) {
-            int oa[D];
-            offset_split<D>(o, oa);
-            int li = rel[0] + oa[0] + bext[0] * (rel[1] + oa[1] + (D == 3 ? bext[1] * (rel[D - 1] + oa[D - 1]) : 0));
-            real v[NV];
-            vals(oa, v);
+        for (int k = 0; k < D; ++k) rel[k] = active ? base[k] - blo[k] : 0;
+        const int lrel = rel[0] + bext[0] * (rel[1] + (D == 3 ? bext[1] * rel[D - 1] : 0));
+        const bool emit = active && seg_tail;
 #pragma unroll
-            for (int q = 0; q < NV; ++q) atomicAdd(&blds[value_slot<D, NV>(q) * bcap + li], (double)v[q]);
-            o = (o + 1 == S3) ? 0 : o + 1;
+        for (int o = 0; o < S3; ++o) {
+            const int a0 = o % 3, a1 = (o / 3) % 3, a2 = o / 9;
+            int oa[D];
+            oa[0] = a0;
+            oa[1] = a1;
+            if (D == 3) oa[D - 1] = a2;
+            real v[NV];
+            if (active) {
+                vals(oa, v);
+            } else {
+#pragma unroll
+                for (int q = 0; q < NV; ++q) v[q] = real(0);
+            }
+            const int li = lrel + a0 + bext[0] * (a1 + (D == 3 ? bext[1] * a2 : 0));
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                const int sl = value_slot<D, NV>(q);
+                const acc_t sum = seg_row_sum(Acc::enc(v[q], scl[sl]), seg_d);
+                if (emit) atomicAdd(&blds[sl * bcap + li], sum);
+            }
         }
     } else if (active) {
         for (int o = 0; o < S3; ++o) {
@@ -242,11 +356,11 @@ __device__ __forceinline__ void scatter_box(const Args<real>& a, const InstDev<r
     if (block_mode) {
         for (int l = t; l < vol; l += kBlock)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) dst[4 * l + q] = (real)blds[q * bcap + l];
+            for (int q = 0; q < 4; ++q) dst[4 * l + q] = Acc::dec(blds[q * bcap + l], inv[q]);
     } else if (staged) {
         for (int l = t & 63; l < wvol; l += 64)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) dst[4 * l + q] = (real)blds[q * bcap + l];
+            for (int q = 0; q < 4; ++q) dst[4 * l + q] = Acc::dec(blds[q * bcap + l], inv[q]);
     }
     // one writer per descriptor: thread t < kWaves in block mode, lane 0 of each wave otherwise
     if (block_mode ? (t < kWaves) : ((t & 63) == 0)) {
@@ -263,42 +377,127 @@ __device__ __forceinline__ void scatter_box(const Args<real>& a, const InstDev<r
     // register the boxes (also the ranges of waves that fell back, so the
     // grid update visits their coarse blocks)
     if (block_mode) {
-        register_box<real, D>(a, I, id, lo, ext, blds, bcap, true, fb, phase, t, kBlock);
+        register_box<real, D>(a, I, id, lo, ext, blds, bcap, inv, true, fb, phase, t, kBlock);
     } else if (wave_live) {
-        register_box<real, D>(a, I, id, wlo, wext, blds, bcap, staged, fb, phase, t & 63, 64);
+        register_box<real, D>(a, I, id, wlo, wext, blds, bcap, inv, staged, fb, phase, t & 63, 64);
     }
 }
 
-// Gathers the boxes registered with coarse block b into the NV-value records
-// of its nodes (plus the dense fallback accumulator fb, which is cleared).
-// Calls node_fn(local node index, global node index, grid coords, summed[4]) for
-// every node of the block inside the grid, then resets the registration count.
+// Gathers the boxes registered with coarse block b into the records of its
+// nodes (plus the dense fallback accumulator fb, which is cleared), then calls
+// node_fn(global node index, grid coords, summed[4]) for every node of the block
+// inside the grid and resets the registration count. The (box, node) pairs of
+// all registered boxes are enumerated flat across the workgroup so their loads
+// are independent; sums go through LDS in double.
 template <typename real, int D, typename NodeFn>
 __device__ __forceinline__ void gather_coarse(const Args<real>& a, const InstDev<real>& I, int b, real* fb,
                                               NodeFn node_fn)
 {
     using CB = Coarse<D>;
+    constexpr int U = 8;   // pairs in flight per thread
     __shared__ int s_id[CB::cap];
-    __shared__ int4 s_lo[CB::cap], s_ext[CB::cap];
+    __shared__ int s_ilo[CB::cap][3];    // intersection origin (grid coords)
+    __shared__ int s_iext[CB::cap][3];   // intersection extent
+    __shared__ int s_blo[CB::cap][3];    // box origin and extent (for the box-local index)
+    __shared__ int s_bext[CB::cap][2];
+    __shared__ int s_off[CB::cap + 1];
+    __shared__ double s_acc[4][CB::nodes];
     const int t = threadIdx.x;
-    __syncthreads();   // the previous coarse block of this workgroup is done with the shared lists
+    __syncthreads();   // the previous coarse block of this workgroup is done with the shared arrays
     const int cnt_raw = a.reg_count[b];
     if (cnt_raw == 0) return;
     const int cnt = min(cnt_raw, CB::cap);
+    const int lb = b - I.cb_off;
+    const int bc[3] = {lb % I.nb, D == 3 ? (lb / I.nb) % I.nb : lb / I.nb, D == 3 ? lb / (I.nb * I.nb) : 0};
+    int co[3] = {bc[0] * CB::edge, bc[1] * CB::edge, D == 3 ? bc[2] * CB::edge : 0};
     for (int j = t; j < cnt; j += blockDim.x) {
-        int id = a.reg_list[b * CB::cap + j];
+        const int id = a.reg_list[b * CB::cap + j];
+        const int4 lo = a.box[2 * id], ex = a.box[2 * id + 1];
+        const int blo[3] = {lo.x, lo.y, lo.z}, bex[3] = {ex.x, ex.y, ex.z};
+        int sz = 1;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            int l = k < D ? max(blo[k], co[k]) : 0;
+            int h = k < D ? min(blo[k] + bex[k], co[k] + CB::edge) : 1;
+            int e = bex[k] > 0 ? max(0, h - l) : 0;
+            s_ilo[j][k] = l;
+            s_iext[j][k] = e;
+            s_blo[j][k] = blo[k];
+            sz *= e;
+        }
+        s_bext[j][0] = bex[0];
+        s_bext[j][1] = bex[1];
         s_id[j] = id;
-        s_lo[j] = a.box[2 * id];
-        s_ext[j] = a.box[2 * id + 1];
+        s_off[j + 1] = sz;
+    }
+    for (int i = t; i < CB::nodes; i += blockDim.x)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s_acc[q][i] = 0.0;
+    if (t == 0) s_off[0] = 0;
+    __syncthreads();
+    // inclusive scan of s_off[1..cnt] (cnt <= blockDim.x): wave scans, then wave totals
+    {
+        __shared__ int s_wsum[kWaves];
+        const int lane = t & 63, wv = t >> 6;
+        int v = (t < cnt) ? s_off[t + 1] : 0;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            int y = __shfl_up(v, off, 64);
+            if (lane >= off) v += y;
+        }
+        if (lane == 63) s_wsum[wv] = v;
+        __syncthreads();
+        int add = 0;
+        for (int w2 = 0; w2 < wv; ++w2) add += s_wsum[w2];
+        if (t < cnt) s_off[t + 1] = v + add;
     }
     __syncthreads();
-    const int lb = b - I.cb_off;
-    int bc[3] = {lb % I.nb, D == 3 ? (lb / I.nb) % I.nb : lb / I.nb, D == 3 ? lb / (I.nb * I.nb) : 0};
+    const int P = s_off[cnt];
+    for (int k0 = t; k0 < P; k0 += blockDim.x * U) {
+        const real* src[U];
+        int nl[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u * blockDim.x;
+            src[u] = nullptr;
+            nl[u] = 0;
+            if (k < P) {
+                int lo = 0, hi = cnt - 1;   // last j with s_off[j] <= k
+                while (lo < hi) {
+                    int mid = (lo + hi + 1) >> 1;
+                    if (s_off[mid] <= k) lo = mid; else hi = mid - 1;
+                }
+                const int j = lo;
+                int r = k - s_off[j];
+                const int ex0 = s_iext[j][0], ex1 = s_iext[j][1];
+                int g3[3];
+                g3[0] = s_ilo[j][0] + r % ex0;
+                r /= ex0;
+                g3[1] = s_ilo[j][1] + r % ex1;
+                g3[2] = s_ilo[j][2] + r / ex1;
+                const int l = (g3[0] - s_blo[j][0]) +
+                              s_bext[j][0] * ((g3[1] - s_blo[j][1]) + s_bext[j][1] * (g3[2] - s_blo[j][2]));
+                src[u] = a.part + (box_offset(s_id[j]) + l) * 4;
+                nl[u] = (g3[0] - co[0]) + CB::edge * ((g3[1] - co[1]) + CB::edge * (g3[2] - co[2]));
+            }
+        }
+        real v[U][4];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[u][q] = src[u] ? src[u][q] : real(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (src[u])
+#pragma unroll
+                for (int q = 0; q < 4; ++q) atomicAdd(&s_acc[q][nl[u]], (double)v[u][q]);
+    }
+    __syncthreads();
     for (int ln = t; ln < CB::nodes; ln += blockDim.x) {
         int g3[3];
-        g3[0] = bc[0] * CB::edge + ln % CB::edge;
-        g3[1] = bc[1] * CB::edge + (ln / CB::edge) % CB::edge;
-        g3[2] = D == 3 ? bc[2] * CB::edge + ln / (CB::edge * CB::edge) : 0;
+        g3[0] = co[0] + ln % CB::edge;
+        g3[1] = co[1] + (ln / CB::edge) % CB::edge;
+        g3[2] = D == 3 ? co[2] + ln / (CB::edge * CB::edge) : 0;
         bool inside = g3[0] < I.n_grid && g3[1] < I.n_grid && (D == 2 || g3[2] < I.n_grid);
         if (!inside) continue;
         const int64_t local = (int64_t)g3[0] + (int64_t)I.n_grid * (g3[1] + (D == 3 ? (int64_t)I.n_grid * g3[2] : 0));
@@ -306,45 +505,92 @@ __device__ __forceinline__ void gather_coarse(const Args<real>& a, const InstDev
         real acc[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            acc[q] = fb[4 * g + q];
+            acc[q] = fb[4 * g + q] + (real)s_acc[q][ln];
             fb[4 * g + q] = real(0);
         }
-        // four boxes per round so their loads are in flight together
-        for (int j0 = 0; j0 < cnt; j0 += 4) {
-            const real* src[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                src[u] = nullptr;
-                const int j = j0 + u;
-                if (j < cnt) {
-                    const int4 lo = s_lo[j], ex = s_ext[j];
-                    int rx = g3[0] - lo.x, ry = g3[1] - lo.y, rz = D == 3 ? g3[2] - lo.z : 0;
-                    if (rx >= 0 && rx < ex.x && ry >= 0 && ry < ex.y && (D == 2 || (rz >= 0 && rz < ex.z)))
-                        src[u] = a.part + (box_offset(s_id[j]) + rx + ex.x * (ry + ex.y * rz)) * 4;
-                }
-            }
-            real v[4][4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) v[u][q] = src[u] ? src[u][q] : real(0);
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) acc[q] += v[u][q];
-        }
-        node_fn((int)local, g, g3, acc);
+        node_fn(g, g3, acc);
     }
     __syncthreads();
     if (t == 0) a.reg_count[b] = 0;
 }
 
-__device__ __forceinline__ void chunk_origin(const int4* corig, int c, int org[3])
+// Box of grid nodes covering the active particles' stencils, copied from a
+// grid array (4 values per node) into LDS for the block's gathers.
+template <int D>
+struct NodeBox {
+    int lo[3], ext[3];
+    bool staged;
+};
+
+// Block-wide: reduces the bounding box of the active lanes' stencil bases and,
+// when it holds at most `cap` nodes, loads those node records of the instance
+// grid `src` into lds[4 * node] with coalesced loads. Every thread must call it.
+template <typename real, int D>
+__device__ __forceinline__ NodeBox<D> stage_nodes(const InstDev<real>& I, bool active, const int base[D],
+                                                  const real* src, real* lds, int cap)
 {
-    const int4 o = corig[c];
-    org[0] = o.x;
-    org[1] = o.y;
-    org[2] = o.z;
+    __shared__ int s_nb[kWaves][6];
+    const int t = threadIdx.x;
+    NodeBox<D> nb;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        nb.lo[k] = 0;
+        nb.ext[k] = 1;
+    }
+    int lo[D], hi[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        lo[k] = wave_min(active ? base[k] : 0x3fffffff);
+        hi[k] = wave_max(active ? base[k] : -0x3fffffff);
+    }
+    __syncthreads();   // s_nb may still be read by a previous call
+    if ((t & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            s_nb[t >> 6][k] = lo[k];
+            s_nb[t >> 6][3 + k] = hi[k];
+        }
+    __syncthreads();
+    int vol = 1;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        int l = s_nb[0][k], h = s_nb[0][3 + k];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) {
+            l = min(l, s_nb[w][k]);
+            h = max(h, s_nb[w][3 + k]);
+        }
+        nb.lo[k] = l;
+        nb.ext[k] = h - l + 3;
+        vol *= nb.ext[k];
+    }
+    nb.staged = vol > 0 && vol <= cap;
+    if (nb.staged) {
+        for (int l = t; l < vol; l += kBlock) {
+            int x = l % nb.ext[0], r = l / nb.ext[0];
+            int y = D == 3 ? r % nb.ext[1] : r;
+            int z = D == 3 ? r / nb.ext[1] : 0;
+            int64_t g = (int64_t)(nb.lo[0] + x) +
+                        (int64_t)I.n_grid * ((nb.lo[1] + y) + (D == 3 ? (int64_t)I.n_grid * (nb.lo[D - 1] + z) : 0));
+#pragma unroll
+            for (int q = 0; q < 4; ++q) lds[4 * l + q] = src[4 * g + q];
+        }
+    }
+    __syncthreads();
+    return nb;
+}
+
+// record of stencil node (base + a): from the staged box when there is one
+template <typename real, int D>
+__device__ __forceinline__ const real* node_rec(const NodeBox<D>& nb, const real* lds, const real* src,
+                                                const int base[D], const int a[D], int n)
+{
+    if (nb.staged) {
+        int l = (base[0] + a[0] - nb.lo[0]) +
+                nb.ext[0] * ((base[1] + a[1] - nb.lo[1]) + (D == 3 ? nb.ext[1] * (base[D - 1] + a[D - 1] - nb.lo[D - 1]) : 0));
+        return lds + 4 * l;
+    }
+    return src + 4 * ((int64_t)(base[0] + a[0]) + (int64_t)n * ((base[1] + a[1]) + (D == 3 ? (int64_t)n * (base[D - 1] + a[D - 1]) : 0)));
 }
 
 template <typename real, int D>
@@ -533,7 +779,7 @@ __device__ __forceinline__ void node_grad(const Stencil<real, D>& S, const int a
 template <typename real, int D>
 __global__ __launch_bounds__(kBlock) void k_p2g(Args<real> a, const real* __restrict__ st, int step)
 {
-    __shared__ double lds[4 * kBoxCap];
+    __shared__ typename LdsAcc<real>::T lds[4 * kBoxCap];
     const ChunkDev ch = a.chunks[blockIdx.x];
     const InstDev<real>& I = a.inst[ch.inst];
     const int t = threadIdx.x;
@@ -573,7 +819,17 @@ __global__ __launch_bounds__(kBlock) void k_p2g(Args<real> a, const real* __rest
 #pragma unroll
     for (int k = 0; k < D; ++k) mv[k] = T.m * q.v[k];
     const real dx = I.dx;
-    scatter_box<real, D, D + 1>(a, I, lds, active, Sx.base, a.gm, 0,
+    // magnitude bound of one contribution (weights <= 1, |dpos| <= 1.5 dx)
+    real bnd[D + 1];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+        real s = fabs(mv[r]);
+#pragma unroll
+        for (int c = 0; c < D; ++c) s += fabs(T.A[r][c]) * real(1.5) * dx;
+        bnd[r] = s;
+    }
+    bnd[D] = T.m;
+    scatter_box<real, D, D + 1>(a, I, lds, active, Sx.base, bnd, a.gm, 0,
         [&](const int o[D], real out[D + 1]) {
             real dpos[D];
             real w = node_weight<real, D>(Sx, o, dx, dpos);
@@ -657,17 +913,18 @@ __device__ __forceinline__ int node_velocity(const InstDev<real>& I, const int i
     return branch;
 }
 
-// One block per coarse block: gathers the staged P2G boxes, applies Eqs. 16-18
-// and writes the node velocity. keep = 1 (reverse sweep) also stores the summed
-// (momentum, mass) for the grid transpose and clears the adjoint accumulator.
+// Grid-stride over the coarse blocks the P2G registered: gathers the staged
+// boxes, applies Eqs. 16-18 and writes the node velocity to gv_out. When gmd_out
+// is given (reverse sweep) the summed (momentum, mass) records are kept there
+// for the grid transpose.
 template <typename real, int D>
-__global__ __launch_bounds__(kGridBlock) void k_grid(Args<real> a, int keep)
+__global__ __launch_bounds__(kGridBlock) void k_grid(Args<real> a, real* gv_out, real* gmd_out)
 {
   const int n_act = a.active[0];
   for (int ai = blockIdx.x; ai < n_act; ai += gridDim.x) {
     const int b = a.active_list[ai];
     const InstDev<real>& I = a.inst[a.cb_inst[b]];
-    gather_coarse<real, D>(a, I, b, a.gm, [&](int local, int64_t g, const int g3[3], const real node[4]) {
+    gather_coarse<real, D>(a, I, b, a.gm, [&](int64_t g, const int g3[3], const real node[4]) {
         real v[D];
         if (node[3] > real(0)) {
             int ijk[D];
@@ -682,14 +939,10 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Args<real> a, int keep)
             for (int k = 0; k < D; ++k) v[k] = real(0);
         }
 #pragma unroll
-        for (int k = 0; k < D; ++k) a.gv[4 * g + k] = v[k];
-        if (keep) {
+        for (int k = 0; k < D; ++k) gv_out[4 * g + k] = v[k];
+        if (gmd_out)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                a.gmd[4 * g + q] = node[q];
-                a.gbar[4 * g + q] = real(0);
-            }
-        }
+            for (int q = 0; q < 4; ++q) gmd_out[4 * g + q] = node[q];
     });
   }
 }
@@ -699,7 +952,8 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Args<real> a, int keep)
 // --------------------------------------------------------------------------
 
 template <typename real, int D>
-__global__ __launch_bounds__(kBlock) void k_g2p(Args<real> a, const real* sin, real* sout, int step, int traj_on)
+__global__ __launch_bounds__(kBlock) void k_g2p(Args<real> a, const real* __restrict__ gv_in, const real* sin,
+                                                real* sout, int step, int traj_on)
 {
     const ChunkDev ch = a.chunks[blockIdx.x];
     const InstDev<real>& I = a.inst[ch.inst];
@@ -718,7 +972,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(Args<real> a, const real* sin, r
         chunk_origin(a.corig, blockIdx.x, org);
         Stencil<real, D> Sx;
         make_stencil<real, D>(x, org, I.inv_dx, I.n_grid, Sx);
-        const real* gv = a.gv + 4 * (int64_t)I.grid_off;
+        const real* gv = gv_in + 4 * (int64_t)I.grid_off;
         real vn[D], Bm[D][D];
 #pragma unroll
         for (int r = 0; r < D; ++r) {
@@ -913,10 +1167,11 @@ __global__ __launch_bounds__(kBlock) void k_seed(Args<real> a, const real* st, r
 // --------------------------------------------------------------------------
 
 template <typename real, int D>
-__global__ __launch_bounds__(kBlock) void k_g2p_adj(Args<real> a, const real* st, real* adj, const real* dloss)
+__global__ __launch_bounds__(kBlock) void k_g2p_adj(Args<real> a, const real* __restrict__ gv_in, const real* st,
+                                                    real* adj, const real* dloss)
 {
     using Cp = Comp<D>;
-    __shared__ double lds[4 * kBoxCap];
+    __shared__ typename LdsAcc<real>::T lds[4 * kBoxCap];
     const ChunkDev ch = a.chunks[blockIdx.x];
     const InstDev<real>& I = a.inst[ch.inst];
     const int t = threadIdx.x;
@@ -961,66 +1216,54 @@ __global__ __launch_bounds__(kBlock) void k_g2p_adj(Args<real> a, const real* st
     chunk_origin(a.corig, blockIdx.x, org);
     Stencil<real, D> Sx;
     make_stencil<real, D>(x, org, I.inv_dx, I.n_grid, Sx);
-    const real* gv = a.gv + 4 * (int64_t)I.grid_off;
-    // recompute C' of the forward G2P
+    const real* gv = gv_in + 4 * (int64_t)I.grid_off;
+    // the velocity box is staged in the LDS that later holds the scatter box
+    real* glds = reinterpret_cast<real*>(lds);
+    const NodeBox<D> nbx = stage_nodes<real, D>(I, active, Sx.base, gv, glds, kBoxCap);
+    // x' = x + dt v' and F' = (I + dt C') F give vbt = vb' + dt xb' and
+    // Cbt = Cb' + dt Fb' F^T, neither of which depends on C'
+    real Cbt[D][D], vbt[D], xb[D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+        vbt[r] = vb1[r] + I.dt * xb1[r];
+        xb[r] = xb1[r];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            real u = Cb1[r][c];
+#pragma unroll
+            for (int k = 0; k < D; ++k) u += I.dt * Fb1[r][k] * F[c][k];
+            Cbt[r][c] = u;
+        }
+    }
+    const real lam = I.lam, dx = I.dx;
+    // one gather pass: C' of the forward G2P, and the share of xbar through the
+    // weights and dpos, which needs the grid velocity:
+    // xb += (v_i . u_i) grad w - lam w Cbt^T v_i,  u_i = vbt + lam Cbt dpos_i
     real Bm[D][D];
 #pragma unroll
     for (int r = 0; r < D; ++r)
 #pragma unroll
         for (int c = 0; c < D; ++c) Bm[r][c] = 0;
     if (active) {
+#pragma unroll 3
         for (int o = 0; o < Cp::S3; ++o) {
             int oa[D];
             offset_split<D>(o, oa);
-            real dpos[D];
-            real w = node_weight<real, D>(Sx, oa, I.dx, dpos);
-            real vi[D];
-            load_vec<real, D>(gv + 4 * node_index<real, D>(Sx.base, oa, I.n_grid), vi);
-#pragma unroll
-            for (int r = 0; r < D; ++r)
-#pragma unroll
-                for (int c = 0; c < D; ++c) Bm[r][c] += w * vi[r] * dpos[c];
-        }
-    }
-    // F' = (I + dt C') F  ->  Fb = (I + dt C')^T Fb',  Cbt = Cb' + dt Fb' F^T
-    real Fb[D][D], Cbt[D][D], vbt[D], xb[D];
-#pragma unroll
-    for (int r = 0; r < D; ++r)
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            real s = Fb1[r][c];
-            real u = Cb1[r][c];
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                s += I.dt * I.lam * Bm[k][r] * Fb1[k][c];
-                u += I.dt * Fb1[r][k] * F[c][k];
-            }
-            Fb[r][c] = s;
-            Cbt[r][c] = u;
-        }
-    // x' = x + dt v'
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-        vbt[k] = vb1[k] + I.dt * xb1[k];
-        xb[k] = xb1[k];
-    }
-    const real lam = I.lam, dx = I.dx;
-    scatter_box<real, D, D>(a, I, lds, active, Sx.base, a.gbar, 1,
-        [&](const int o[D], real out[D]) {
             real dpos[D], gw[D];
-            real w = node_weight<real, D>(Sx, o, dx, dpos);
-            node_grad<real, D>(Sx, o, gw);
+            real w = node_weight<real, D>(Sx, oa, dx, dpos);
+            node_grad<real, D>(Sx, oa, gw);
             real vi[D];
-            load_vec<real, D>(gv + 4 * node_index<real, D>(Sx.base, o, I.n_grid), vi);
+            load_vec<real, D>(node_rec<real, D>(nbx, glds, gv, Sx.base, oa, I.n_grid), vi);
             real vu = 0;
 #pragma unroll
             for (int r = 0; r < D; ++r) {
-                real s = 0;
+                real cd = 0;
 #pragma unroll
-                for (int c = 0; c < D; ++c) s += Cbt[r][c] * dpos[c];
-                real u = vbt[r] + lam * s;
-                out[r] = w * u;
-                vu += vi[r] * u;
+                for (int c = 0; c < D; ++c) {
+                    Bm[r][c] += w * vi[r] * dpos[c];
+                    cd += Cbt[r][c] * dpos[c];
+                }
+                vu += vi[r] * (vbt[r] + lam * cd);
             }
 #pragma unroll
             for (int k = 0; k < D; ++k) {
@@ -1028,6 +1271,39 @@ __global__ __launch_bounds__(kBlock) void k_g2p_adj(Args<real> a, const real* st
 #pragma unroll
                 for (int r = 0; r < D; ++r) ctv += Cbt[r][k] * vi[r];
                 xb[k] += vu * gw[k] - lam * w * ctv;
+            }
+        }
+    }
+    // F' = (I + dt C') F  ->  Fb = (I + dt C')^T Fb'
+    real Fb[D][D];
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            real s = Fb1[r][c];
+#pragma unroll
+            for (int k = 0; k < D; ++k) s += I.dt * lam * Bm[k][r] * Fb1[k][c];
+            Fb[r][c] = s;
+        }
+    // scatter w u_i to the grid velocity adjoint (registers only)
+    real bnd[D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+        real s = fabs(vbt[r]);
+#pragma unroll
+        for (int c = 0; c < D; ++c) s += lam * fabs(Cbt[r][c]) * real(1.5) * dx;
+        bnd[r] = s;
+    }
+    scatter_box<real, D, D>(a, I, lds, active, Sx.base, bnd, a.gbar, 1,
+        [&](const int o[D], real out[D]) {
+            real dpos[D];
+            real w = node_weight<real, D>(Sx, o, dx, dpos);
+#pragma unroll
+            for (int r = 0; r < D; ++r) {
+                real cd = 0;
+#pragma unroll
+                for (int c = 0; c < D; ++c) cd += Cbt[r][c] * dpos[c];
+                out[r] = w * (vbt[r] + lam * cd);
             }
         });
     if (active) {
@@ -1045,16 +1321,17 @@ __global__ __launch_bounds__(kBlock) void k_g2p_adj(Args<real> a, const real* st
 // --------------------------------------------------------------------------
 
 template <typename real, int D>
-__global__ __launch_bounds__(kGridBlock) void k_grid_adj(Args<real> a)
+__global__ __launch_bounds__(kGridBlock) void k_grid_adj(Args<real> a, const real* __restrict__ gmd_in,
+                                                         real* __restrict__ gpm_out)
 {
   const int n_act = a.active[1];
   for (int ai = blockIdx.x; ai < n_act; ai += gridDim.x) {
     const int b = a.active_list[a.n_coarse + ai];
     const InstDev<real>& I = a.inst[a.cb_inst[b]];
-    gather_coarse<real, D>(a, I, b, a.gbar, [&](int local, int64_t g, const int g3[3], const real vb[4]) {
+    gather_coarse<real, D>(a, I, b, a.gbar, [&](int64_t g, const int g3[3], const real vb[4]) {
         real node[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) node[q] = a.gmd[4 * g + q];
+        for (int q = 0; q < 4; ++q) node[q] = gmd_in[4 * g + q];
         real out[4] = {0, 0, 0, 0};
         if (node[3] > real(0)) {
             int ijk[D];
@@ -1105,7 +1382,7 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_adj(Args<real> a)
             out[3] = mb * rm;
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a.gbar[4 * g + q] = out[q];
+        for (int q = 0; q < 4; ++q) gpm_out[4 * g + q] = out[q];
     });
   }
 }
@@ -1115,7 +1392,8 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_adj(Args<real> a)
 // --------------------------------------------------------------------------
 
 template <typename real, int D>
-__global__ __launch_bounds__(kBlock) void k_p2g_adj(Args<real> a, const real* st, real* adj, int step)
+__global__ __launch_bounds__(kBlock, sizeof(real) == 4 ? 3 : 2) void k_p2g_adj(Args<real> a, const real* __restrict__ gpm_in, const real* st,
+                                                    real* adj, int step)
 {
     using Cp = Comp<D>;
     const ChunkDev ch = a.chunks[blockIdx.x];
@@ -1130,20 +1408,27 @@ __global__ __launch_bounds__(kBlock) void k_p2g_adj(Args<real> a, const real* st
     double gBl[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) gBl[k] = 0.0;
+    __shared__ real lds[4 * kBoxCap];
+    Particle<real, D> q;
+    real phi = 0, br[D];
+    int org[3];
+    chunk_origin(a.corig, blockIdx.x, org);
+    Stencil<real, D> Sx;
     if (active) {
-        Particle<real, D> q;
         load_particle<real, D>(st, a.x0s, S, i, q);
-        const real phi = a.phi[i];
-        real br[D];
+        phi = a.phi[i];
 #pragma unroll
         for (int k = 0; k < D; ++k) br[k] = a.br[k * S + i];
-        int org[3];
-        chunk_origin(a.corig, blockIdx.x, org);
-        Stencil<real, D> Sx;
-        make_stencil<real, D>(q.x, org, I.inv_dx, I.n_grid, Sx);
+    } else {
+#pragma unroll
+        for (int k = 0; k < D; ++k) q.x[k] = real(0.5);
+    }
+    make_stencil<real, D>(q.x, org, I.inv_dx, I.n_grid, Sx);
+    const real* gsrc = gpm_in + 4 * (int64_t)I.grid_off;
+    const NodeBox<D> nbx = stage_nodes<real, D>(I, active, Sx.base, gsrc, lds, kBoxCap);
+    if (active) {
         P2GTerms<real, D> T;
         p2g_terms<real, D>(I, q, phi, br, B, T);
-        const real* gb = a.gbar + 4 * (int64_t)I.grid_off;
         real mb = 0, vb[D], Ab[D][D], xb[D];
 #pragma unroll
         for (int r = 0; r < D; ++r) {
@@ -1152,13 +1437,14 @@ __global__ __launch_bounds__(kBlock) void k_p2g_adj(Args<real> a, const real* st
 #pragma unroll
             for (int c = 0; c < D; ++c) Ab[r][c] = 0;
         }
+#pragma unroll 3
         for (int o = 0; o < Cp::S3; ++o) {
             int oa[D];
             offset_split<D>(o, oa);
             real dpos[D], gw[D];
             real w = node_weight<real, D>(Sx, oa, I.dx, dpos);
             node_grad<real, D>(Sx, oa, gw);
-            const real* nd = gb + 4 * node_index<real, D>(Sx.base, oa, I.n_grid);
+            const real* nd = node_rec<real, D>(nbx, lds, gsrc, Sx.base, oa, I.n_grid);
             real pb[D];
             load_vec<real, D>(nd, pb);
             real mbi = nd[3];
@@ -1187,6 +1473,14 @@ __global__ __launch_bounds__(kBlock) void k_p2g_adj(Args<real> a, const real* st
             }
         }
         mb += ddot<real, D>(Ab, q.C);
+        // Recompute the stress here rather than keeping it live through the
+        // gather loop (the empty asm hides F's value so the compiler does not
+        // reuse the copy from before the loop); this halves register pressure.
+#pragma unroll
+        for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int c = 0; c < D; ++c) asm volatile("" : "+v"(q.F[r][c]));
+        p2g_terms<real, D>(I, q, phi, br, B, T);
         // A = m C - kappa V P F^T
         real Pb[D][D], Fbp[D][D], dP[D][D];
 #pragma unroll
