@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "particle-steps/s fwd+adjoint vs plain fwd; grad rel err vs FP64 oracle"
 
 # particle-steps the oracle sample covers, per workload: (instances, steps)
-CPU_SAMPLE = {"c1": (1, 120), "c2": (1, 20), "c3": (1, 20), "c4": (2, 20), "c5": (1, 1)}
+CPU_SAMPLE = {"cantilever2d": (1, 500), "walker2d": (1, 200), "plate3d": (1, 300), "batch2d": (4, 100), "quadruped3d": (1, 6)}
 
 
 def log(*a):
@@ -140,7 +140,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c5", choices=sorted(W.WORKLOADS))
+    ap.add_argument("--workload", default="quadruped3d", choices=sorted(W.WORKLOADS))
     ap.add_argument("--n-steps", type=int, default=0, help="override the rollout length (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")

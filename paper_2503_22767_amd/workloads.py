@@ -14,13 +14,15 @@ program is a piecewise-constant stand-in for the harmonic stimulus of Eq. 29.
 
 Workloads (the paper prints no particle counts, grids or targets, so these are
 synthetic stand-ins with its case-study shapes):
-  c1  2D cantilever, 64^2 grid, 1,280 particles, FP64, 500 steps, final-shape loss
-  c2  2D three-leg walker on a frictional floor, 256^2 grid, 30,593 particles,
-      2,000 steps, centre-of-mass displacement loss
-  c3  3D clamped plate, 64^3 grid, 16,384 particles, 1,000 steps, surface-shape loss
-  c4  64 independent 2D beams/walkers, 1k..30k particles each, 1,000 steps
-  c5  3D quadruped, 128^3 grid, 1,146,344 particles, three field programs sharing
-      one design (Eq. 35), 4,000 steps each
+  cantilever2d  2D cantilever, 64^2 grid, 1,280 particles, FP64, 500 steps,
+                final-shape loss
+  walker2d      2D three-leg walker on a frictional floor, 256^2 grid, 30,593
+                particles, 2,000 steps, centre-of-mass displacement loss
+  plate3d       3D clamped plate, 64^3 grid, 16,384 particles, 1,000 steps,
+                surface-shape loss
+  batch2d       64 independent 2D beams/walkers, 1k..30k particles each, 1,000 steps
+  quadruped3d   3D quadruped, 128^3 grid, 1,146,344 particles, three field
+                programs sharing one design (Eq. 35), 4,000 steps each
 """
 from __future__ import annotations
 
@@ -210,36 +212,36 @@ def quadruped_particles(n_grid: int, s: int, floor_y: float = 0.05) -> np.ndarra
 # the workloads
 # ----------------------------------------------------------------------------
 
-def make_c1(seed: int = 1, n_steps: int = 500) -> Workload:
+def make_cantilever2d(seed: int = 1, n_steps: int = 500) -> Workload:
     rng = np.random.default_rng(seed)
     inst = beam_instance(rng, dim=2, n_grid=64, s=2, length=0.625, height=0.125,
                          dt=1e-4, n_steps=500, n_segments=5)
     inst.params["n_steps"] = n_steps
     inst.params["ckpt_every"] = 1
-    return Workload("c1", [inst], 8,
+    return Workload("cantilever2d", [inst], 8,
                     "2D plane-strain cantilever, 64^2 grid, 1,280 particles, FP64")
 
 
-def make_c2(seed: int = 2, n_steps: int = 2000) -> Workload:
+def make_walker2d(seed: int = 2, n_steps: int = 2000) -> Workload:
     rng = np.random.default_rng(seed)
     inst = walker_instance(rng, n_grid=256, s=3, dt=5e-5, n_steps=2000, n_segments=20)
     inst.params["n_steps"] = n_steps
     inst.params["ckpt_every"] = 100
-    return Workload("c2", [inst], 4,
+    return Workload("walker2d", [inst], 4,
                     "2D three-leg walker, 256^2 grid, 30,593 particles, floor mu=0.5")
 
 
-def make_c3(seed: int = 3, n_steps: int = 1000, n_grid: int = 64) -> Workload:
+def make_plate3d(seed: int = 3, n_steps: int = 1000, n_grid: int = 64) -> Workload:
     rng = np.random.default_rng(seed)
     inst = beam_instance(rng, dim=3, n_grid=n_grid, s=2, length=0.5, height=0.125,
                          dt=1e-4, n_steps=1000, n_segments=10, loss="bend")
     inst.params["n_steps"] = n_steps
     inst.params["ckpt_every"] = 100
-    return Workload("c3", [inst], 4,
+    return Workload("plate3d", [inst], 4,
                     f"3D clamped plate, {n_grid}^3 grid, {inst.n} particles")
 
 
-def make_c4(seed: int = 4, n_steps: int = 1000, n_instances: int = 64) -> Workload:
+def make_batch2d(seed: int = 4, n_steps: int = 1000, n_instances: int = 64) -> Workload:
     rng = np.random.default_rng(seed)
     counts = np.round(np.exp(rng.uniform(math.log(1e3), math.log(3e4), size=n_instances)))
     insts = []
@@ -260,10 +262,10 @@ def make_c4(seed: int = 4, n_steps: int = 1000, n_instances: int = 64) -> Worklo
         inst.params["n_steps"] = n_steps
         inst.params["ckpt_every"] = 100
         insts.append(inst)
-    return Workload("c4", insts, 4, f"{n_instances} batched 2D beams/walkers")
+    return Workload("batch2d", insts, 4, f"{n_instances} batched 2D beams/walkers")
 
 
-def make_c5(seed: int = 5, n_steps: int = 4000, n_grid: int = 128, s: int = 3) -> Workload:
+def make_quadruped3d(seed: int = 5, n_steps: int = 4000, n_grid: int = 128, s: int = 3) -> Workload:
     rng = np.random.default_rng(seed)
     dx = 1.0 / n_grid
     h = dx / s
@@ -289,7 +291,7 @@ def make_c5(seed: int = 5, n_steps: int = 4000, n_grid: int = 128, s: int = 3) -
         else:
             p.update(seg_steps=100, periodic=0, loss_kind=LOSS_FINAL_MSE)
             insts.append(Instance(p, x0, density, br, progs[task], target, mask, group=0))
-    return Workload("c5", insts, 4,
+    return Workload("quadruped3d", insts, 4,
                     f"3D quadruped, {n_grid}^3 grid, {n} particles x 3 field programs")
 
 
@@ -332,7 +334,7 @@ def make_tiny(seed: int = 0, dim: int = 2, n_grid: int = 16, s: int = 2, n_steps
     return Instance(p, x0, density, br, b_prog, target, mask)
 
 
-WORKLOADS = {"c1": make_c1, "c2": make_c2, "c3": make_c3, "c4": make_c4, "c5": make_c5}
+WORKLOADS = {"cantilever2d": make_cantilever2d, "walker2d": make_walker2d, "plate3d": make_plate3d, "batch2d": make_batch2d, "quadruped3d": make_quadruped3d}
 
 
 def make(name: str, **kw) -> Workload:

@@ -49,51 +49,51 @@ def test_fp32_matches_oracle(case):
     compare(got, ref, pos_tol=1e-4, grad_tol=1e-3, label=f"fp32 {case}")
 
 
-def test_c1_full_fp64():
+def test_cantilever2d_full_fp64():
     """The 2D cantilever workload (64^2 grid, 1,280 particles, 500 steps, FP64)."""
-    wl = W.make_c1()
+    wl = W.make_cantilever2d()
     inst = wl.instances[0]
     ref = oracle_run([inst], ckpt_every=25)
     got = gpu_run([inst], precision=8)
-    compare(got, ref, pos_tol=1e-10, grad_tol=1e-9, loss_tol=1e-9, label="c1 fp64")
+    compare(got, ref, pos_tol=1e-10, grad_tol=1e-9, loss_tol=1e-9, label="cantilever2d fp64")
 
 
-def test_c1_full_fp32():
-    wl = W.make_c1()
+def test_cantilever2d_full_fp32():
+    wl = W.make_cantilever2d()
     inst = wl.instances[0]
     ref = oracle_run([inst], ckpt_every=25)
     got = gpu_run([inst], precision=4)
-    compare(got, ref, pos_tol=1e-4, grad_tol=1e-3, label="c1 fp32")
+    compare(got, ref, pos_tol=1e-4, grad_tol=1e-3, label="cantilever2d fp32")
 
 
-def test_c2_walker_full_size_first_steps():
+def test_walker2d_full_size_first_steps():
     """The 2D walker at full size (256^2 grid, 30,593 particles, floor contact),
     first 160 steps of its program, FP32."""
-    wl = W.make_c2(n_steps=160)
+    wl = W.make_walker2d(n_steps=160)
     inst = wl.instances[0]
     ref = oracle_run([inst], ckpt_every=16)
     got = gpu_run([inst], precision=4, options={"ckpt_every": 16})
-    compare(got, ref, pos_tol=1e-4, grad_tol=1e-3, label="c2[:160] fp32")
+    compare(got, ref, pos_tol=1e-4, grad_tol=1e-3, label="walker2d[:160] fp32")
 
 
-def test_c3_plate_full_size_first_steps():
+def test_plate3d_full_size_first_steps():
     """The 3D plate at full size (64^3 grid, 16,384 particles), first 40 steps, FP32."""
-    wl = W.make_c3(n_steps=40)
+    wl = W.make_plate3d(n_steps=40)
     inst = wl.instances[0]
     ref = oracle_run([inst], ckpt_every=8)
     got = gpu_run([inst], precision=4)
-    compare(got, ref, pos_tol=1e-4, grad_tol=1e-3, label="c3[:40] fp32")
+    compare(got, ref, pos_tol=1e-4, grad_tol=1e-3, label="plate3d[:40] fp32")
 
 
-def test_c5_quadruped_full_size_first_steps():
+def test_quadruped3d_full_size_first_steps():
     """The 3D quadruped at full size (128^3 grid, 1,146,344 particles per task):
     the locomotion task (centre-of-mass loss, floor contact, gravity) and the
     morphing task (final-shape loss) over their first 2 steps, FP32."""
-    wl = W.make_c5(n_steps=2)
+    wl = W.make_quadruped3d(n_steps=2)
     insts = [wl.instances[0], wl.instances[2]]
     ref = oracle_run(insts, ckpt_every=1)
     got = gpu_run(insts, precision=4)
-    compare(got, ref, pos_tol=1e-4, grad_tol=1e-3, label="c5[:2] tasks 0,2 fp32")
+    compare(got, ref, pos_tol=1e-4, grad_tol=1e-3, label="quadruped3d[:2] tasks 0,2 fp32")
 
 
 def _cloud(dim, seed, n=700, n_grid=32, steps=12):

@@ -24,7 +24,7 @@ from paper_2503_22767_amd import workloads as W
 
 
 def _cantilever(Ba, theta, n_steps, dt=4e-3, c=0.7):
-    inst = W.make_c1().instances[0]
+    inst = W.make_cantilever2d().instances[0]
     p = dict(inst.params)
     p.update(dt=dt, n_steps=n_steps, damping=c, n_segments=1, seg_steps=0)
     br = np.zeros_like(inst.br); br[:, 0] = 1.0
@@ -88,7 +88,7 @@ def test_simp_interpolation_scales_the_response():
     eps + (1 - eps) phi^3 equals phi, the same factor as the mass, so the motion is
     that of a full-density beam whose magnetic load is scaled by s_m / phi = phi^2."""
     phi_g = (math.sqrt(5.0) - 1.0) / 2.0
-    inst = W.make_c1().instances[0]
+    inst = W.make_cantilever2d().instances[0]
     outs = []
     for phi, eps in ((1.0, 0.5), (phi_g, 0.5)):
         p = dict(inst.params)

@@ -131,7 +131,7 @@ def test_mirror_symmetry_axial_field():
     """Beam centred on the y = 0.5 node line, remanence and field both along x:
     the magnetic effect vanishes for parallel vectors and the problem is mirror
     symmetric, so particle pairs (x, y) and (x, 1 - y) stay mirrored."""
-    wl = W.make_c1(n_steps=150)
+    wl = W.make_cantilever2d(n_steps=150)
     inst = wl.instances[0]
     p = dict(inst.params)
     br = np.zeros_like(inst.br); br[:, 0] = 1.0
