@@ -38,13 +38,20 @@ template <typename real> struct LdsAcc;
 template <> struct LdsAcc<float> {
     using T = int;
     static constexpr float range = 1073741824.0f / (float)kBlock;   // 2^30 / contributions per node
-    __device__ static T enc(float v, float s) { return __float2int_rn(v * s); }
+    // w u + 1.5 2^23 leaves w u rounded to the nearest integer in the low
+    // mantissa bits (|w u| <= 2^22); subtracting the bits of 1.5 2^23 yields it
+    static constexpr float magic = 12582912.0f;
+    static constexpr unsigned magic_bits = 0x4B400000u;
+    __device__ static T enc(float w, float u)
+    {
+        return (int)((unsigned)__float_as_int(__fmaf_rn(w, u, magic)) - magic_bits);
+    }
     __device__ static float dec(T a, float inv) { return (float)a * inv; }
 };
 template <> struct LdsAcc<double> {
     using T = double;
     static constexpr double range = 0.0;
-    __device__ static T enc(double v, double) { return v; }
+    __device__ static T enc(double w, double u) { return w * u; }
     __device__ static double dec(T a, double) { return a; }
 };
 // coarse blocks of the grid used to hand staged boxes to the grid update
@@ -149,10 +156,9 @@ __device__ __forceinline__ void register_box(const Args<real>& a, const InstDev<
 }
 
 // Lanes of one 16-lane row that share a stencil base form contiguous segments
-// (particles are sorted along a Hilbert curve of their cells). seg_d = lane
-// distance to the start of its segment within the row. seg_row_sum adds, into
-// the last lane of each segment, the values of the whole segment (four DPP
-// shift-right steps, an exact sum for the fixed-point integers).
+// (particles are sorted along a Hilbert curve of their cells). Four DPP
+// shift-right steps leave in the last lane of each segment the sum of the
+// segment's values (exact for the fixed-point integers).
 __device__ __forceinline__ int dpp_shr(int v, int off)
 {
     switch (off) {
@@ -163,26 +169,36 @@ __device__ __forceinline__ int dpp_shr(int v, int off)
     }
 }
 
-__device__ __forceinline__ int seg_row_sum(int v, int seg_d)
+// one step of the segmented sum: add the value of lane l - off when the mask
+// (all ones or zero) says that lane is in the same segment
+__device__ __forceinline__ int seg_step(int v, int off, int m) { return v + (dpp_shr(v, off) & m); }
+
+__device__ __forceinline__ double seg_step(double v, int off, int m)
 {
-#pragma unroll
-    for (int off = 1; off < 16; off <<= 1) {
-        int y = dpp_shr(v, off);
-        v = seg_d >= off ? v + y : v;
-    }
-    return v;
+    const int lo = dpp_shr(__double2loint(v), off) & m;
+    const int hi = dpp_shr(__double2hiint(v), off) & m;
+    return v + __hiloint2double(hi, lo);
 }
 
-__device__ __forceinline__ double seg_row_sum(double v, int seg_d)
+// segmented sums of NV values at once (steps interleaved over the values so
+// the DPP reads do not wait on the adds just issued)
+template <int NV, typename T>
+__device__ __forceinline__ void seg_row_sums(T (&e)[NV], const int (&m)[4])
 {
 #pragma unroll
-    for (int off = 1; off < 16; off <<= 1) {
-        int lo = dpp_shr(__double2loint(v), off);
-        int hi = dpp_shr(__double2hiint(v), off);
-        double y = __hiloint2double(hi, lo);
-        v = seg_d >= off ? v + y : v;
-    }
-    return v;
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) e[q] = seg_step(e[q], 1 << j, m[j]);
+}
+
+// inclusive prefix sums within each 16-lane row (integers, modulo 2^32)
+template <int NV>
+__device__ __forceinline__ void row_prefix_sums(int (&e)[NV])
+{
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) e[q] = (int)((unsigned)e[q] + (unsigned)dpp_shr(e[q], 1 << j));
 }
 
 // Adds NV values per stencil node of every active particle of the block to the
@@ -316,26 +332,47 @@ __device__ __forceinline__ void scatter_box(const Args<real>& a, const InstDev<r
         for (int k = 0; k < D; ++k) rel[k] = active ? base[k] - blo[k] : 0;
         const int lrel = rel[0] + bext[0] * (rel[1] + (D == 3 ? bext[1] * rel[D - 1] : 0));
         const bool emit = active && seg_tail;
+        int msk[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) msk[j] = seg_d >= (1 << j) ? -1 : 0;
+        // FP32 (integer sums): a segment's sum is the row prefix at its tail
+        // minus the row prefix just before its head, so the tail adds the one
+        // and the head subtracts the other (exact in modular arithmetic)
+        const bool head_sub = active && seg_d == 0 && (t & 15) != 0;
+        real sq[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) sq[q] = scl[value_slot<D, NV>(q)];
 #pragma unroll
         for (int o = 0; o < S3; ++o) {
-            const int a0 = o % 3, a1 = (o / 3) % 3, a2 = o / 9;
             int oa[D];
-            oa[0] = a0;
-            oa[1] = a1;
-            if (D == 3) oa[D - 1] = a2;
-            real v[NV];
-            if (active) {
-                vals(oa, v);
+            oa[0] = o % 3;
+            oa[1] = (o / 3) % 3;
+            if (D == 3) oa[D - 1] = o / 9;
+            real wgt, u[NV];
+            vals(oa, sq, wgt, u);
+            acc_t e[NV];
+#pragma unroll
+            for (int q = 0; q < NV; ++q) e[q] = Acc::enc(wgt, u[q]);
+            const int li = lrel + oa[0] + bext[0] * (oa[1] + (D == 3 ? bext[1] * oa[D - 1] : 0));
+            if constexpr (sizeof(acc_t) == 4) {
+                row_prefix_sums<NV>(e);
+                acc_t pm[NV];
+#pragma unroll
+                for (int q = 0; q < NV; ++q) pm[q] = dpp_shr(e[q], 1);
+                if (emit) {
+#pragma unroll
+                    for (int q = 0; q < NV; ++q) atomicAdd(&blds[value_slot<D, NV>(q) * bcap + li], e[q]);
+                }
+                if (head_sub) {
+#pragma unroll
+                    for (int q = 0; q < NV; ++q) atomicSub(&blds[value_slot<D, NV>(q) * bcap + li], pm[q]);
+                }
             } else {
+                seg_row_sums<NV>(e, msk);
+                if (emit) {
 #pragma unroll
-                for (int q = 0; q < NV; ++q) v[q] = real(0);
-            }
-            const int li = lrel + a0 + bext[0] * (a1 + (D == 3 ? bext[1] * a2 : 0));
-#pragma unroll
-            for (int q = 0; q < NV; ++q) {
-                const int sl = value_slot<D, NV>(q);
-                const acc_t sum = seg_row_sum(Acc::enc(v[q], scl[sl]), seg_d);
-                if (emit) atomicAdd(&blds[sl * bcap + li], sum);
+                    for (int q = 0; q < NV; ++q) atomicAdd(&blds[value_slot<D, NV>(q) * bcap + li], e[q]);
+                }
             }
         }
     } else if (active) {
@@ -344,10 +381,12 @@ __device__ __forceinline__ void scatter_box(const Args<real>& a, const InstDev<r
             offset_split<D>(o, oa);
             int64_t g = (int64_t)I.grid_off + (int64_t)(base[0] + oa[0]) +
                         (int64_t)n_grid * ((base[1] + oa[1]) + (D == 3 ? (int64_t)n_grid * (base[D - 1] + oa[D - 1]) : 0));
-            real v[NV];
-            vals(oa, v);
+            real one[NV], wgt, u[NV];
 #pragma unroll
-            for (int q = 0; q < NV; ++q) atomic_add(&fb[4 * g + value_slot<D, NV>(q)], v[q]);
+            for (int q = 0; q < NV; ++q) one[q] = real(1);
+            vals(oa, one, wgt, u);
+#pragma unroll
+            for (int q = 0; q < NV; ++q) atomic_add(&fb[4 * g + value_slot<D, NV>(q)], wgt * u[q]);
         }
     }
     __syncthreads();
@@ -753,6 +792,19 @@ __device__ __forceinline__ real node_weight(const Stencil<real, D>& S, const int
     return w;
 }
 
+// the same weight with the product taken over the outer axes first, so that
+// stencil nodes sharing their (y, z) offsets share that partial product
+template <typename real, int D>
+__device__ __forceinline__ real node_weight_outer(const Stencil<real, D>& S, const int a[D], real dx, real dpos[D])
+{
+    real w = sel3(S.w[D - 1], a[D - 1]);
+#pragma unroll
+    for (int k = D - 2; k >= 0; --k) w = sel3(S.w[k], a[k]) * w;
+#pragma unroll
+    for (int k = 0; k < D; ++k) dpos[k] = (real(a[k]) - S.f[k]) * dx;
+    return w;
+}
+
 template <typename real, int D>
 __device__ __forceinline__ void node_grad(const Stencil<real, D>& S, const int a[D], real gw[D])
 {
@@ -830,17 +882,17 @@ __global__ __launch_bounds__(kBlock) void k_p2g(Args<real> a, const real* __rest
     }
     bnd[D] = T.m;
     scatter_box<real, D, D + 1>(a, I, lds, active, Sx.base, bnd, a.gm, 0,
-        [&](const int o[D], real out[D + 1]) {
+        [&](const int o[D], const real sq[D + 1], real& w, real u[D + 1]) {
             real dpos[D];
-            real w = node_weight<real, D>(Sx, o, dx, dpos);
+            w = node_weight_outer<real, D>(Sx, o, dx, dpos);
 #pragma unroll
             for (int r = 0; r < D; ++r) {
-                real s = mv[r];
+                real s = mv[r] * sq[r];
 #pragma unroll
-                for (int c = 0; c < D; ++c) s += T.A[r][c] * dpos[c];
-                out[r] = w * s;
+                for (int c = D - 1; c >= 0; --c) s += (T.A[r][c] * sq[r]) * dpos[c];
+                u[r] = s;
             }
-            out[D] = w * T.m;
+            u[D] = T.m * sq[D];
         });
 }
 
@@ -1295,15 +1347,15 @@ __global__ __launch_bounds__(kBlock) void k_g2p_adj(Args<real> a, const real* __
         bnd[r] = s;
     }
     scatter_box<real, D, D>(a, I, lds, active, Sx.base, bnd, a.gbar, 1,
-        [&](const int o[D], real out[D]) {
+        [&](const int o[D], const real sq[D], real& w, real u[D]) {
             real dpos[D];
-            real w = node_weight<real, D>(Sx, o, dx, dpos);
+            w = node_weight_outer<real, D>(Sx, o, dx, dpos);
 #pragma unroll
             for (int r = 0; r < D; ++r) {
-                real cd = 0;
+                real s = vbt[r] * sq[r];
 #pragma unroll
-                for (int c = 0; c < D; ++c) cd += Cbt[r][c] * dpos[c];
-                out[r] = w * (vbt[r] + lam * cd);
+                for (int c = D - 1; c >= 0; --c) s += (lam * Cbt[r][c] * sq[r]) * dpos[c];
+                u[r] = s;
             }
         });
     if (active) {
