@@ -96,6 +96,22 @@ def roofline(sim, tens, dloss):
                 avg_launch_us=round(avg_ms * 1e3, 2), bytes_per_launch=int(bytes_per_launch)), per_kernel
 
 
+def separate(wl, opts, reps=2):
+    """Forward + adjoint of every instance through a handle of its own, run
+    one after another; returns seconds per pass over all instances."""
+    runs = []
+    for inst in wl.instances:
+        one = W.Workload(wl.name, [inst], wl.precision)
+        sim, tens, dtype = make_sim(one, opts)
+        runs.append((sim, tens, torch.ones(1, dtype=dtype, device="cuda")))
+    for sim, tens, dl in runs:
+        run_step(sim, tens, dl)
+    t = timed(lambda: [run_step(sim, tens, dl) for sim, tens, dl in runs], reps)
+    for sim, _, _ in runs:
+        sim.close()
+    return t
+
+
 def cpu_baseline(wl_name, wl, sim_tol_check=True):
     """FP64 oracle on a bounded sample of the workload: the first instances and
     steps listed in CPU_SAMPLE. Returns the baseline record and the sample."""
@@ -145,6 +161,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--option", action="append", default=[], help="library option key=value")
+    ap.add_argument("--compare-separate", action="store_true",
+                    help="also time one handle per instance (default for the batched workload)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not built.",
@@ -185,6 +203,11 @@ def main():
                            grid=[i.params["n_grid"] for i in wl.instances[:1]][0], parallelism="single-gpu"),
                fwd_value=round(ps / t_fwd, 1), fwd_ms=round(t_fwd * 1e3, 3),
                adj_over_fwd=round((t_step - t_rec) / t_fwd, 3), fwdadj_over_fwd=round(t_step / t_fwd, 3))
+    if args.compare_separate or wl.name == "batch2d":
+        t_sep = separate(wl, opts)
+        rec["separate_ms_per_step"] = round(t_sep * 1e3, 3)
+        rec["batched_speedup"] = round(t_sep / t_step, 3)
+        log(f"[bench] {len(wl.instances)} separate handles: {t_sep * 1e3:.1f} ms per fwd+adj pass")
     if not args.no_roofline:
         rl, per_kernel = roofline(sim, tens, dloss)
         rec["roofline"] = rl

@@ -141,10 +141,11 @@ const char* mpm_mag_last_error(const mpm_mag* h);
 
 /*
  * Tuning and instrumentation switches (key = value):
- *   "graph"         1: replay captured HIP graphs of step sequences (default), 0: direct launches
+ *   "graph"         1: capture the step loop of a rollout and the reverse sweep of
+ *                   backward once into HIP graphs and replay them on the stream;
+ *                   0: direct launches (default). Ignored while kernel_timing is on.
  *   "kernel_timing" 1: bracket every kernel launch with HIP events on the stream
  *   "p2g_lds"       1: LDS-staged scatter (default), 0: direct global atomics
- *   "fused"         1: fused G2P->P2G step kernel in the forward (default), 0: separate kernels
  *   "ckpt_every"    checkpoint spacing K (0: automatic); takes effect at the next recorded rollout
  * Returns EINVAL for an unknown key or value.
  */

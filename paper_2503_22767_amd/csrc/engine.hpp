@@ -187,10 +187,13 @@ public:
     {
         if (!key) return fail(MPM_MAG_EINVAL, "null option key");
         std::string k(key);
-        if (k == "graph") { graph_ = value != 0; return MPM_MAG_OK; }
+        if (k == "graph") {
+            if (value != 0 && value != 1) return fail(MPM_MAG_EINVAL, "graph must be 0 or 1");
+            graph_ = value != 0;
+            return MPM_MAG_OK;
+        }
         if (k == "kernel_timing") { timing_ = value != 0; return MPM_MAG_OK; }
         if (k == "p2g_lds") { use_lds_ = value != 0; return MPM_MAG_OK; }
-        if (k == "fused") { fused_ = value != 0; return MPM_MAG_OK; }
         if (k == "ckpt_every") {
             if (value < 0 || value > (1 << 30)) return fail(MPM_MAG_EINVAL, "bad ckpt_every");
             ckpt_opt_ = (int)value;
@@ -224,14 +227,19 @@ public:
         MPM_HIP(hipMemcpyAsync(bprog_, b_prog, sizeof(real) * S_tot_ * D, hipMemcpyDeviceToDevice, s));
         int st = sort_and_gather(s, (const real*)x0, (const real*)density, (const real*)br, (const real*)target, mask);
         if (st) return st;
-        for (int n = 0; n < T_; ++n) {
-            if (record && n % K_ == 0) {
-                MPM_HIP(hipMemcpyAsync(ckpt_slot(n / K_), st_, state_bytes(), hipMemcpyDeviceToDevice, s));
-                count(K_CKPT, 2.0 * state_bytes());
+        auto steps = [&](hipStream_t cs) -> int {
+            for (int n = 0; n < T_; ++n) {
+                if (record && n % K_ == 0) {
+                    MPM_HIP(hipMemcpyAsync(ckpt_slot(n / K_), st_, state_bytes(), hipMemcpyDeviceToDevice, cs));
+                    count(K_CKPT, 2.0 * state_bytes());
+                }
+                int r = step(cs, n, st_, st_, true);
+                if (r) return r;
             }
-            st = step(s, n, st_, st_, true);
-            if (st) return st;
-        }
+            return MPM_MAG_OK;
+        };
+        st = use_graph() ? replay(s, gfwd_[record ? 1 : 0], steps) : steps(s);
+        if (st) return st;
         Args<real> a = args();
         st = launch(K_LOSS, s, n_chunks_, kBlock, k_loss_sums<real, D>, a, (const real*)st_, (const real*)x0s_,
                     (const real*)tgt_, (const uint8_t*)mask_, has_target_ ? 1 : 0);
@@ -257,42 +265,49 @@ public:
         if (!dloss) return fail(MPM_MAG_EINVAL, "dloss is required");
         MPM_HIP(hipMemsetAsync(err_d_, 0, sizeof(int), s));
         MPM_HIP(hipMemsetAsync(gB_, 0, sizeof(double) * S_tot_ * D, s));
+        MPM_HIP(hipMemcpyAsync(dloss_, dloss, sizeof(real) * n_inst_, hipMemcpyDeviceToDevice, s));
         MPM_HIP(hipMemsetAsync(active_, 0, sizeof(int) * 2, s));
         Args<real> a = args();
         int st = launch(K_SEED, s, n_chunks_, kBlock, k_seed<real, D>, a, (const real*)st_, adj_,
-                        (const real*)x0s_, (const real*)tgt_, (const uint8_t*)mask_, (const real*)dloss);
+                        (const real*)x0s_, (const real*)tgt_, (const uint8_t*)mask_, (const real*)dloss_);
         if (st) return st;
-        for (int c = nck_ - 1; c >= 0; --c) {
-            const int s0 = c * K_;
-            const int s1 = std::min(T_, s0 + K_);
-            // recompute the segment, keeping every step's grid (sparse: only
-            // the active coarse blocks are written)
-            for (int n = s0; n < s1; ++n) {
-                const int j = n - s0;
-                st = launch(K_P2G, s, n_chunks_, kBlock, k_p2g<real, D>, a, (const real*)seg_state(c, j), n);
-                if (st) return st;
-                st = launch(K_GRID, s, grid_blocks(), kGridBlock, k_grid<real, D>, a, gv_slot(j), gm_slot(j));
-                if (st) return st;
-                if (n + 1 < s1) {
-                    st = launch(K_G2P, s, n_chunks_, kBlock, k_g2p<real, D>, a, (const real*)gv_slot(j),
-                                (const real*)seg_state(c, j), seg_state(c, j + 1), n, 0);
-                    if (st) return st;
+        auto sweep = [&](hipStream_t cs) -> int {
+            int r = MPM_MAG_OK;
+            for (int c = nck_ - 1; c >= 0; --c) {
+                const int s0 = c * K_;
+                const int s1 = std::min(T_, s0 + K_);
+                // recompute the segment, keeping every step's grid (sparse: only
+                // the active coarse blocks are written)
+                for (int n = s0; n < s1; ++n) {
+                    const int j = n - s0;
+                    r = launch(K_P2G, cs, n_chunks_, kBlock, k_p2g<real, D>, a, (const real*)seg_state(c, j), n);
+                    if (r) return r;
+                    r = launch(K_GRID, cs, grid_blocks(), kGridBlock, k_grid<real, D>, a, gv_slot(j), gm_slot(j));
+                    if (r) return r;
+                    if (n + 1 < s1) {
+                        r = launch(K_G2P, cs, n_chunks_, kBlock, k_g2p<real, D>, a, (const real*)gv_slot(j),
+                                    (const real*)seg_state(c, j), seg_state(c, j + 1), n, 0);
+                        if (r) return r;
+                    }
+                }
+                // transpose of every step, last first
+                for (int n = s1 - 1; n >= s0; --n) {
+                    const int j = n - s0;
+                    const real* sn = seg_state(c, j);
+                    r = launch(K_G2P_ADJ, cs, n_chunks_, kBlock, k_g2p_adj<real, D>, a, (const real*)gv_slot(j), sn, adj_,
+                                (const real*)dloss_);
+                    if (r) return r;
+                    r = launch(K_GRID_ADJ, cs, grid_blocks(), kGridBlock, k_grid_adj<real, D>, a, (const real*)gm_slot(j),
+                                gpm_);
+                    if (r) return r;
+                    r = launch(K_P2G_ADJ, cs, n_chunks_, kBlock, k_p2g_adj<real, D>, a, (const real*)gpm_, sn, adj_, n);
+                    if (r) return r;
                 }
             }
-            // transpose of every step, last first
-            for (int n = s1 - 1; n >= s0; --n) {
-                const int j = n - s0;
-                const real* sn = seg_state(c, j);
-                st = launch(K_G2P_ADJ, s, n_chunks_, kBlock, k_g2p_adj<real, D>, a, (const real*)gv_slot(j), sn, adj_,
-                            (const real*)dloss);
-                if (st) return st;
-                st = launch(K_GRID_ADJ, s, grid_blocks(), kGridBlock, k_grid_adj<real, D>, a, (const real*)gm_slot(j),
-                            gpm_);
-                if (st) return st;
-                st = launch(K_P2G_ADJ, s, n_chunks_, kBlock, k_p2g_adj<real, D>, a, (const real*)gpm_, sn, adj_, n);
-                if (st) return st;
-            }
-        }
+            return MPM_MAG_OK;
+        };
+        st = use_graph() ? replay(s, gbwd_, sweep) : sweep(s);
+        if (st) return st;
         if (g_density || g_br) {
             st = launch(K_OUT, s, n_chunks_, kBlock, k_scatter_out<real, D>, a, (const int*)id_, (const real*)st_,
                         (real*)nullptr, (real*)g_density, (real*)g_br);
@@ -415,6 +430,67 @@ private:
         return events_[ev_used_++];
     }
 
+    // ------------------------------------------------------------ graphs
+    // The step loop of a rollout and the reverse sweep of backward touch only
+    // buffers the handle owns, so each is captured once into a HIP graph and
+    // replayed on the caller's stream. A graph is rebuilt when the checkpoint
+    // plan (and with it the buffer addresses) changes. Per-kernel launch and
+    // byte counters recorded during capture are re-added on every replay.
+    struct Graph {
+        hipGraphExec_t exec = nullptr;
+        int64_t key = -1;
+        KernelStat delta[K_COUNT];
+    };
+
+    bool use_graph() const { return graph_ && !timing_; }
+
+    void drop(Graph& g)
+    {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g.exec = nullptr;
+        g.key = -1;
+    }
+
+    template <typename Body>
+    int replay(hipStream_t s, Graph& g, Body body)
+    {
+        const int64_t key = plan_gen_;
+        if (!g.exec || g.key != key) {
+            drop(g);
+            if (!cap_) MPM_HIP(hipStreamCreateWithFlags(&cap_, hipStreamNonBlocking));
+            KernelStat before[K_COUNT];
+            for (int k = 0; k < K_COUNT; ++k) before[k] = stats_[k];
+            MPM_HIP(hipStreamBeginCapture(cap_, hipStreamCaptureModeThreadLocal));
+            const int st = body(cap_);
+            hipGraph_t graph = nullptr;
+            const hipError_t e = hipStreamEndCapture(cap_, &graph);
+            for (int k = 0; k < K_COUNT; ++k) {
+                g.delta[k].launches = stats_[k].launches - before[k].launches;
+                g.delta[k].bytes = stats_[k].bytes - before[k].bytes;
+                g.delta[k].ms = 0.0;
+                stats_[k] = before[k];
+            }
+            if (st) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return st;
+            }
+            if (e != hipSuccess) return fail(MPM_MAG_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+            const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ei != hipSuccess) {
+                g.exec = nullptr;
+                return fail(MPM_MAG_EHIP, std::string("graph instantiation: ") + hipGetErrorString(ei));
+            }
+            g.key = key;
+        }
+        MPM_HIP(hipGraphLaunch(g.exec, s));
+        for (int k = 0; k < K_COUNT; ++k) {
+            stats_[k].launches += g.delta[k].launches;
+            stats_[k].bytes += g.delta[k].bytes;
+        }
+        return MPM_MAG_OK;
+    }
+
     // one forward step n: P2G, grid operation, G2P (sin -> sout)
     int step(hipStream_t s, int n, real* sin, real* sout, bool traj)
     {
@@ -498,6 +574,7 @@ private:
         bytes_ += ckpt_bytes_ + stash_bytes_;
         K_ = K;
         nck_ = nck;
+        ++plan_gen_;
         return MPM_MAG_OK;
     }
 
@@ -544,6 +621,7 @@ private:
         st |= dalloc(&gB_, (size_t)S_tot_ * D);
         st |= dalloc(&acc_, (size_t)kAccCount * n_inst_);
         st |= dalloc(&loss_val_, (size_t)n_inst_);
+        st |= dalloc(&dloss_, (size_t)n_inst_);
         st |= dalloc(&err_d_, 1);
         for (int b = 0; b < 2; ++b) {
             st |= dalloc(&keys_[b], (size_t)N_);
@@ -572,6 +650,11 @@ private:
 
     void release()
     {
+        drop(gfwd_[0]);
+        drop(gfwd_[1]);
+        drop(gbwd_);
+        if (cap_) (void)hipStreamDestroy(cap_);
+        cap_ = nullptr;
         for (void* p : allocs_) (void)hipFree(p);
         allocs_.clear();
         if (ckpt_) (void)hipFree(ckpt_);
@@ -621,6 +704,7 @@ private:
     std::vector<int> cb_inst_h_;
     int64_t n_cb_ = 0;
     double *gB_ = nullptr, *acc_ = nullptr, *loss_val_ = nullptr;
+    real* dloss_ = nullptr;   // copy of the upstream loss gradient (stable address for graphs)
     int* err_d_ = nullptr;
     int* err_h_ = nullptr;
     uint32_t* keys_[2] = {nullptr, nullptr};
@@ -635,9 +719,13 @@ private:
     int K_ = 0, nck_ = 0, ckpt_desc_ = 0, ckpt_opt_ = 0;
     bool recorded_ = false, has_target_ = false;
     // options
-    bool graph_ = false, timing_ = false, use_lds_ = true, fused_ = false;
+    bool graph_ = false, timing_ = false, use_lds_ = true;
     std::vector<hipEvent_t> events_;
     size_t ev_used_ = 0;
+    // captured graphs: forward step loop (plain, recorded) and reverse sweep
+    Graph gfwd_[2], gbwd_;
+    hipStream_t cap_ = nullptr;
+    int64_t plan_gen_ = 0;
     std::vector<Pending> pending_;
 };
 
