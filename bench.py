@@ -161,6 +161,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--option", action="append", default=[], help="library option key=value")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick launch options with the autotuner (cached) before timing")
     ap.add_argument("--compare-separate", action="store_true",
                     help="also time one handle per instance (default for the batched workload)")
     args = ap.parse_args()
@@ -180,6 +182,12 @@ def main():
         opts[k] = int(v)
     log(f"[bench] workload {wl.name}: {wl.description}; {len(wl.instances)} instance(s), "
         f"N={wl.n_particles}, T={wl.n_steps}")
+    tuned = None
+    if args.autotune:
+        from paper_2503_22767_amd import autotune as A
+        tuned = A.autotune(wl.instances, wl.precision, log=log)
+        log(f"[bench] autotune {tuned['key']}: {tuned['options']} ({'cached' if tuned['cached'] else 'timed'})")
+        opts = {**tuned["options"], **opts}
     sim, tens, dtype = make_sim(wl, opts)
     dloss = torch.ones(len(wl.instances), dtype=dtype, device="cuda")
     log(f"[bench] device bytes {sim.device_bytes() / 2**30:.2f} GiB (before checkpoints)")
@@ -203,6 +211,8 @@ def main():
                            grid=[i.params["n_grid"] for i in wl.instances[:1]][0], parallelism="single-gpu"),
                fwd_value=round(ps / t_fwd, 1), fwd_ms=round(t_fwd * 1e3, 3),
                adj_over_fwd=round((t_step - t_rec) / t_fwd, 3), fwdadj_over_fwd=round(t_step / t_fwd, 3))
+    if tuned is not None:
+        rec["tuned_options"] = tuned["options"]
     if args.compare_separate or wl.name == "batch2d":
         t_sep = separate(wl, opts)
         rec["separate_ms_per_step"] = round(t_sep * 1e3, 3)

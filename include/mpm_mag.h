@@ -146,6 +146,11 @@ const char* mpm_mag_last_error(const mpm_mag* h);
  *                   0: direct launches (default). Ignored while kernel_timing is on.
  *   "kernel_timing" 1: bracket every kernel launch with HIP events on the stream
  *   "p2g_lds"       1: LDS-staged scatter (default), 0: direct global atomics
+ *   "sort_curve"    particle order by cell: 0 Hilbert (default), 1 Morton, 2 row major;
+ *                   takes effect at the next rollout
+ *   "box_cap"       largest per-block staging box in grid nodes, 64..1024 (default 1024);
+ *                   larger boxes are staged per wave or fall back to global atomics
+ *   "grid_wgs"      workgroups of the grid kernels, 16..2^20 (default 2048)
  *   "ckpt_every"    checkpoint spacing K (0: automatic); takes effect at the next recorded rollout
  * Returns EINVAL for an unknown key or value.
  */

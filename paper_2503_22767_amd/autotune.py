@@ -1,0 +1,200 @@
+"""Launch-option autotuner for the MPM library.
+
+The knobs are options of the library:
+  sort_curve  order of the particles by cell (Hilbert, Morton, row major)
+  box_cap     largest per-block LDS staging box before per-wave boxes
+  grid_wgs    workgroups of the grid kernels (they stride over active blocks)
+  graph       replay of captured HIP graphs instead of direct launches
+  p2g_lds     LDS-staged scatter vs direct global atomics
+
+Each candidate setting is timed on the workload's own instances over a short
+horizon (20 steps by default): a recorded rollout and its backward, median of
+a few repetitions after one untimed run, which also sorts and captures. The
+search is coordinate descent from the library defaults, one knob at a time.
+The winner must reproduce the defaults' loss and gradients (the options change
+summation order only); otherwise the defaults are kept. Results are cached in
+a JSON file keyed by precision, dimension, grid sizes, particle count (to the
+nearest power of two), particles per cell and instance count.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import statistics
+import tempfile
+import time
+from typing import Callable, Dict, List, Sequence, Tuple
+
+DEFAULTS: Dict[str, int] = dict(sort_curve=0, box_cap=1024, grid_wgs=2048, graph=0, p2g_lds=1)
+SPACE: Dict[str, List[int]] = dict(
+    sort_curve=[0, 1, 2],
+    box_cap=[256, 512, 1024],
+    grid_wgs=[256, 1024, 2048, 4096],
+    graph=[0, 1],
+    p2g_lds=[1, 0],
+)
+CACHE_ENV = "MPM_MAG_TUNE_CACHE"
+
+
+def default_cache_path() -> str:
+    return os.environ.get(CACHE_ENV) or os.path.join(os.path.expanduser("~"), ".cache", "mpm_mag", "autotune.json")
+
+
+def particles_per_cell(params: dict) -> int:
+    dx = 1.0 / params["n_grid"]
+    return int(round(dx ** params["dim"] / params["particle_volume"]))
+
+
+def cache_key(instances: Sequence, precision: int) -> str:
+    """Workload signature: what the best launch options depend on."""
+    n = sum(int(i.n) for i in instances)
+    dims = {int(i.params["dim"]) for i in instances}
+    grids = sorted({int(i.params["n_grid"]) for i in instances})
+    ppc = sorted({particles_per_cell(i.params) for i in instances})
+    nb = int(round(math.log2(max(1, n))))
+    return (f"fp{8 * precision}-d{'/'.join(map(str, sorted(dims)))}-g{'/'.join(map(str, grids))}"
+            f"-n2^{nb}-ppc{'/'.join(map(str, ppc))}-inst{len(instances)}")
+
+
+def load_cache(path: str) -> dict:
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        return data if isinstance(data, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(path: str, data: dict) -> None:
+    d = os.path.dirname(os.path.abspath(path))
+    os.makedirs(d, exist_ok=True)
+    fd, tmp = tempfile.mkstemp(dir=d, prefix=".autotune.", suffix=".json")
+    with os.fdopen(fd, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def coordinate_descent(measure: Callable[[Dict[str, int]], float], space: Dict[str, List[int]],
+                       start: Dict[str, int], rounds: int = 1) -> Tuple[Dict[str, int], float, list]:
+    """Minimize measure(options) one knob at a time (each knob's values tried
+    with the others held at the best so far). Returns (best options, best
+    time, [(options, time), ...] of every evaluation)."""
+    best = dict(start)
+    seen: Dict[tuple, float] = {}
+    table = []
+
+    def ev(opts):
+        key = tuple(sorted(opts.items()))
+        if key not in seen:
+            seen[key] = float(measure(dict(opts)))
+            table.append((dict(opts), seen[key]))
+        return seen[key]
+
+    best_t = ev(best)
+    for _ in range(rounds):
+        changed = False
+        for knob, values in space.items():
+            for v in values:
+                if v == best.get(knob):
+                    continue
+                cand = dict(best)
+                cand[knob] = v
+                t = ev(cand)
+                if t < best_t:
+                    best, best_t, changed = cand, t, True
+        if not changed:
+            break
+    return best, best_t, table
+
+
+def _short(instances, steps):
+    from . import workloads as W
+    out = []
+    for i in instances:
+        p = dict(i.params)
+        p["n_steps"] = steps
+        p["ckpt_every"] = 0
+        out.append(W.Instance(p, i.x0, i.density, i.br, i.b_prog, i.target, i.mask, i.group))
+    return out
+
+
+def autotune(instances, precision: int, steps: int = 20, reps: int = 3, cache_path: str = None,
+             force: bool = False, space: Dict[str, List[int]] = None, log: Callable = None) -> dict:
+    """Best launch options for this workload (from the cache when present).
+
+    Returns {"options": {...}, "seconds": t, "default_seconds": t0, "cached": bool, "key": key}."""
+    import numpy as np
+    import torch
+
+    from . import mpm_mag as M
+
+    space = space or SPACE
+    path = cache_path or default_cache_path()
+    key = cache_key(instances, precision)
+    cache = load_cache(path)
+    if not force and key in cache and isinstance(cache[key].get("options"), dict):
+        rec = dict(cache[key])
+        rec.update(cached=True, key=key)
+        return rec
+    short = _short(instances, steps)
+    dtype = torch.float32 if precision == 4 else torch.float64
+    sim = M.MpmMag([i.params for i in short], [i.n for i in short], precision=precision)
+    try:
+        tens = M.instance_tensors(short, dtype=dtype)
+        dl = torch.ones(len(short), dtype=dtype, device="cuda")
+
+        def run(opts):
+            for k, v in opts.items():
+                sim.set_option(k, int(v))
+            loss, _ = sim.rollout(*tens, record=True, want_x=False)
+            g = sim.backward(dl)
+            return loss, g
+
+        def measure(opts):
+            run(opts)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                run(opts)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            t = statistics.median(ts)
+            if log:
+                log(f"[autotune] {opts} {t * 1e3:.2f} ms")
+            return t
+
+        def outputs(opts):
+            loss, g = run(opts)
+            torch.cuda.synchronize()
+            return [loss.double().cpu().numpy()] + [x.double().cpu().numpy() for x in g]
+
+        start = {k: DEFAULTS[k] for k in space}
+        best, best_t, table = coordinate_descent(measure, space, start)
+        t0 = next(t for o, t in table if o == start)
+        # the options change summation order only: the winner must agree with the defaults
+        ref = outputs(start)
+        got = outputs(best)
+        ok = True
+        for a, b in zip(got, ref):
+            den = float(np.linalg.norm(b))
+            err = float(np.linalg.norm(a - b)) / den if den > 0 else float(np.linalg.norm(a - b))
+            ok &= err <= 1e-3
+        if not ok:
+            best, best_t = start, t0
+    finally:
+        sim.close()
+    rec = dict(options=best, seconds=best_t, default_seconds=t0, steps=steps,
+               table=[[o, t] for o, t in table])
+    cache = load_cache(path)
+    cache[key] = rec
+    save_cache(path, cache)
+    out = dict(rec)
+    out.update(cached=False, key=key)
+    return out
+
+
+def apply(sim, options: Dict[str, int]) -> None:
+    for k, v in options.items():
+        sim.set_option(k, int(v))

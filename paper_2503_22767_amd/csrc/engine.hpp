@@ -177,6 +177,7 @@ public:
         kp_.n_inst = n_inst;
         kp_.cell_bits = max_cell_bits;
         kp_.axis_bits = max_axis_bits;
+        kp_.curve = 0;
         if (max_cell_bits + inst_bits > 32) return fail(MPM_MAG_EINVAL, "too many grid cells x instances for the sort key");
         sort_passes_ = (max_cell_bits + inst_bits + 7) / 8;
         sort_blocks_ = (int)((N_ + kSortTile - 1) / kSortTile);
@@ -193,7 +194,28 @@ public:
             return MPM_MAG_OK;
         }
         if (k == "kernel_timing") { timing_ = value != 0; return MPM_MAG_OK; }
-        if (k == "p2g_lds") { use_lds_ = value != 0; return MPM_MAG_OK; }
+        if (k == "p2g_lds") {
+            use_lds_ = value != 0;
+            ++plan_gen_;   // kernel arguments of captured launches
+            return MPM_MAG_OK;
+        }
+        if (k == "sort_curve") {
+            if (value < 0 || value > 2) return fail(MPM_MAG_EINVAL, "sort_curve must be 0, 1 or 2");
+            kp_.curve = (int)value;
+            return MPM_MAG_OK;
+        }
+        if (k == "box_cap") {
+            if (value < 64 || value > kBoxCap) return fail(MPM_MAG_EINVAL, "box_cap must be in [64, 1024]");
+            box_cap_ = (int)value;
+            ++plan_gen_;   // kernel arguments of captured launches
+            return MPM_MAG_OK;
+        }
+        if (k == "grid_wgs") {
+            if (value < 16 || value > (1 << 20)) return fail(MPM_MAG_EINVAL, "grid_wgs must be in [16, 2^20]");
+            grid_wgs_ = (int)value;
+            ++plan_gen_;   // baked into captured launches
+            return MPM_MAG_OK;
+        }
         if (k == "ckpt_every") {
             if (value < 0 || value > (1 << 30)) return fail(MPM_MAG_EINVAL, "bad ckpt_every");
             ckpt_opt_ = (int)value;
@@ -324,7 +346,7 @@ public:
 
 private:
     // workgroups of the grid kernels, which stride over the active coarse blocks
-    int grid_blocks() const { return (int)std::min<int64_t>(n_cb_, 2048); }
+    int grid_blocks() const { return (int)std::min<int64_t>(n_cb_, grid_wgs_); }
     size_t state_elems() const { return (size_t)Cp::NC * nalloc_; }
     size_t state_bytes() const { return sizeof(real) * state_elems(); }
     real* ckpt_slot(int c) { return ckpt_ + (size_t)c * state_elems(); }
@@ -371,6 +393,7 @@ private:
         a.n_coarse = (int)n_cb_;
 
         a.use_lds = use_lds_ ? 1 : 0;
+        a.box_cap = box_cap_;
         return a;
     }
 
@@ -720,6 +743,7 @@ private:
     bool recorded_ = false, has_target_ = false;
     // options
     bool graph_ = false, timing_ = false, use_lds_ = true;
+    int box_cap_ = kBoxCap, grid_wgs_ = 2048;
     std::vector<hipEvent_t> events_;
     size_t ev_used_ = 0;
     // captured graphs: forward step loop (plain, recorded) and reverse sweep

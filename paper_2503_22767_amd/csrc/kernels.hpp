@@ -91,6 +91,7 @@ struct Args {
     int* active_list;    // [2][n_coarse]
     int n_coarse;
     int use_lds;
+    int box_cap;         // largest block staging box (nodes, <= kBoxCap)
 };
 
 // --------------------------------------------------------------------------
@@ -291,7 +292,7 @@ __device__ __forceinline__ void scatter_box(const Args<real>& a, const InstDev<r
         ext[k] = h - l + 3;
         vol *= ext[k];
     }
-    const bool block_mode = a.use_lds && vol <= kBoxCap;
+    const bool block_mode = a.use_lds && vol <= a.box_cap;
     // this lane's staging box: the block's, or its wave's
     const bool staged = block_mode || (a.use_lds && wave_live && wvol <= kWaveBoxCap);
     int blo[3], bext[3];

@@ -1,5 +1,5 @@
-// Cell binning of particles: spatial keys (instance, Hilbert index of the
-// particle's cell) and a stable LSD radix sort of (key, caller index) pairs with
+// Cell binning of particles: spatial keys (instance, Hilbert, Morton or
+// row-major index of the particle's cell) and a stable LSD radix sort of (key, caller index) pairs with
 // 8-bit digits. One block histograms / scatters kSortTile consecutive items;
 // ranks inside a wave come from ballots, waves of a block take their turn.
 #pragma once
@@ -15,7 +15,17 @@ struct KeyParams {
     int n_inst;
     int cell_bits;      // bits of the per-instance cell key (dim * axis_bits)
     int axis_bits;      // bits per axis: ceil(log2(n_grid)) over the instances
+    int curve;          // cell order: 0 Hilbert, 1 Morton (Z order), 2 row major (x fastest)
 };
+
+// Morton index: bits of the axes interleaved, x least significant.
+__device__ __forceinline__ uint32_t morton_index(const int c[3], int dim, int bits)
+{
+    uint32_t key = 0;
+    for (int b = bits - 1; b >= 0; --b)
+        for (int i = dim - 1; i >= 0; --i) key = (key << 1) | (((uint32_t)c[i] >> b) & 1u);
+    return key;
+}
 
 // Hilbert index of a cell (dim 2 or 3, `bits` bits per axis) by Skilling's
 // transpose method ("Programming the Hilbert curve", AIP Conf. Proc. 707,
@@ -71,7 +81,15 @@ __global__ __launch_bounds__(kBlock) void k_sort_keys(const InstDev<real>* inst,
         int b = (xs >= real(0)) ? (int)xs : 0;
         c[k] = min(max(b, 0), I.n_grid - 3);
     }
-    keys[q] = ((uint32_t)lo << kp.cell_bits) | hilbert_index(c, D, kp.axis_bits);
+    uint32_t cell;
+    if (kp.curve == 1) {
+        cell = morton_index(c, D, kp.axis_bits);
+    } else if (kp.curve == 2) {
+        cell = (uint32_t)c[0] | ((uint32_t)c[1] << kp.axis_bits) | (D == 3 ? ((uint32_t)c[2] << (2 * kp.axis_bits)) : 0u);
+    } else {
+        cell = hilbert_index(c, D, kp.axis_bits);
+    }
+    keys[q] = ((uint32_t)lo << kp.cell_bits) | cell;
     vals[q] = (uint32_t)q;
 }
 
