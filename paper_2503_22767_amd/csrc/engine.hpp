@@ -19,13 +19,14 @@ namespace mpm {
 
 enum KernelId {
     K_SORT = 0, K_GATHER, K_P2G, K_GRID, K_G2P, K_LOSS, K_CKPT, K_SEED,
-    K_G2P_ADJ, K_GRID_ADJ, K_P2G_ADJ, K_OUT, K_COUNT
+    K_G2P_ADJ, K_GRID_ADJ, K_P2G_ADJ, K_OUT, K_ADJ_FUSED, K_COUNT
 };
 
 inline const char* kernel_name(int k)
 {
     static const char* names[K_COUNT] = {"sort", "gather", "p2g", "grid_update", "g2p", "loss", "checkpoint",
-                                         "seed", "g2p_adj", "grid_adj", "p2g_adj", "output"};
+                                         "seed", "g2p_adj", "grid_adj", "p2g_adj", "output",
+                                         "p2g_g2p_adj"};
     return (k >= 0 && k < K_COUNT) ? names[k] : "";
 }
 
@@ -194,6 +195,11 @@ public:
             return MPM_MAG_OK;
         }
         if (k == "kernel_timing") { timing_ = value != 0; return MPM_MAG_OK; }
+        if (k == "fuse_adj") {
+            fuse_adj_ = value != 0;
+            ++plan_gen_;   // changes the captured launch sequence
+            return MPM_MAG_OK;
+        }
         if (k == "p2g_lds") {
             use_lds_ = value != 0;
             ++plan_gen_;   // kernel arguments of captured launches
@@ -245,7 +251,7 @@ public:
         MPM_HIP(hipMemsetAsync(acc_, 0, sizeof(double) * kAccCount * n_inst_, s));
         MPM_HIP(hipMemsetAsync(gm_, 0, sizeof(real) * 4 * G_, s));
         MPM_HIP(hipMemsetAsync(reg_count_, 0, sizeof(int) * n_cb_, s));
-        MPM_HIP(hipMemsetAsync(active_, 0, sizeof(int) * 2, s));
+        MPM_HIP(hipMemsetAsync(active_, 0, sizeof(int) * 3, s));
         MPM_HIP(hipMemcpyAsync(bprog_, b_prog, sizeof(real) * S_tot_ * D, hipMemcpyDeviceToDevice, s));
         int st = sort_and_gather(s, (const real*)x0, (const real*)density, (const real*)br, (const real*)target, mask);
         if (st) return st;
@@ -288,7 +294,7 @@ public:
         MPM_HIP(hipMemsetAsync(err_d_, 0, sizeof(int), s));
         MPM_HIP(hipMemsetAsync(gB_, 0, sizeof(double) * S_tot_ * D, s));
         MPM_HIP(hipMemcpyAsync(dloss_, dloss, sizeof(real) * n_inst_, hipMemcpyDeviceToDevice, s));
-        MPM_HIP(hipMemsetAsync(active_, 0, sizeof(int) * 2, s));
+        MPM_HIP(hipMemsetAsync(active_, 0, sizeof(int) * 3, s));
         Args<real> a = args();
         int st = launch(K_SEED, s, n_chunks_, kBlock, k_seed<real, D>, a, (const real*)st_, adj_,
                         (const real*)x0s_, (const real*)tgt_, (const uint8_t*)mask_, (const real*)dloss_);
@@ -312,18 +318,34 @@ public:
                         if (r) return r;
                     }
                 }
-                // transpose of every step, last first
+                // transpose of every step, last first. The P2G transpose of
+                // step n runs fused with the G2P transpose of step n - 1; the
+                // scatter lists of consecutive steps alternate (1, 2).
+                auto lst = [](int n) { return 1 + (n & 1); };
+                r = launch(K_G2P_ADJ, cs, n_chunks_, kBlock, k_g2p_adj<real, D>, a, (const real*)gv_slot(s1 - 1 - s0),
+                           (const real*)seg_state(c, s1 - 1 - s0), adj_, (const real*)dloss_, lst(s1 - 1));
+                if (r) return r;
                 for (int n = s1 - 1; n >= s0; --n) {
                     const int j = n - s0;
-                    const real* sn = seg_state(c, j);
-                    r = launch(K_G2P_ADJ, cs, n_chunks_, kBlock, k_g2p_adj<real, D>, a, (const real*)gv_slot(j), sn, adj_,
-                                (const real*)dloss_);
-                    if (r) return r;
                     r = launch(K_GRID_ADJ, cs, grid_blocks(), kGridBlock, k_grid_adj<real, D>, a, (const real*)gm_slot(j),
-                                gpm_);
+                               gpm_, lst(n));
                     if (r) return r;
-                    r = launch(K_P2G_ADJ, cs, n_chunks_, kBlock, k_p2g_adj<real, D>, a, (const real*)gpm_, sn, adj_, n);
-                    if (r) return r;
+                    if (n > s0 && fuse_adj_) {
+                        r = launch(K_ADJ_FUSED, cs, n_chunks_, kBlock, k_adj_fused<real, D>, a, (const real*)gpm_,
+                                   (const real*)seg_state(c, j), n, (const real*)gv_slot(j - 1),
+                                   (const real*)seg_state(c, j - 1), adj_, (const real*)dloss_, lst(n), lst(n - 1));
+                        if (r) return r;
+                    } else {
+                        r = launch(K_P2G_ADJ, cs, n_chunks_, kBlock, k_p2g_adj<real, D>, a, (const real*)gpm_,
+                                   (const real*)seg_state(c, j), adj_, n, lst(n));
+                        if (r) return r;
+                        if (n > s0) {
+                            r = launch(K_G2P_ADJ, cs, n_chunks_, kBlock, k_g2p_adj<real, D>, a,
+                                       (const real*)gv_slot(j - 1), (const real*)seg_state(c, j - 1), adj_,
+                                       (const real*)dloss_, lst(n - 1));
+                            if (r) return r;
+                        }
+                    }
                 }
             }
             return MPM_MAG_OK;
@@ -409,6 +431,10 @@ private:
         case K_G2P_ADJ: return n * r * ((D + D * D) + (2 * D + 2 * D * D) + (D + D * D));
         case K_GRID_ADJ: return 0.0;
         case K_P2G_ADJ: return n * r * ((2 * D + 2 * D * D) + 1 + D + (2 * D + 2 * D * D) + (D + D * D) + 2 * (1 + D));
+        // P2G transpose of step n (state n, phi, br, G2P share of the adjoint,
+        // gradient read-modify-write) and G2P transpose of step n-1 (x, F of
+        // state n-1, store of its G2P share)
+        case K_ADJ_FUSED: return n * r * ((2 * D + 2 * D * D) + 1 + D + (D + D * D) + 2 * (1 + D) + (D + D * D) + (D + D * D));
         default: return 0.0;
         }
     }
@@ -634,8 +660,8 @@ private:
         st |= dalloc(&reg_count_, (size_t)n_cb_);
         st |= dalloc(&reg_list_, (size_t)n_cb_ * Coarse<D>::cap);
         st |= dalloc(&cb_inst_d_, (size_t)n_cb_);
-        st |= dalloc(&active_, 2);
-        st |= dalloc(&active_list_, (size_t)2 * n_cb_);
+        st |= dalloc(&active_, 3);
+        st |= dalloc(&active_list_, (size_t)3 * n_cb_);
         st |= dalloc(&gpm_, (size_t)4 * G_);
         st |= dalloc(&gm_, (size_t)4 * G_);
         st |= dalloc(&gv_, (size_t)4 * G_);
@@ -660,7 +686,7 @@ private:
                           hipMemcpyHostToDevice));
         MPM_HIP(hipMemcpy(cb_inst_d_, cb_inst_h_.data(), sizeof(int) * cb_inst_h_.size(), hipMemcpyHostToDevice));
         MPM_HIP(hipMemset(reg_count_, 0, sizeof(int) * n_cb_));
-        MPM_HIP(hipMemset(active_, 0, sizeof(int) * 2));
+        MPM_HIP(hipMemset(active_, 0, sizeof(int) * 3));
         MPM_HIP(hipMemset(gm_, 0, sizeof(real) * 4 * G_));
         MPM_HIP(hipMemset(gv_, 0, sizeof(real) * 4 * G_));
         MPM_HIP(hipMemset(gbar_, 0, sizeof(real) * 4 * G_));
@@ -744,6 +770,7 @@ private:
     // options
     bool graph_ = false, timing_ = false, use_lds_ = true;
     int box_cap_ = kBoxCap, grid_wgs_ = 2048;
+    bool fuse_adj_ = true;
     std::vector<hipEvent_t> events_;
     size_t ev_used_ = 0;
     // captured graphs: forward step loop (plain, recorded) and reverse sweep

@@ -87,8 +87,8 @@ struct Args {
     int* reg_count;      // [n_coarse] boxes registered with each coarse block this phase
     int* reg_list;       // [n_coarse][cap] chunk ids
     const int* cb_inst;  // [n_coarse] instance of each coarse block
-    int* active;         // [2]: coarse blocks activated in the scatter phases (P2G, G2P transpose)
-    int* active_list;    // [2][n_coarse]
+    int* active;         // [3]: coarse blocks activated in the scatter phases (P2G; G2P transpose, two lists)
+    int* active_list;    // [3][n_coarse]
     int n_coarse;
     int use_lds;
     int box_cap;         // largest block staging box (nodes, <= kBoxCap)
@@ -1219,50 +1219,50 @@ __global__ __launch_bounds__(kBlock) void k_seed(Args<real> a, const real* st, r
 // the G2P share of the adjoint of state n
 // --------------------------------------------------------------------------
 
+// adjoint of one particle's state (x, v, C, F)
 template <typename real, int D>
-__global__ __launch_bounds__(kBlock) void k_g2p_adj(Args<real> a, const real* __restrict__ gv_in, const real* st,
-                                                    real* adj, const real* dloss)
+struct AdjState {
+    real x[D], v[D], C[D][D], F[D][D];
+};
+
+template <typename real, int D>
+__device__ __forceinline__ void adj_zero(AdjState<real, D>& A)
+{
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+        A.x[r] = A.v[r] = real(0);
+#pragma unroll
+        for (int c = 0; c < D; ++c) A.C[r][c] = A.F[r][c] = real(0);
+    }
+}
+
+// Transpose of the G2P of step n for the particles of this block: from the
+// adjoint A1 of state n+1 (registers) and state n (st), scatter the grid
+// velocity adjoint (list `list` of the scatter phases) and store the G2P share
+// of the adjoint of state n (x and F parts) in adj. lds: 4 kBoxCap words.
+template <typename real, int D>
+__device__ __forceinline__ void g2p_adj_phase(const Args<real>& a, const InstDev<real>& I, int inst, bool active,
+                                              int64_t i, const real* __restrict__ gv_in, const real* st,
+                                              AdjState<real, D>& A1, real* adj, const real* dloss, int list,
+                                              typename LdsAcc<real>::T* lds)
 {
     using Cp = Comp<D>;
-    __shared__ typename LdsAcc<real>::T lds[4 * kBoxCap];
-    const ChunkDev ch = a.chunks[blockIdx.x];
-    const InstDev<real>& I = a.inst[ch.inst];
-    const int t = threadIdx.x;
-    const bool active = t < ch.count;
-    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
     const int64_t S = a.nalloc;
-    if (blockIdx.x == 0 && t == 0) a.active[0] = 0;   // the grid update has consumed the P2G list
-    real x[D], F[D][D], xb1[D], vb1[D], Cb1[D][D], Fb1[D][D];
+    real x[D], F[D][D];
     if (active) {
         load_xF<real, D>(st, a.x0s, S, i, x, F);
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            xb1[k] = adj[(Cp::X + k) * S + i];
-            vb1[k] = adj[(Cp::V + k) * S + i];
-        }
-#pragma unroll
-        for (int r = 0; r < D; ++r)
-#pragma unroll
-            for (int c = 0; c < D; ++c) {
-                Cb1[r][c] = adj[(Cp::C + r * D + c) * S + i];
-                Fb1[r][c] = adj[(Cp::F + r * D + c) * S + i];
-            }
         if (I.loss_kind == kTrajVel) {
-            const double M = a.acc[ch.inst * kAccCount + kAccMass];
-            const double sc = -(double)dloss[ch.inst] * (double)I.dt * (double)a.phi[i] * (double)I.mass_p / M;
+            const double M = a.acc[inst * kAccCount + kAccMass];
+            const double sc = -(double)dloss[inst] * (double)I.dt * (double)a.phi[i] * (double)I.mass_p / M;
 #pragma unroll
-            for (int k = 0; k < D; ++k) vb1[k] += (real)(sc * (double)I.loss_dir[k]);
+            for (int k = 0; k < D; ++k) A1.v[k] += (real)(sc * (double)I.loss_dir[k]);
         }
     } else {
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             x[k] = real(0.5);
-            xb1[k] = vb1[k] = real(0);
 #pragma unroll
-            for (int c = 0; c < D; ++c) {
-                F[k][c] = k == c ? real(1) : real(0);
-                Cb1[k][c] = Fb1[k][c] = real(0);
-            }
+            for (int c = 0; c < D; ++c) F[k][c] = k == c ? real(1) : real(0);
         }
     }
     int org[3];
@@ -1278,13 +1278,13 @@ __global__ __launch_bounds__(kBlock) void k_g2p_adj(Args<real> a, const real* __
     real Cbt[D][D], vbt[D], xb[D];
 #pragma unroll
     for (int r = 0; r < D; ++r) {
-        vbt[r] = vb1[r] + I.dt * xb1[r];
-        xb[r] = xb1[r];
+        vbt[r] = A1.v[r] + I.dt * A1.x[r];
+        xb[r] = A1.x[r];
 #pragma unroll
         for (int c = 0; c < D; ++c) {
-            real u = Cb1[r][c];
+            real u = A1.C[r][c];
 #pragma unroll
-            for (int k = 0; k < D; ++k) u += I.dt * Fb1[r][k] * F[c][k];
+            for (int k = 0; k < D; ++k) u += I.dt * A1.F[r][k] * F[c][k];
             Cbt[r][c] = u;
         }
     }
@@ -1333,9 +1333,9 @@ __global__ __launch_bounds__(kBlock) void k_g2p_adj(Args<real> a, const real* __
     for (int r = 0; r < D; ++r)
 #pragma unroll
         for (int c = 0; c < D; ++c) {
-            real s = Fb1[r][c];
+            real s = A1.F[r][c];
 #pragma unroll
-            for (int k = 0; k < D; ++k) s += I.dt * lam * Bm[k][r] * Fb1[k][c];
+            for (int k = 0; k < D; ++k) s += I.dt * lam * Bm[k][r] * A1.F[k][c];
             Fb[r][c] = s;
         }
     // scatter w u_i to the grid velocity adjoint (registers only)
@@ -1347,7 +1347,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p_adj(Args<real> a, const real* __
         for (int c = 0; c < D; ++c) s += lam * fabs(Cbt[r][c]) * real(1.5) * dx;
         bnd[r] = s;
     }
-    scatter_box<real, D, D>(a, I, lds, active, Sx.base, bnd, a.gbar, 1,
+    scatter_box<real, D, D>(a, I, lds, active, Sx.base, bnd, a.gbar, list,
         [&](const int o[D], const real sq[D], real& w, real u[D]) {
             real dpos[D];
             w = node_weight_outer<real, D>(Sx, o, dx, dpos);
@@ -1369,17 +1369,49 @@ __global__ __launch_bounds__(kBlock) void k_g2p_adj(Args<real> a, const real* __
     }
 }
 
+template <typename real, int D>
+__global__ __launch_bounds__(kBlock) void k_g2p_adj(Args<real> a, const real* __restrict__ gv_in, const real* st,
+                                                    real* adj, const real* dloss, int list)
+{
+    using Cp = Comp<D>;
+    __shared__ typename LdsAcc<real>::T lds[4 * kBoxCap];
+    const ChunkDev ch = a.chunks[blockIdx.x];
+    const InstDev<real>& I = a.inst[ch.inst];
+    const int t = threadIdx.x;
+    const bool active = t < ch.count;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+    const int64_t S = a.nalloc;
+    if (blockIdx.x == 0 && t == 0) a.active[0] = 0;   // the grid update has consumed the P2G list
+    AdjState<real, D> A1;
+    adj_zero(A1);
+    if (active) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            A1.x[k] = adj[(Cp::X + k) * S + i];
+            A1.v[k] = adj[(Cp::V + k) * S + i];
+        }
+#pragma unroll
+        for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                A1.C[r][c] = adj[(Cp::C + r * D + c) * S + i];
+                A1.F[r][c] = adj[(Cp::F + r * D + c) * S + i];
+            }
+    }
+    g2p_adj_phase<real, D>(a, I, ch.inst, active, i, gv_in, st, A1, adj, dloss, list, lds);
+}
+
 // --------------------------------------------------------------------------
 // grid transpose: vbar -> (pbar, mbar), in place in gbar; clears gm
 // --------------------------------------------------------------------------
 
 template <typename real, int D>
 __global__ __launch_bounds__(kGridBlock) void k_grid_adj(Args<real> a, const real* __restrict__ gmd_in,
-                                                         real* __restrict__ gpm_out)
+                                                         real* __restrict__ gpm_out, int list)
 {
-  const int n_act = a.active[1];
+  const int n_act = a.active[list];
   for (int ai = blockIdx.x; ai < n_act; ai += gridDim.x) {
-    const int b = a.active_list[a.n_coarse + ai];
+    const int b = a.active_list[list * a.n_coarse + ai];
     const InstDev<real>& I = a.inst[a.cb_inst[b]];
     gather_coarse<real, D>(a, I, b, a.gbar, [&](int64_t g, const int g3[3], const real vb[4]) {
         real node[4];
@@ -1444,24 +1476,23 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_adj(Args<real> a, const rea
 // P2G transpose: gather (pbar, mbar) -> adjoint of state n and design
 // --------------------------------------------------------------------------
 
+// Transpose of the P2G of step n for the particles of this block: gather
+// (pbar, mbar) of the grid transpose, accumulate the design gradients, and
+// return the full adjoint A0 of state n (the G2P share of its x and F parts is
+// read from adj). lds: 4 kBoxCap words.
 template <typename real, int D>
-__global__ __launch_bounds__(kBlock, sizeof(real) == 4 ? 3 : 2) void k_p2g_adj(Args<real> a, const real* __restrict__ gpm_in, const real* st,
-                                                    real* adj, int step)
+__device__ __forceinline__ void p2g_adj_phase(const Args<real>& a, const InstDev<real>& I, int inst, bool active,
+                                              int64_t i, const real* __restrict__ gpm_in, const real* st,
+                                              const real* adj, int step, AdjState<real, D>& A0, real* lds)
 {
     using Cp = Comp<D>;
-    const ChunkDev ch = a.chunks[blockIdx.x];
-    const InstDev<real>& I = a.inst[ch.inst];
     const int t = threadIdx.x;
-    const bool active = t < ch.count;
-    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
     const int64_t S = a.nalloc;
-    if (blockIdx.x == 0 && t == 0) a.active[1] = 0;   // the grid transpose has consumed the G2P-transpose list
     real B[D];
     field_at<real, D>(I, a.bprog, step, B);
     double gBl[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) gBl[k] = 0.0;
-    __shared__ real lds[4 * kBoxCap];
     Particle<real, D> q;
     real phi = 0, br[D];
     int org[3];
@@ -1575,16 +1606,18 @@ __global__ __launch_bounds__(kBlock, sizeof(real) == 4 ? 3 : 2) void k_p2g_adj(A
         // adjoint of state n: x and F add to the G2P share, v and C are set
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            adj[(Cp::X + k) * S + i] += xb[k];
-            adj[(Cp::V + k) * S + i] = vb[k];
+            A0.x[k] = adj[(Cp::X + k) * S + i] + xb[k];
+            A0.v[k] = vb[k];
         }
 #pragma unroll
         for (int r = 0; r < D; ++r)
 #pragma unroll
             for (int c = 0; c < D; ++c) {
-                adj[(Cp::C + r * D + c) * S + i] = T.m * Ab[r][c];
-                adj[(Cp::F + r * D + c) * S + i] += Fbp[r][c] + T.se * dP[r][c];
+                A0.C[r][c] = T.m * Ab[r][c];
+                A0.F[r][c] = adj[(Cp::F + r * D + c) * S + i] + Fbp[r][c] + T.se * dP[r][c];
             }
+    } else {
+        adj_zero(A0);
     }
     block_sum<D>(gBl);
     if (t == 0) {
@@ -1592,6 +1625,59 @@ __global__ __launch_bounds__(kBlock, sizeof(real) == 4 ? 3 : 2) void k_p2g_adj(A
 #pragma unroll
         for (int k = 0; k < D; ++k) unsafeAtomicAdd(&a.gB[(int64_t)(I.seg_off + seg) * D + k], gBl[k]);
     }
+}
+
+template <typename real, int D>
+__global__ __launch_bounds__(kBlock, sizeof(real) == 4 ? 3 : 2) void k_p2g_adj(Args<real> a, const real* __restrict__ gpm_in,
+                                                                             const real* st, real* adj, int step,
+                                                                             int list_done)
+{
+    using Cp = Comp<D>;
+    __shared__ real lds[4 * kBoxCap];
+    const ChunkDev ch = a.chunks[blockIdx.x];
+    const InstDev<real>& I = a.inst[ch.inst];
+    const int t = threadIdx.x;
+    const bool active = t < ch.count;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+    const int64_t S = a.nalloc;
+    if (blockIdx.x == 0 && t == 0) a.active[list_done] = 0;   // the grid transpose has consumed this list
+    AdjState<real, D> A0;
+    p2g_adj_phase<real, D>(a, I, ch.inst, active, i, gpm_in, st, adj, step, A0, lds);
+    if (active) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            adj[(Cp::X + k) * S + i] = A0.x[k];
+            adj[(Cp::V + k) * S + i] = A0.v[k];
+        }
+#pragma unroll
+        for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                adj[(Cp::C + r * D + c) * S + i] = A0.C[r][c];
+                adj[(Cp::F + r * D + c) * S + i] = A0.F[r][c];
+            }
+    }
+}
+
+// Transposes of P2G at step n and of G2P at step n - 1 in one pass: the
+// adjoint of state n stays in registers between them. Resets the scatter list
+// the grid transpose of step n consumed and fills the other one for step n - 1.
+template <typename real, int D>
+__global__ __launch_bounds__(kBlock, sizeof(real) == 4 ? 3 : 2) void k_adj_fused(
+    Args<real> a, const real* __restrict__ gpm_in, const real* st_n, int step, const real* __restrict__ gv_prev,
+    const real* st_prev, real* adj, const real* dloss, int list_done, int list_next)
+{
+    __shared__ typename LdsAcc<real>::T lds[4 * kBoxCap];
+    const ChunkDev ch = a.chunks[blockIdx.x];
+    const InstDev<real>& I = a.inst[ch.inst];
+    const int t = threadIdx.x;
+    const bool active = t < ch.count;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+    if (blockIdx.x == 0 && t == 0) a.active[list_done] = 0;
+    AdjState<real, D> A;
+    p2g_adj_phase<real, D>(a, I, ch.inst, active, i, gpm_in, st_n, adj, step, A, reinterpret_cast<real*>(lds));
+    __syncthreads();   // the LDS node box of the gather is reused below
+    g2p_adj_phase<real, D>(a, I, ch.inst, active, i, gv_prev, st_prev, A, adj, dloss, list_next, lds);
 }
 
 // --------------------------------------------------------------------------
