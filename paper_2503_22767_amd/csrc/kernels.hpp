@@ -1292,39 +1292,51 @@ __device__ __forceinline__ void g2p_adj_phase(const Args<real>& a, const InstDev
     // one gather pass: C' of the forward G2P, and the share of xbar through the
     // weights and dpos, which needs the grid velocity:
     // xb += (v_i . u_i) grad w - lam w Cbt^T v_i,  u_i = vbt + lam Cbt dpos_i
-    real Bm[D][D];
+    // (the last term summed as lam Cbt^T V after the loop, V = sum w v_i)
+    real Bm[D][D], V[D];
 #pragma unroll
-    for (int r = 0; r < D; ++r)
+    for (int r = 0; r < D; ++r) {
+        V[r] = 0;
 #pragma unroll
         for (int c = 0; c < D; ++c) Bm[r][c] = 0;
+    }
     if (active) {
-#pragma unroll 3
-        for (int o = 0; o < Cp::S3; ++o) {
-            int oa[D];
-            offset_split<D>(o, oa);
-            real dpos[D], gw[D];
-            real w = node_weight<real, D>(Sx, oa, dx, dpos);
-            node_grad<real, D>(Sx, oa, gw);
-            real vi[D];
-            load_vec<real, D>(node_rec<real, D>(nbx, glds, gv, Sx.base, oa, I.n_grid), vi);
-            real vu = 0;
+#pragma unroll 1
+        for (int a2 = 0; a2 < (D == 3 ? 3 : 1); ++a2)
+#pragma unroll 1
+            for (int a1 = 0; a1 < 3; ++a1)
 #pragma unroll
-            for (int r = 0; r < D; ++r) {
-                real cd = 0;
+                for (int a0 = 0; a0 < 3; ++a0) {
+                    int oa[D];
+                    oa[0] = a0;
+                    oa[1] = a1;
+                    if (D == 3) oa[D - 1] = a2;
+                    real dpos[D], gw[D];
+                    const real w = node_weight<real, D>(Sx, oa, dx, dpos);
+                    node_grad<real, D>(Sx, oa, gw);
+                    real vi[D];
+                    load_vec<real, D>(node_rec<real, D>(nbx, glds, gv, Sx.base, oa, I.n_grid), vi);
+                    real vu = 0;
 #pragma unroll
-                for (int c = 0; c < D; ++c) {
-                    Bm[r][c] += w * vi[r] * dpos[c];
-                    cd += Cbt[r][c] * dpos[c];
+                    for (int r = 0; r < D; ++r) {
+                        real cd = 0;
+#pragma unroll
+                        for (int c = 0; c < D; ++c) cd += Cbt[r][c] * dpos[c];
+                        vu += vi[r] * (vbt[r] + lam * cd);
+                        const real wv = w * vi[r];
+                        V[r] += wv;
+#pragma unroll
+                        for (int c = 0; c < D; ++c) Bm[r][c] += wv * dpos[c];
+                    }
+#pragma unroll
+                    for (int k = 0; k < D; ++k) xb[k] += vu * gw[k];
                 }
-                vu += vi[r] * (vbt[r] + lam * cd);
-            }
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-                real ctv = 0;
+        for (int k = 0; k < D; ++k) {
+            real ctv = 0;
 #pragma unroll
-                for (int r = 0; r < D; ++r) ctv += Cbt[r][k] * vi[r];
-                xb[k] += vu * gw[k] - lam * w * ctv;
-            }
+            for (int r = 0; r < D; ++r) ctv += Cbt[r][k] * V[r];
+            xb[k] -= lam * ctv;
         }
     }
     // F' = (I + dt C') F  ->  Fb = (I + dt C')^T Fb'
@@ -1513,50 +1525,63 @@ __device__ __forceinline__ void p2g_adj_phase(const Args<real>& a, const InstDev
     if (active) {
         P2GTerms<real, D> T;
         p2g_terms<real, D>(I, q, phi, br, B, T);
-        real mb = 0, vb[D], Ab[D][D], xb[D];
+        // Sums over the stencil; the terms linear in a per-particle factor are
+        // summed first and multiplied once after the loop:
+        //   mb = sum w mbar_i + v . S0 + Ab : C,  vb = m S0,  xb -= A^T S0,
+        //   S0 = sum w pbar_i,  Ab = sum w pbar_i dpos_i^T
+        real smb = 0, S0[D], Ab[D][D], xb[D], mv[D];
 #pragma unroll
         for (int r = 0; r < D; ++r) {
-            vb[r] = 0;
+            S0[r] = 0;
             xb[r] = 0;
+            mv[r] = T.m * q.v[r];
 #pragma unroll
             for (int c = 0; c < D; ++c) Ab[r][c] = 0;
         }
-#pragma unroll 3
-        for (int o = 0; o < Cp::S3; ++o) {
-            int oa[D];
-            offset_split<D>(o, oa);
-            real dpos[D], gw[D];
-            real w = node_weight<real, D>(Sx, oa, I.dx, dpos);
-            node_grad<real, D>(Sx, oa, gw);
-            const real* nd = node_rec<real, D>(nbx, lds, gsrc, Sx.base, oa, I.n_grid);
-            real pb[D];
-            load_vec<real, D>(nd, pb);
-            real mbi = nd[3];
-            real pv = 0, pmom = 0;
-            real Atp[D];
+#pragma unroll 1
+        for (int a2 = 0; a2 < (D == 3 ? 3 : 1); ++a2)
+#pragma unroll 1
+            for (int a1 = 0; a1 < 3; ++a1)
 #pragma unroll
-            for (int r = 0; r < D; ++r) {
-                real ad = 0;
-                Atp[r] = 0;
+                for (int a0 = 0; a0 < 3; ++a0) {
+                    int oa[D];
+                    oa[0] = a0;
+                    oa[1] = a1;
+                    if (D == 3) oa[D - 1] = a2;
+                    real dpos[D], gw[D];
+                    const real w = node_weight<real, D>(Sx, oa, I.dx, dpos);
+                    node_grad<real, D>(Sx, oa, gw);
+                    const real* nd = node_rec<real, D>(nbx, lds, gsrc, Sx.base, oa, I.n_grid);
+                    real pb[D];
+                    load_vec<real, D>(nd, pb);
+                    const real mbi = nd[3];
+                    real pmom = 0;
 #pragma unroll
-                for (int c = 0; c < D; ++c) {
-                    ad += T.A[r][c] * dpos[c];
-                    Atp[r] += T.A[c][r] * pb[c];
+                    for (int r = 0; r < D; ++r) {
+                        real ad = mv[r];
+#pragma unroll
+                        for (int c = 0; c < D; ++c) ad += T.A[r][c] * dpos[c];
+                        pmom += pb[r] * ad;
+                    }
+                    const real coef = mbi * T.m + pmom;
+                    smb += w * mbi;
+#pragma unroll
+                    for (int r = 0; r < D; ++r) {
+                        const real wp = w * pb[r];
+                        S0[r] += wp;
+                        xb[r] += coef * gw[r];
+#pragma unroll
+                        for (int c = 0; c < D; ++c) Ab[r][c] += wp * dpos[c];
+                    }
                 }
-                pv += pb[r] * q.v[r];
-                pmom += pb[r] * (T.m * q.v[r] + ad);
-            }
-            mb += w * (mbi + pv);
-            real coef = mbi * T.m + pmom;
+        real mb = smb + ddot<real, D>(Ab, q.C), vb[D];
 #pragma unroll
-            for (int r = 0; r < D; ++r) {
-                vb[r] += w * T.m * pb[r];
-                xb[r] += coef * gw[r] - w * Atp[r];
+        for (int r = 0; r < D; ++r) {
+            mb += q.v[r] * S0[r];
+            vb[r] = T.m * S0[r];
 #pragma unroll
-                for (int c = 0; c < D; ++c) Ab[r][c] += w * pb[r] * dpos[c];
-            }
+            for (int c = 0; c < D; ++c) xb[r] -= T.A[c][r] * S0[c];
         }
-        mb += ddot<real, D>(Ab, q.C);
         // Recompute the stress here rather than keeping it live through the
         // gather loop (the empty asm hides F's value so the compiler does not
         // reuse the copy from before the loop); this halves register pressure.
