@@ -151,6 +151,9 @@ const char* mpm_mag_last_error(const mpm_mag* h);
  *   "box_cap"       largest per-block staging box in grid nodes, 64..1024 (default 1024);
  *                   larger boxes are staged per wave or fall back to global atomics
  *   "grid_wgs"      workgroups of the grid kernels, 16..2^20 (default 2048)
+ *   "fuse_fwd"      1: G2P of step n and P2G of step n+1 in one kernel (default), 0: separate
+ *   "fuse_adj"      1: P2G transpose of step n and G2P transpose of step n-1 in one
+ *                   kernel (default), 0: separate
  *   "ckpt_every"    checkpoint spacing K (0: automatic); takes effect at the next recorded rollout
  * Returns EINVAL for an unknown key or value.
  */

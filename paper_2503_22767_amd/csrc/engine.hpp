@@ -19,14 +19,14 @@ namespace mpm {
 
 enum KernelId {
     K_SORT = 0, K_GATHER, K_P2G, K_GRID, K_G2P, K_LOSS, K_CKPT, K_SEED,
-    K_G2P_ADJ, K_GRID_ADJ, K_P2G_ADJ, K_OUT, K_ADJ_FUSED, K_COUNT
+    K_G2P_ADJ, K_GRID_ADJ, K_P2G_ADJ, K_OUT, K_ADJ_FUSED, K_G2P2G, K_COUNT
 };
 
 inline const char* kernel_name(int k)
 {
     static const char* names[K_COUNT] = {"sort", "gather", "p2g", "grid_update", "g2p", "loss", "checkpoint",
                                          "seed", "g2p_adj", "grid_adj", "p2g_adj", "output",
-                                         "p2g_g2p_adj"};
+                                         "p2g_g2p_adj", "g2p_p2g"};
     return (k >= 0 && k < K_COUNT) ? names[k] : "";
 }
 
@@ -195,6 +195,11 @@ public:
             return MPM_MAG_OK;
         }
         if (k == "kernel_timing") { timing_ = value != 0; return MPM_MAG_OK; }
+        if (k == "fuse_fwd") {
+            fuse_fwd_ = value != 0;
+            ++plan_gen_;
+            return MPM_MAG_OK;
+        }
         if (k == "fuse_adj") {
             fuse_adj_ = value != 0;
             ++plan_gen_;   // changes the captured launch sequence
@@ -251,18 +256,41 @@ public:
         MPM_HIP(hipMemsetAsync(acc_, 0, sizeof(double) * kAccCount * n_inst_, s));
         MPM_HIP(hipMemsetAsync(gm_, 0, sizeof(real) * 4 * G_, s));
         MPM_HIP(hipMemsetAsync(reg_count_, 0, sizeof(int) * n_cb_, s));
-        MPM_HIP(hipMemsetAsync(active_, 0, sizeof(int) * 3, s));
+        MPM_HIP(hipMemsetAsync(active_, 0, sizeof(int) * 4, s));
         MPM_HIP(hipMemcpyAsync(bprog_, b_prog, sizeof(real) * S_tot_ * D, hipMemcpyDeviceToDevice, s));
         int st = sort_and_gather(s, (const real*)x0, (const real*)density, (const real*)br, (const real*)target, mask);
         if (st) return st;
         auto steps = [&](hipStream_t cs) -> int {
+            Args<real> a = args();
             for (int n = 0; n < T_; ++n) {
-                if (record && n % K_ == 0) {
-                    MPM_HIP(hipMemcpyAsync(ckpt_slot(n / K_), st_, state_bytes(), hipMemcpyDeviceToDevice, cs));
-                    count(K_CKPT, 2.0 * state_bytes());
+                const bool ck = record && n % K_ == 0;
+                if (n == 0 || !fuse_fwd_) {
+                    if (ck) {
+                        MPM_HIP(hipMemcpyAsync(ckpt_slot(n / K_), st_, state_bytes(), hipMemcpyDeviceToDevice, cs));
+                        count(K_CKPT, 2.0 * state_bytes());
+                    }
+                    int r = launch(K_P2G, cs, n_chunks_, kBlock, k_p2g<real, D>, a, (const real*)st_, n, lf(n));
+                    if (r) return r;
                 }
-                int r = step(cs, n, st_, st_, true);
+                int r = launch(K_GRID, cs, grid_blocks(), kGridBlock, k_grid<real, D>, a, gv_, (real*)nullptr, lf(n));
                 if (r) return r;
+                if (n + 1 < T_ && fuse_fwd_) {
+                    // G2P of step n with P2G of step n + 1; v and C are stored
+                    // only for the checkpoint taken before step n + 1
+                    const bool ck1 = record && (n + 1) % K_ == 0;
+                    r = launch(K_G2P2G, cs, n_chunks_, kBlock, k_g2p2g<real, D>, a, (const real*)gv_, (const real*)st_,
+                               st_, n, 1, ck1 ? 1 : 0, lf(n), lf(n + 1));
+                    if (r) return r;
+                    if (ck1) {
+                        MPM_HIP(hipMemcpyAsync(ckpt_slot((n + 1) / K_), st_, state_bytes(), hipMemcpyDeviceToDevice,
+                                               cs));
+                        count(K_CKPT, 2.0 * state_bytes());
+                    }
+                } else {
+                    r = launch(K_G2P, cs, n_chunks_, kBlock, k_g2p<real, D>, a, (const real*)gv_, (const real*)st_, st_,
+                               n, 1, lf(n));
+                    if (r) return r;
+                }
             }
             return MPM_MAG_OK;
         };
@@ -294,7 +322,7 @@ public:
         MPM_HIP(hipMemsetAsync(err_d_, 0, sizeof(int), s));
         MPM_HIP(hipMemsetAsync(gB_, 0, sizeof(double) * S_tot_ * D, s));
         MPM_HIP(hipMemcpyAsync(dloss_, dloss, sizeof(real) * n_inst_, hipMemcpyDeviceToDevice, s));
-        MPM_HIP(hipMemsetAsync(active_, 0, sizeof(int) * 3, s));
+        MPM_HIP(hipMemsetAsync(active_, 0, sizeof(int) * 4, s));
         Args<real> a = args();
         int st = launch(K_SEED, s, n_chunks_, kBlock, k_seed<real, D>, a, (const real*)st_, adj_,
                         (const real*)x0s_, (const real*)tgt_, (const uint8_t*)mask_, (const real*)dloss_);
@@ -308,13 +336,20 @@ public:
                 // the active coarse blocks are written)
                 for (int n = s0; n < s1; ++n) {
                     const int j = n - s0;
-                    r = launch(K_P2G, cs, n_chunks_, kBlock, k_p2g<real, D>, a, (const real*)seg_state(c, j), n);
-                    if (r) return r;
-                    r = launch(K_GRID, cs, grid_blocks(), kGridBlock, k_grid<real, D>, a, gv_slot(j), gm_slot(j));
+                    if (n == s0 || !fuse_fwd_) {
+                        r = launch(K_P2G, cs, n_chunks_, kBlock, k_p2g<real, D>, a, (const real*)seg_state(c, j), n,
+                                   lf(n));
+                        if (r) return r;
+                    }
+                    r = launch(K_GRID, cs, grid_blocks(), kGridBlock, k_grid<real, D>, a, gv_slot(j), gm_slot(j), lf(n));
                     if (r) return r;
                     if (n + 1 < s1) {
-                        r = launch(K_G2P, cs, n_chunks_, kBlock, k_g2p<real, D>, a, (const real*)gv_slot(j),
-                                    (const real*)seg_state(c, j), seg_state(c, j + 1), n, 0);
+                        if (fuse_fwd_)
+                            r = launch(K_G2P2G, cs, n_chunks_, kBlock, k_g2p2g<real, D>, a, (const real*)gv_slot(j),
+                                       (const real*)seg_state(c, j), seg_state(c, j + 1), n, 0, 1, lf(n), lf(n + 1));
+                        else
+                            r = launch(K_G2P, cs, n_chunks_, kBlock, k_g2p<real, D>, a, (const real*)gv_slot(j),
+                                       (const real*)seg_state(c, j), seg_state(c, j + 1), n, 0, lf(n));
                         if (r) return r;
                     }
                 }
@@ -323,7 +358,7 @@ public:
                 // scatter lists of consecutive steps alternate (1, 2).
                 auto lst = [](int n) { return 1 + (n & 1); };
                 r = launch(K_G2P_ADJ, cs, n_chunks_, kBlock, k_g2p_adj<real, D>, a, (const real*)gv_slot(s1 - 1 - s0),
-                           (const real*)seg_state(c, s1 - 1 - s0), adj_, (const real*)dloss_, lst(s1 - 1));
+                           (const real*)seg_state(c, s1 - 1 - s0), adj_, (const real*)dloss_, lst(s1 - 1), lf(s1 - 1));
                 if (r) return r;
                 for (int n = s1 - 1; n >= s0; --n) {
                     const int j = n - s0;
@@ -342,7 +377,7 @@ public:
                         if (n > s0) {
                             r = launch(K_G2P_ADJ, cs, n_chunks_, kBlock, k_g2p_adj<real, D>, a,
                                        (const real*)gv_slot(j - 1), (const real*)seg_state(c, j - 1), adj_,
-                                       (const real*)dloss_, lst(n - 1));
+                                       (const real*)dloss_, lst(n - 1), lf(s1 - 1));
                             if (r) return r;
                         }
                     }
@@ -434,6 +469,9 @@ private:
         // P2G transpose of step n (state n, phi, br, G2P share of the adjoint,
         // gradient read-modify-write) and G2P transpose of step n-1 (x, F of
         // state n-1, store of its G2P share)
+        // G2P of step n with P2G of step n+1: read x, F, phi, br; write x, F
+        // (v and C only at checkpoints and in the segment recompute, not priced)
+        case K_G2P2G: return n * r * (2 * (D + D * D) + 1 + D);
         case K_ADJ_FUSED: return n * r * ((2 * D + 2 * D * D) + 1 + D + (D + D * D) + 2 * (1 + D) + (D + D * D) + (D + D * D));
         default: return 0.0;
         }
@@ -540,17 +578,9 @@ private:
         return MPM_MAG_OK;
     }
 
-    // one forward step n: P2G, grid operation, G2P (sin -> sout)
-    int step(hipStream_t s, int n, real* sin, real* sout, bool traj)
-    {
-        Args<real> a = args();
-        int st = launch(K_P2G, s, n_chunks_, kBlock, k_p2g<real, D>, a, (const real*)sin, n);
-        if (st) return st;
-        st = launch(K_GRID, s, grid_blocks(), kGridBlock, k_grid<real, D>, a, gv_, (real*)nullptr);
-        if (st) return st;
-        return launch(K_G2P, s, n_chunks_, kBlock, k_g2p<real, D>, a, (const real*)gv_, (const real*)sin, sout, n,
-                      traj ? 1 : 0);
-    }
+    // scatter list of the forward P2G of step n (alternating, so a fused
+    // G2P + P2G pass can reset the list its grid update consumed)
+    static int lf(int n) { return (n & 1) ? 3 : 0; }
 
     int sort_and_gather(hipStream_t s, const real* x0, const real* phi, const real* br, const real* tgt,
                         const uint8_t* mask)
@@ -660,8 +690,8 @@ private:
         st |= dalloc(&reg_count_, (size_t)n_cb_);
         st |= dalloc(&reg_list_, (size_t)n_cb_ * Coarse<D>::cap);
         st |= dalloc(&cb_inst_d_, (size_t)n_cb_);
-        st |= dalloc(&active_, 3);
-        st |= dalloc(&active_list_, (size_t)3 * n_cb_);
+        st |= dalloc(&active_, 4);
+        st |= dalloc(&active_list_, (size_t)4 * n_cb_);
         st |= dalloc(&gpm_, (size_t)4 * G_);
         st |= dalloc(&gm_, (size_t)4 * G_);
         st |= dalloc(&gv_, (size_t)4 * G_);
@@ -686,7 +716,7 @@ private:
                           hipMemcpyHostToDevice));
         MPM_HIP(hipMemcpy(cb_inst_d_, cb_inst_h_.data(), sizeof(int) * cb_inst_h_.size(), hipMemcpyHostToDevice));
         MPM_HIP(hipMemset(reg_count_, 0, sizeof(int) * n_cb_));
-        MPM_HIP(hipMemset(active_, 0, sizeof(int) * 3));
+        MPM_HIP(hipMemset(active_, 0, sizeof(int) * 4));
         MPM_HIP(hipMemset(gm_, 0, sizeof(real) * 4 * G_));
         MPM_HIP(hipMemset(gv_, 0, sizeof(real) * 4 * G_));
         MPM_HIP(hipMemset(gbar_, 0, sizeof(real) * 4 * G_));
@@ -770,7 +800,7 @@ private:
     // options
     bool graph_ = false, timing_ = false, use_lds_ = true;
     int box_cap_ = kBoxCap, grid_wgs_ = 2048;
-    bool fuse_adj_ = true;
+    bool fuse_adj_ = true, fuse_fwd_ = true;
     std::vector<hipEvent_t> events_;
     size_t ev_used_ = 0;
     // captured graphs: forward step loop (plain, recorded) and reverse sweep

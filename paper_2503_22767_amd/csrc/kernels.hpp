@@ -87,8 +87,8 @@ struct Args {
     int* reg_count;      // [n_coarse] boxes registered with each coarse block this phase
     int* reg_list;       // [n_coarse][cap] chunk ids
     const int* cb_inst;  // [n_coarse] instance of each coarse block
-    int* active;         // [3]: coarse blocks activated in the scatter phases (P2G; G2P transpose, two lists)
-    int* active_list;    // [3][n_coarse]
+    int* active;         // [4]: coarse blocks activated per scatter list (P2G: 0, 3; G2P transpose: 1, 2)
+    int* active_list;    // [4][n_coarse]
     int n_coarse;
     int use_lds;
     int box_cap;         // largest block staging box (nodes, <= kBoxCap)
@@ -829,35 +829,24 @@ __device__ __forceinline__ void node_grad(const Stencil<real, D>& S, const int a
 // P2G (Eqs. 14-15)
 // --------------------------------------------------------------------------
 
+// P2G (Eqs. 14-15) of this block's particles from their state in registers
+// (positions relative to the chunk origin): stress, affine momentum, and the
+// scatter of (p, m) into staging list `list`. Inactive lanes carry a neutral
+// state (zero mass).
 template <typename real, int D>
-__global__ __launch_bounds__(kBlock) void k_p2g(Args<real> a, const real* __restrict__ st, int step)
+__device__ __forceinline__ void p2g_scatter(const Args<real>& a, const InstDev<real>& I, bool active, int64_t i,
+                                            const Particle<real, D>& q, int step, int list,
+                                            typename LdsAcc<real>::T* lds)
 {
-    __shared__ typename LdsAcc<real>::T lds[4 * kBoxCap];
-    const ChunkDev ch = a.chunks[blockIdx.x];
-    const InstDev<real>& I = a.inst[ch.inst];
-    const int t = threadIdx.x;
-    const bool active = t < ch.count;
-    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
     const int64_t S = a.nalloc;
-    Particle<real, D> q;
     real phi = 0, br[D];
     if (active) {
-        load_particle<real, D>(st, a.x0s, S, i, q);
         phi = a.phi[i];
 #pragma unroll
         for (int k = 0; k < D; ++k) br[k] = a.br[k * S + i];
     } else {
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-            q.x[k] = real(0.5);
-            q.v[k] = real(0);
-            br[k] = real(0);
-#pragma unroll
-            for (int b = 0; b < D; ++b) {
-                q.C[k][b] = real(0);
-                q.F[k][b] = k == b ? real(1) : real(0);
-            }
-        }
+        for (int k = 0; k < D; ++k) br[k] = real(0);
     }
     real B[D];
     field_at<real, D>(I, a.bprog, step, B);
@@ -882,7 +871,7 @@ __global__ __launch_bounds__(kBlock) void k_p2g(Args<real> a, const real* __rest
         bnd[r] = s;
     }
     bnd[D] = T.m;
-    scatter_box<real, D, D + 1>(a, I, lds, active, Sx.base, bnd, a.gm, 0,
+    scatter_box<real, D, D + 1>(a, I, lds, active, Sx.base, bnd, a.gm, list,
         [&](const int o[D], const real sq[D + 1], real& w, real u[D + 1]) {
             real dpos[D];
             w = node_weight_outer<real, D>(Sx, o, dx, dpos);
@@ -895,6 +884,38 @@ __global__ __launch_bounds__(kBlock) void k_p2g(Args<real> a, const real* __rest
             }
             u[D] = T.m * sq[D];
         });
+}
+
+template <typename real, int D>
+__device__ __forceinline__ void neutral_particle(Particle<real, D>& q)
+{
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        q.x[k] = real(0.5);
+        q.v[k] = real(0);
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            q.C[k][b] = real(0);
+            q.F[k][b] = k == b ? real(1) : real(0);
+        }
+    }
+}
+
+template <typename real, int D>
+__global__ __launch_bounds__(kBlock) void k_p2g(Args<real> a, const real* __restrict__ st, int step, int list)
+{
+    __shared__ typename LdsAcc<real>::T lds[4 * kBoxCap];
+    const ChunkDev ch = a.chunks[blockIdx.x];
+    const InstDev<real>& I = a.inst[ch.inst];
+    const int t = threadIdx.x;
+    const bool active = t < ch.count;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+    Particle<real, D> q;
+    if (active)
+        load_particle<real, D>(st, a.x0s, a.nalloc, i, q);
+    else
+        neutral_particle(q);
+    p2g_scatter<real, D>(a, I, active, i, q, step, list, lds);
 }
 
 // --------------------------------------------------------------------------
@@ -971,11 +992,11 @@ __device__ __forceinline__ int node_velocity(const InstDev<real>& I, const int i
 // is given (reverse sweep) the summed (momentum, mass) records are kept there
 // for the grid transpose.
 template <typename real, int D>
-__global__ __launch_bounds__(kGridBlock) void k_grid(Args<real> a, real* gv_out, real* gmd_out)
+__global__ __launch_bounds__(kGridBlock) void k_grid(Args<real> a, real* gv_out, real* gmd_out, int list)
 {
-  const int n_act = a.active[0];
+  const int n_act = a.active[list];
   for (int ai = blockIdx.x; ai < n_act; ai += gridDim.x) {
-    const int b = a.active_list[ai];
+    const int b = a.active_list[list * a.n_coarse + ai];
     const InstDev<real>& I = a.inst[a.cb_inst[b]];
     gather_coarse<real, D>(a, I, b, a.gm, [&](int64_t g, const int g3[3], const real node[4]) {
         real v[D];
@@ -1004,102 +1025,169 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Args<real> a, real* gv_out,
 // G2P (Eqs. 19-22)
 // --------------------------------------------------------------------------
 
+// G2P (Eqs. 19-22) of one active particle: gather the grid velocity at its
+// stencil, update v, C, F and the displacement (stored in q.x); x1 gets the
+// new position relative to the chunk origin. Returns the error flags.
+template <typename real, int D>
+__device__ __forceinline__ int g2p_update(const Args<real>& a, const InstDev<real>& I, int64_t i,
+                                          const real* __restrict__ gv_in, const real* sin, const int org[3],
+                                          Particle<real, D>& q, real x1[D])
+{
+    const int64_t S = a.nalloc;
+    real x[D], F[D][D], u[D];
+    load_xF<real, D>(sin, a.x0s, S, i, x, F);
+#pragma unroll
+    for (int k = 0; k < D; ++k) u[k] = sin[(Comp<D>::X + k) * S + i];
+    Stencil<real, D> Sx;
+    make_stencil<real, D>(x, org, I.inv_dx, I.n_grid, Sx);
+    const real* gv = gv_in + 4 * (int64_t)I.grid_off;
+    real vn[D], Bm[D][D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+        vn[r] = 0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) Bm[r][c] = 0;
+    }
+    for (int o = 0; o < Comp<D>::S3; ++o) {
+        int oa[D];
+        offset_split<D>(o, oa);
+        real dpos[D];
+        real w = node_weight<real, D>(Sx, oa, I.dx, dpos);
+        real vi[D];
+        load_vec<real, D>(gv + 4 * node_index<real, D>(Sx.base, oa, I.n_grid), vi);
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            real wv = w * vi[r];
+            vn[r] += wv;
+#pragma unroll
+            for (int c = 0; c < D; ++c) Bm[r][c] += wv * dpos[c];
+        }
+    }
+    real IdC[D][D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+        q.v[r] = vn[r];
+        q.x[r] = u[r] + I.dt * vn[r];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            q.C[r][c] = I.lam * Bm[r][c];
+            IdC[r][c] = (r == c ? real(1) : real(0)) + I.dt * q.C[r][c];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            real s = 0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) s += IdC[r][k] * F[k][c];
+            q.F[r][c] = s;
+        }
+#pragma unroll
+    for (int r = 0; r < D; ++r) x1[r] = a.x0s[r * S + i] + q.x[r];
+    int err = 0;
+    bool fin = true;
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+        fin = fin && rfinite(q.x[r]) && rfinite(q.v[r]);
+#pragma unroll
+        for (int c = 0; c < D; ++c) fin = fin && rfinite(q.F[r][c]) && rfinite(q.C[r][c]);
+    }
+    if (!fin) {
+        err |= kErrNonFinite;
+    } else {
+        if (!(det<real, D>(q.F) > real(0))) err |= kErrInvert;
+        Stencil<real, D> S1;
+        err |= make_stencil<real, D>(x1, org, I.inv_dx, I.n_grid, S1);
+    }
+    return err;
+}
+
+// mass-weighted velocity along the loss direction (trajectory loss, Eq. 39),
+// summed over the block into the instance accumulator
+template <typename real, int D>
+__device__ __forceinline__ void traj_accumulate(const Args<real>& a, const InstDev<real>& I, int inst, bool active,
+                                                int64_t i, const Particle<real, D>& q)
+{
+    double traj = 0.0;
+    if (active) {
+        real ve = 0;
+#pragma unroll
+        for (int r = 0; r < D; ++r) ve += I.loss_dir[r] * q.v[r];
+        traj = (double)(a.phi[i] * I.mass_p) * (double)ve;
+    }
+    double v1[1] = {traj};
+    block_sum<1>(v1);
+    if (threadIdx.x == 0) unsafeAtomicAdd(&a.acc[inst * kAccCount + kAccTraj], v1[0]);
+}
+
 template <typename real, int D>
 __global__ __launch_bounds__(kBlock) void k_g2p(Args<real> a, const real* __restrict__ gv_in, const real* sin,
-                                                real* sout, int step, int traj_on)
+                                                real* sout, int step, int traj_on, int list_done)
 {
     const ChunkDev ch = a.chunks[blockIdx.x];
     const InstDev<real>& I = a.inst[ch.inst];
     const int t = threadIdx.x;
     const bool active = t < ch.count;
     const int64_t i = (int64_t)blockIdx.x * kBlock + t;
-    const int64_t S = a.nalloc;
-    if (blockIdx.x == 0 && t == 0) a.active[0] = 0;   // the grid update has consumed the P2G list
-    double traj = 0.0;
+    if (blockIdx.x == 0 && t == 0) a.active[list_done] = 0;   // the grid update has consumed this list
+    Particle<real, D> q;
     if (active) {
-        real x[D], F[D][D], u[D];
-        load_xF<real, D>(sin, a.x0s, S, i, x, F);
-#pragma unroll
-        for (int k = 0; k < D; ++k) u[k] = sin[(Comp<D>::X + k) * S + i];
         int org[3];
         chunk_origin(a.corig, blockIdx.x, org);
-        Stencil<real, D> Sx;
-        make_stencil<real, D>(x, org, I.inv_dx, I.n_grid, Sx);
-        const real* gv = gv_in + 4 * (int64_t)I.grid_off;
-        real vn[D], Bm[D][D];
+        real x1[D];
+        const int err = g2p_update<real, D>(a, I, i, gv_in, sin, org, q, x1);
+        if (err) atomicOr(a.err, err);
+        store_particle<real, D>(sout, a.nalloc, i, q);
+    }
+    if (traj_on && I.loss_kind == kTrajVel) traj_accumulate<real, D>(a, I, ch.inst, active, i, q);
+}
+
+// G2P of step n and P2G of step n + 1 in one pass: the new state stays in
+// registers for the scatter. x and F are always stored; v and C only when a
+// later pass reads them (checkpoints, stashed states).
+template <typename real, int D>
+__global__ __launch_bounds__(kBlock) void k_g2p2g(Args<real> a, const real* __restrict__ gv_in, const real* sin,
+                                                  real* sout, int step, int traj_on, int store_vc, int list_done,
+                                                  int list_next)
+{
+    using Cp = Comp<D>;
+    __shared__ typename LdsAcc<real>::T lds[4 * kBoxCap];
+    const ChunkDev ch = a.chunks[blockIdx.x];
+    const InstDev<real>& I = a.inst[ch.inst];
+    const int t = threadIdx.x;
+    const bool active = t < ch.count;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+    const int64_t S = a.nalloc;
+    if (blockIdx.x == 0 && t == 0) a.active[list_done] = 0;
+    Particle<real, D> q;
+    if (active) {
+        int org[3];
+        chunk_origin(a.corig, blockIdx.x, org);
+        real x1[D];
+        const int err = g2p_update<real, D>(a, I, i, gv_in, sin, org, q, x1);
+        if (err) atomicOr(a.err, err);
 #pragma unroll
         for (int r = 0; r < D; ++r) {
-            vn[r] = 0;
+            sout[(Cp::X + r) * S + i] = q.x[r];
 #pragma unroll
-            for (int c = 0; c < D; ++c) Bm[r][c] = 0;
+            for (int c = 0; c < D; ++c) sout[(Cp::F + r * D + c) * S + i] = q.F[r][c];
         }
-        for (int o = 0; o < Comp<D>::S3; ++o) {
-            int oa[D];
-            offset_split<D>(o, oa);
-            real dpos[D];
-            real w = node_weight<real, D>(Sx, oa, I.dx, dpos);
-            real vi[D];
-            load_vec<real, D>(gv + 4 * node_index<real, D>(Sx.base, oa, I.n_grid), vi);
+        if (store_vc) {
 #pragma unroll
             for (int r = 0; r < D; ++r) {
-                real wv = w * vi[r];
-                vn[r] += wv;
+                sout[(Cp::V + r) * S + i] = q.v[r];
 #pragma unroll
-                for (int c = 0; c < D; ++c) Bm[r][c] += wv * dpos[c];
-            }
-        }
-        Particle<real, D> q;
-        real IdC[D][D];
-#pragma unroll
-        for (int r = 0; r < D; ++r) {
-            q.v[r] = vn[r];
-            q.x[r] = u[r] + I.dt * vn[r];
-#pragma unroll
-            for (int c = 0; c < D; ++c) {
-                q.C[r][c] = I.lam * Bm[r][c];
-                IdC[r][c] = (r == c ? real(1) : real(0)) + I.dt * q.C[r][c];
+                for (int c = 0; c < D; ++c) sout[(Cp::C + r * D + c) * S + i] = q.C[r][c];
             }
         }
 #pragma unroll
-        for (int r = 0; r < D; ++r)
-#pragma unroll
-            for (int c = 0; c < D; ++c) {
-                real s = 0;
-#pragma unroll
-                for (int k = 0; k < D; ++k) s += IdC[r][k] * F[k][c];
-                q.F[r][c] = s;
-            }
-        int err = 0;
-        bool fin = true;
-#pragma unroll
-        for (int r = 0; r < D; ++r) {
-            fin = fin && rfinite(q.x[r]) && rfinite(q.v[r]);
-#pragma unroll
-            for (int c = 0; c < D; ++c) fin = fin && rfinite(q.F[r][c]) && rfinite(q.C[r][c]);
-        }
-        if (!fin) err |= kErrNonFinite;
-        else {
-            if (!(det<real, D>(q.F) > real(0))) err |= kErrInvert;
-            real x1[D];
-#pragma unroll
-            for (int r = 0; r < D; ++r) x1[r] = a.x0s[r * S + i] + q.x[r];
-            Stencil<real, D> S1;
-            err |= make_stencil<real, D>(x1, org, I.inv_dx, I.n_grid, S1);
-        }
-        if (err) atomicOr(a.err, err);
-        store_particle<real, D>(sout, S, i, q);
-        if (traj_on && I.loss_kind == kTrajVel) {
-            real ve = 0;
-#pragma unroll
-            for (int r = 0; r < D; ++r) ve += I.loss_dir[r] * q.v[r];
-            traj = (double)(a.phi[i] * I.mass_p) * (double)ve;
-        }
+        for (int r = 0; r < D; ++r) q.x[r] = x1[r];
+    } else {
+        neutral_particle(q);
     }
-    if (traj_on && I.loss_kind == kTrajVel) {
-        double v1[1] = {traj};
-        block_sum<1>(v1);
-        if (t == 0) unsafeAtomicAdd(&a.acc[ch.inst * kAccCount + kAccTraj], v1[0]);
-    }
+    if (traj_on && I.loss_kind == kTrajVel) traj_accumulate<real, D>(a, I, ch.inst, active, i, q);
+    p2g_scatter<real, D>(a, I, active, i, q, step + 1, list_next, lds);
 }
 
 // --------------------------------------------------------------------------
@@ -1383,7 +1471,7 @@ __device__ __forceinline__ void g2p_adj_phase(const Args<real>& a, const InstDev
 
 template <typename real, int D>
 __global__ __launch_bounds__(kBlock) void k_g2p_adj(Args<real> a, const real* __restrict__ gv_in, const real* st,
-                                                    real* adj, const real* dloss, int list)
+                                                    real* adj, const real* dloss, int list, int list_fwd_done)
 {
     using Cp = Comp<D>;
     __shared__ typename LdsAcc<real>::T lds[4 * kBoxCap];
@@ -1393,7 +1481,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p_adj(Args<real> a, const real* __
     const bool active = t < ch.count;
     const int64_t i = (int64_t)blockIdx.x * kBlock + t;
     const int64_t S = a.nalloc;
-    if (blockIdx.x == 0 && t == 0) a.active[0] = 0;   // the grid update has consumed the P2G list
+    if (blockIdx.x == 0 && t == 0) a.active[list_fwd_done] = 0;   // the grid update has consumed this P2G list
     AdjState<real, D> A1;
     adj_zero(A1);
     if (active) {
