@@ -163,6 +163,8 @@ def main():
     ap.add_argument("--option", action="append", default=[], help="library option key=value")
     ap.add_argument("--autotune", action="store_true",
                     help="pick launch options with the autotuner (cached) before timing")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first copy a MIB-sized device buffer (reference kernel for HBM byte counters)")
     ap.add_argument("--compare-separate", action="store_true",
                     help="also time one handle per instance (default for the batched workload)")
     args = ap.parse_args()
@@ -174,6 +176,15 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: 3 copies of {args.copy_probe} MiB")
+        del src, dst
     kw = {"n_steps": args.n_steps} if args.n_steps else {}
     wl = W.make(args.workload, **kw)
     opts = {}

@@ -54,14 +54,18 @@ template <> __device__ __forceinline__ double rfloor<double>(double v) { return 
 
 template <typename real> __device__ __forceinline__ bool rfinite(real v) { return isfinite(v); }
 
-// J^{-2/3}
-template <typename real> __device__ __forceinline__ real jpow_m23(real J);
-template <> __device__ __forceinline__ float jpow_m23<float>(float J) { return powf(J, -2.0f / 3.0f); }
-template <> __device__ __forceinline__ double jpow_m23<double>(double J) { return pow(J, -2.0 / 3.0); }
-
+// Powers for J^{-2/3} and the SIMP factors. In single precision a^b is taken
+// as 2^(b log2 a) with the hardware base-2 logarithm and exponential (about one
+// ulp each; J and phi stay near [0.1, 10]); double precision uses pow.
 template <typename real> __device__ __forceinline__ real rpow(real a, real b);
-template <> __device__ __forceinline__ float rpow<float>(float a, float b) { return powf(a, b); }
+template <> __device__ __forceinline__ float rpow<float>(float a, float b)
+{
+    return __builtin_amdgcn_exp2f(b * __builtin_amdgcn_logf(a));
+}
 template <> __device__ __forceinline__ double rpow<double>(double a, double b) { return pow(a, b); }
+
+// J^{-2/3}
+template <typename real> __device__ __forceinline__ real jpow_m23(real J) { return rpow<real>(J, real(-2) / real(3)); }
 
 // phi^q and q phi^(q-1), with the common q = 3 spelled out
 template <typename real>
@@ -279,18 +283,35 @@ __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
+// Reductions over the 64 lanes of a wave with DPP moves (pairs, quads, half
+// rows, rows, then row broadcasts 15 and 31), result read from lane 63 and
+// returned to every lane. Every lane must take part.
+template <typename Op>
+__device__ __forceinline__ int wave_reduce(int v, Op op)
+{
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));    // quad_perm [1,0,3,2]
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));    // quad_perm [2,3,0,1]
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));   // row_half_mirror
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));   // row_mirror
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));   // row_bcast:15 into rows 1, 3
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));   // row_bcast:31 into rows 2, 3
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
 __device__ __forceinline__ int wave_min(int v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
-    return v;
+    return wave_reduce(v, [](int a, int b) { return min(a, b); });
 }
 
 __device__ __forceinline__ int wave_max(int v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
-    return v;
+    return wave_reduce(v, [](int a, int b) { return max(a, b); });
+}
+
+// maximum of non-negative floats (their bit patterns order like the values)
+__device__ __forceinline__ float wave_max_nonneg(float v)
+{
+    return __int_as_float(wave_max(__float_as_int(v)));
 }
 
 // origin cell of chunk c (particle positions are stored relative to it)

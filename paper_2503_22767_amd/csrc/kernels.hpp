@@ -113,7 +113,7 @@ __device__ __forceinline__ int64_t box_offset(int id) { return (int64_t)(id / kW
 // the dense accumulator fb instead.
 template <typename real, int D>
 __device__ __forceinline__ void register_box(const Args<real>& a, const InstDev<real>& I, int id, const int lo[3],
-                                             const int ext[3], const typename LdsAcc<real>::T* box_lds, int box_cap,
+                                             const int ext[3], const typename LdsAcc<real>::T* box_lds,
                                              const real inv[4], bool staged, real* fb, int phase, int lane0,
                                              int stride)
 {
@@ -148,7 +148,7 @@ __device__ __forceinline__ void register_box(const Args<real>& a, const InstDev<
                                     (int64_t)I.n_grid * ((lo[1] + y) + (D == 3 ? (int64_t)I.n_grid * (lo[D - 1] + z) : 0));
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
-                            real v = LdsAcc<real>::dec(box_lds[q * box_cap + l], inv[q]);
+                            real v = LdsAcc<real>::dec(box_lds[4 * l + q], inv[q]);
                             if (v != real(0)) atomic_add(&fb[4 * g + q], v);
                         }
                     }
@@ -245,10 +245,7 @@ __device__ __forceinline__ void scatter_box(const Args<real>& a, const InstDev<r
     float bmax[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-        float v = active ? (float)fabs(bound[q]) : 0.0f;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-        bmax[q] = v;
+        bmax[q] = wave_max_nonneg(active ? (float)fabs(bound[q]) : 0.0f);
     }
     if ((t & 63) == 0) {
 #pragma unroll
@@ -301,18 +298,17 @@ __device__ __forceinline__ void scatter_box(const Args<real>& a, const InstDev<r
         blo[k] = block_mode ? lo[k] : wlo[k];
         bext[k] = block_mode ? ext[k] : wext[k];
     }
-    const int bcap = block_mode ? kBoxCap : kWaveBoxCap;
     acc_t* blds = block_mode ? lds : lds + w * 4 * kWaveBoxCap;
     const int id = c * kWaves + (block_mode ? 0 : w);
     // zero the staging boxes
     if (block_mode) {
         for (int i = t; i < vol; i += kBlock)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) blds[q * bcap + i] = acc_t(0);
+            for (int q = 0; q < 4; ++q) blds[4 * i + q] = acc_t(0);
     } else if (staged) {
         for (int i = t & 63; i < wvol; i += 64)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) blds[q * bcap + i] = acc_t(0);
+            for (int q = 0; q < 4; ++q) blds[4 * i + q] = acc_t(0);
     }
     __syncthreads();
     // segments of lanes sharing a stencil base within each 16-lane row
@@ -357,22 +353,22 @@ __device__ __forceinline__ void scatter_box(const Args<real>& a, const InstDev<r
             const int li = lrel + oa[0] + bext[0] * (oa[1] + (D == 3 ? bext[1] * oa[D - 1] : 0));
             if constexpr (sizeof(acc_t) == 4) {
                 row_prefix_sums<NV>(e);
-                acc_t pm[NV];
+                acc_t pm[NV];   // minus the prefix of the lane before
 #pragma unroll
-                for (int q = 0; q < NV; ++q) pm[q] = dpp_shr(e[q], 1);
+                for (int q = 0; q < NV; ++q) pm[q] = (int)(0u - (unsigned)dpp_shr(e[q], 1));
                 if (emit) {
 #pragma unroll
-                    for (int q = 0; q < NV; ++q) atomicAdd(&blds[value_slot<D, NV>(q) * bcap + li], e[q]);
+                    for (int q = 0; q < NV; ++q) atomicAdd(&blds[4 * li + value_slot<D, NV>(q)], e[q]);
                 }
                 if (head_sub) {
 #pragma unroll
-                    for (int q = 0; q < NV; ++q) atomicSub(&blds[value_slot<D, NV>(q) * bcap + li], pm[q]);
+                    for (int q = 0; q < NV; ++q) atomicAdd(&blds[4 * li + value_slot<D, NV>(q)], pm[q]);
                 }
             } else {
                 seg_row_sums<NV>(e, msk);
                 if (emit) {
 #pragma unroll
-                    for (int q = 0; q < NV; ++q) atomicAdd(&blds[value_slot<D, NV>(q) * bcap + li], e[q]);
+                    for (int q = 0; q < NV; ++q) atomicAdd(&blds[4 * li + value_slot<D, NV>(q)], e[q]);
                 }
             }
         }
@@ -396,11 +392,11 @@ __device__ __forceinline__ void scatter_box(const Args<real>& a, const InstDev<r
     if (block_mode) {
         for (int l = t; l < vol; l += kBlock)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) dst[4 * l + q] = Acc::dec(blds[q * bcap + l], inv[q]);
+            for (int q = 0; q < 4; ++q) dst[4 * l + q] = Acc::dec(blds[4 * l + q], inv[q]);
     } else if (staged) {
         for (int l = t & 63; l < wvol; l += 64)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) dst[4 * l + q] = Acc::dec(blds[q * bcap + l], inv[q]);
+            for (int q = 0; q < 4; ++q) dst[4 * l + q] = Acc::dec(blds[4 * l + q], inv[q]);
     }
     // one writer per descriptor: thread t < kWaves in block mode, lane 0 of each wave otherwise
     if (block_mode ? (t < kWaves) : ((t & 63) == 0)) {
@@ -417,9 +413,9 @@ __device__ __forceinline__ void scatter_box(const Args<real>& a, const InstDev<r
     // register the boxes (also the ranges of waves that fell back, so the
     // grid update visits their coarse blocks)
     if (block_mode) {
-        register_box<real, D>(a, I, id, lo, ext, blds, bcap, inv, true, fb, phase, t, kBlock);
+        register_box<real, D>(a, I, id, lo, ext, blds, inv, true, fb, phase, t, kBlock);
     } else if (wave_live) {
-        register_box<real, D>(a, I, id, wlo, wext, blds, bcap, inv, staged, fb, phase, t & 63, 64);
+        register_box<real, D>(a, I, id, wlo, wext, blds, inv, staged, fb, phase, t & 63, 64);
     }
 }
 
@@ -606,14 +602,31 @@ __device__ __forceinline__ NodeBox<D> stage_nodes(const InstDev<real>& I, bool a
     }
     nb.staged = vol > 0 && vol <= cap;
     if (nb.staged) {
+        // walk l = t, t + kBlock, ... keeping its box coordinates (x, y, z)
+        // up to date with carries instead of dividing every step
+        const int e0 = nb.ext[0], e1 = D == 3 ? nb.ext[1] : 1 << 30;
+        int x = t % e0, r = t / e0;
+        int y = D == 3 ? r % e1 : r, z = D == 3 ? r / e1 : 0;
+        const int sx = kBlock % e0, sr = kBlock / e0;
+        const int sy = D == 3 ? sr % e1 : sr, sz = D == 3 ? sr / e1 : 0;
         for (int l = t; l < vol; l += kBlock) {
-            int x = l % nb.ext[0], r = l / nb.ext[0];
-            int y = D == 3 ? r % nb.ext[1] : r;
-            int z = D == 3 ? r / nb.ext[1] : 0;
             int64_t g = (int64_t)(nb.lo[0] + x) +
                         (int64_t)I.n_grid * ((nb.lo[1] + y) + (D == 3 ? (int64_t)I.n_grid * (nb.lo[D - 1] + z) : 0));
 #pragma unroll
             for (int q = 0; q < 4; ++q) lds[4 * l + q] = src[4 * g + q];
+            x += sx;
+            y += sy;
+            if (x >= e0) {
+                x -= e0;
+                ++y;
+            }
+            if (D == 3) {
+                z += sz;
+                if (y >= e1) {
+                    y -= e1;
+                    ++z;
+                }
+            }
         }
     }
     __syncthreads();
@@ -632,6 +645,8 @@ __device__ __forceinline__ const real* node_rec(const NodeBox<D>& nb, const real
     }
     return src + 4 * ((int64_t)(base[0] + a[0]) + (int64_t)n * ((base[1] + a[1]) + (D == 3 ? (int64_t)n * (base[D - 1] + a[D - 1]) : 0)));
 }
+
+__device__ constexpr int kZero3[3] = {0, 0, 0};
 
 template <typename real, int D>
 __device__ __forceinline__ int64_t node_index(const int base[D], const int a[D], int n)
@@ -1040,7 +1055,9 @@ __device__ __forceinline__ int g2p_update(const Args<real>& a, const InstDev<rea
     for (int k = 0; k < D; ++k) u[k] = sin[(Comp<D>::X + k) * S + i];
     Stencil<real, D> Sx;
     make_stencil<real, D>(x, org, I.inv_dx, I.n_grid, Sx);
-    const real* gv = gv_in + 4 * (int64_t)I.grid_off;
+    // the stencil's first node; the others are at small 32-bit offsets
+    const int n = I.n_grid;
+    const real* g0 = gv_in + 4 * ((int64_t)I.grid_off + node_index<real, D>(Sx.base, kZero3, n));
     real vn[D], Bm[D][D];
 #pragma unroll
     for (int r = 0; r < D; ++r) {
@@ -1048,13 +1065,14 @@ __device__ __forceinline__ int g2p_update(const Args<real>& a, const InstDev<rea
 #pragma unroll
         for (int c = 0; c < D; ++c) Bm[r][c] = 0;
     }
+#pragma unroll
     for (int o = 0; o < Comp<D>::S3; ++o) {
         int oa[D];
         offset_split<D>(o, oa);
         real dpos[D];
         real w = node_weight<real, D>(Sx, oa, I.dx, dpos);
         real vi[D];
-        load_vec<real, D>(gv + 4 * node_index<real, D>(Sx.base, oa, I.n_grid), vi);
+        load_vec<real, D>(g0 + 4 * (oa[0] + n * (oa[1] + (D == 3 ? n * oa[D - 1] : 0))), vi);
 #pragma unroll
         for (int r = 0; r < D; ++r) {
             real wv = w * vi[r];
@@ -1147,7 +1165,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(Args<real> a, const real* __rest
 // registers for the scatter. x and F are always stored; v and C only when a
 // later pass reads them (checkpoints, stashed states).
 template <typename real, int D>
-__global__ __launch_bounds__(kBlock) void k_g2p2g(Args<real> a, const real* __restrict__ gv_in, const real* sin,
+__global__ __launch_bounds__(kBlock, 5) void k_g2p2g(Args<real> a, const real* __restrict__ gv_in, const real* sin,
                                                   real* sout, int step, int traj_on, int store_vc, int list_done,
                                                   int list_next)
 {
@@ -1776,7 +1794,7 @@ __global__ __launch_bounds__(kBlock, sizeof(real) == 4 ? 3 : 2) void k_p2g_adj(A
 // adjoint of state n stays in registers between them. Resets the scatter list
 // the grid transpose of step n consumed and fills the other one for step n - 1.
 template <typename real, int D>
-__global__ __launch_bounds__(kBlock, sizeof(real) == 4 ? 3 : 2) void k_adj_fused(
+__global__ __launch_bounds__(kBlock, sizeof(real) == 4 ? 4 : 2) void k_adj_fused(
     Args<real> a, const real* __restrict__ gpm_in, const real* st_n, int step, const real* __restrict__ gv_prev,
     const real* st_prev, real* adj, const real* dloss, int list_done, int list_next)
 {

@@ -23,7 +23,8 @@ from typing import Optional, Sequence
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmpm_mag.so")
+# the in-tree build; MPM_MAG_LIB may name another build of the same library
+LIB_PATH = os.environ.get("MPM_MAG_LIB") or os.path.join(HERE, "libmpm_mag.so")
 
 OK, EINVAL, ENOMEM, EHIP, EDOMAIN, EINVERT, ENONFINITE, ESTATE = range(8)
 
