@@ -11,7 +11,7 @@ namespace mpm {
 
 constexpr int kBlock = 256;       // threads per particle block = particles per chunk
 constexpr int kWaves = kBlock / 64;
-constexpr int kGridBlock = 256;   // nodes per grid block
+constexpr int kGridBlock = 512;   // threads of the grid kernels (and grid padding unit)
 
 // device error word bits
 constexpr int kErrDomain = 1;

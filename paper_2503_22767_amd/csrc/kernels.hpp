@@ -473,7 +473,7 @@ __device__ __forceinline__ void gather_coarse(const Args<real>& a, const InstDev
     __syncthreads();
     // inclusive scan of s_off[1..cnt] (cnt <= blockDim.x): wave scans, then wave totals
     {
-        __shared__ int s_wsum[kWaves];
+        __shared__ int s_wsum[kGridBlock / 64];
         const int lane = t & 63, wv = t >> 6;
         int v = (t < cnt) ? s_off[t + 1] : 0;
 #pragma unroll
@@ -1065,20 +1065,25 @@ __device__ __forceinline__ int g2p_update(const Args<real>& a, const InstDev<rea
 #pragma unroll
         for (int c = 0; c < D; ++c) Bm[r][c] = 0;
     }
+    // all 3^D nodes unrolled; dpos per axis is one of three values
+    real d0[3];
+#pragma unroll
+    for (int a0 = 0; a0 < 3; ++a0) d0[a0] = (real(a0) - Sx.f[0]) * I.dx;
 #pragma unroll
     for (int o = 0; o < Comp<D>::S3; ++o) {
-        int oa[D];
-        offset_split<D>(o, oa);
-        real dpos[D];
-        real w = node_weight<real, D>(Sx, oa, I.dx, dpos);
+        const int a0 = o % 3, a1 = (o / 3) % 3, a2 = o / 9;
+        const real d1 = (real(a1) - Sx.f[1]) * I.dx;
+        const real d2 = D == 3 ? (real(a2) - Sx.f[D - 1]) * I.dx : real(0);
+        const real w = Sx.w[0][a0] * Sx.w[1][a1] * (D == 3 ? Sx.w[D - 1][a2] : real(1));
         real vi[D];
-        load_vec<real, D>(g0 + 4 * (oa[0] + n * (oa[1] + (D == 3 ? n * oa[D - 1] : 0))), vi);
+        load_vec<real, D>(g0 + 4 * (a0 + n * (a1 + (D == 3 ? n * a2 : 0))), vi);
 #pragma unroll
         for (int r = 0; r < D; ++r) {
-            real wv = w * vi[r];
+            const real wv = w * vi[r];
             vn[r] += wv;
-#pragma unroll
-            for (int c = 0; c < D; ++c) Bm[r][c] += wv * dpos[c];
+            Bm[r][0] += wv * d0[a0];
+            Bm[r][1] += wv * d1;
+            if (D == 3) Bm[r][D - 1] += wv * d2;
         }
     }
     real IdC[D][D];
@@ -1407,36 +1412,67 @@ __device__ __forceinline__ void g2p_adj_phase(const Args<real>& a, const InstDev
         for (int c = 0; c < D; ++c) Bm[r][c] = 0;
     }
     if (active) {
+        // lam Cbt, and dpos_x of the three x offsets
+        real lC[D][D], d0[3];
+#pragma unroll
+        for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int c = 0; c < D; ++c) lC[r][c] = lam * Cbt[r][c];
+#pragma unroll
+        for (int a0 = 0; a0 < 3; ++a0) d0[a0] = (real(a0) - Sx.f[0]) * dx;
 #pragma unroll 1
         for (int a2 = 0; a2 < (D == 3 ? 3 : 1); ++a2)
 #pragma unroll 1
-            for (int a1 = 0; a1 < 3; ++a1)
+            for (int a1 = 0; a1 < 3; ++a1) {
+                const real d1 = (real(a1) - Sx.f[1]) * dx;
+                const real d2 = D == 3 ? (real(a2) - Sx.f[D - 1]) * dx : real(0);
+                const real wz = D == 3 ? sel3(Sx.w[D - 1], a2) : real(1);
+                const real dwz = D == 3 ? sel3(Sx.dw[D - 1], a2) : real(0);
+                const real wy = sel3(Sx.w[1], a1), dwy = sel3(Sx.dw[1], a1);
+                const real wyz = wy * wz, dwyz = dwy * wz, wydz = wy * dwz;
+                real h[D];   // u_i = vbt + lam Cbt dpos_i without its x term
+#pragma unroll
+                for (int r = 0; r < D; ++r) {
+                    real u = vbt[r];
+                    if (D == 3) u += lC[r][D - 1] * d2;
+                    h[r] = u + lC[r][1] * d1;
+                }
+                real U[D], W[D];   // row sums of w v_i and of w dpos_x v_i
+#pragma unroll
+                for (int r = 0; r < D; ++r) U[r] = W[r] = real(0);
 #pragma unroll
                 for (int a0 = 0; a0 < 3; ++a0) {
                     int oa[D];
                     oa[0] = a0;
                     oa[1] = a1;
                     if (D == 3) oa[D - 1] = a2;
-                    real dpos[D], gw[D];
-                    const real w = node_weight<real, D>(Sx, oa, dx, dpos);
-                    node_grad<real, D>(Sx, oa, gw);
+                    const real wx = Sx.w[0][a0], dwx = Sx.dw[0][a0];
+                    const real w = wx * wyz;
+                    real gw[D];
+                    gw[0] = dwx * wyz;
+                    gw[1] = wx * dwyz;
+                    if (D == 3) gw[D - 1] = wx * wydz;
                     real vi[D];
                     load_vec<real, D>(node_rec<real, D>(nbx, glds, gv, Sx.base, oa, I.n_grid), vi);
                     real vu = 0;
 #pragma unroll
+                    for (int r = 0; r < D; ++r) vu += vi[r] * (h[r] + lC[r][0] * d0[a0]);
+                    const real wd = w * d0[a0];
+#pragma unroll
                     for (int r = 0; r < D; ++r) {
-                        real cd = 0;
-#pragma unroll
-                        for (int c = 0; c < D; ++c) cd += Cbt[r][c] * dpos[c];
-                        vu += vi[r] * (vbt[r] + lam * cd);
-                        const real wv = w * vi[r];
-                        V[r] += wv;
-#pragma unroll
-                        for (int c = 0; c < D; ++c) Bm[r][c] += wv * dpos[c];
+                        xb[r] += vu * gw[r];
+                        U[r] += w * vi[r];
+                        W[r] += wd * vi[r];
                     }
-#pragma unroll
-                    for (int k = 0; k < D; ++k) xb[k] += vu * gw[k];
                 }
+#pragma unroll
+                for (int r = 0; r < D; ++r) {
+                    V[r] += U[r];
+                    Bm[r][0] += W[r];
+                    Bm[r][1] += d1 * U[r];
+                    if (D == 3) Bm[r][D - 1] += d2 * U[r];
+                }
+            }
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             real ctv = 0;
@@ -1644,42 +1680,68 @@ __device__ __forceinline__ void p2g_adj_phase(const Args<real>& a, const InstDev
 #pragma unroll
             for (int c = 0; c < D; ++c) Ab[r][c] = 0;
         }
+        // outer (z, y) offsets run-time, x offsets unrolled; sums over the
+        // three x nodes of a row are combined once per row
+        real d0[3];
+#pragma unroll
+        for (int a0 = 0; a0 < 3; ++a0) d0[a0] = (real(a0) - Sx.f[0]) * I.dx;
 #pragma unroll 1
         for (int a2 = 0; a2 < (D == 3 ? 3 : 1); ++a2)
 #pragma unroll 1
-            for (int a1 = 0; a1 < 3; ++a1)
+            for (int a1 = 0; a1 < 3; ++a1) {
+                const real d1 = (real(a1) - Sx.f[1]) * I.dx;
+                const real d2 = D == 3 ? (real(a2) - Sx.f[D - 1]) * I.dx : real(0);
+                const real wz = D == 3 ? sel3(Sx.w[D - 1], a2) : real(1);
+                const real dwz = D == 3 ? sel3(Sx.dw[D - 1], a2) : real(0);
+                const real wy = sel3(Sx.w[1], a1), dwy = sel3(Sx.dw[1], a1);
+                const real wyz = wy * wz, dwyz = dwy * wz, wydz = wy * dwz;
+                real h[D];   // m v + A dpos without its x term
+#pragma unroll
+                for (int r = 0; r < D; ++r) {
+                    real u = mv[r];
+                    if (D == 3) u += T.A[r][D - 1] * d2;
+                    h[r] = u + T.A[r][1] * d1;
+                }
+                real U[D], V[D];   // row sums of w pbar and of w dpos_x pbar
+#pragma unroll
+                for (int r = 0; r < D; ++r) U[r] = V[r] = real(0);
 #pragma unroll
                 for (int a0 = 0; a0 < 3; ++a0) {
                     int oa[D];
                     oa[0] = a0;
                     oa[1] = a1;
                     if (D == 3) oa[D - 1] = a2;
-                    real dpos[D], gw[D];
-                    const real w = node_weight<real, D>(Sx, oa, I.dx, dpos);
-                    node_grad<real, D>(Sx, oa, gw);
+                    const real wx = Sx.w[0][a0], dwx = Sx.dw[0][a0];
+                    const real w = wx * wyz;
+                    real gw[D];
+                    gw[0] = dwx * wyz;
+                    gw[1] = wx * dwyz;
+                    if (D == 3) gw[D - 1] = wx * wydz;
                     const real* nd = node_rec<real, D>(nbx, lds, gsrc, Sx.base, oa, I.n_grid);
                     real pb[D];
                     load_vec<real, D>(nd, pb);
                     const real mbi = nd[3];
                     real pmom = 0;
 #pragma unroll
-                    for (int r = 0; r < D; ++r) {
-                        real ad = mv[r];
-#pragma unroll
-                        for (int c = 0; c < D; ++c) ad += T.A[r][c] * dpos[c];
-                        pmom += pb[r] * ad;
-                    }
+                    for (int r = 0; r < D; ++r) pmom += pb[r] * (h[r] + T.A[r][0] * d0[a0]);
                     const real coef = mbi * T.m + pmom;
                     smb += w * mbi;
+                    const real wd = w * d0[a0];
 #pragma unroll
                     for (int r = 0; r < D; ++r) {
-                        const real wp = w * pb[r];
-                        S0[r] += wp;
                         xb[r] += coef * gw[r];
-#pragma unroll
-                        for (int c = 0; c < D; ++c) Ab[r][c] += wp * dpos[c];
+                        U[r] += w * pb[r];
+                        V[r] += wd * pb[r];
                     }
                 }
+#pragma unroll
+                for (int r = 0; r < D; ++r) {
+                    S0[r] += U[r];
+                    Ab[r][0] += V[r];
+                    Ab[r][1] += d1 * U[r];
+                    if (D == 3) Ab[r][D - 1] += d2 * U[r];
+                }
+            }
         real mb = smb + ddot<real, D>(Ab, q.C), vb[D];
 #pragma unroll
         for (int r = 0; r < D; ++r) {
