@@ -72,28 +72,81 @@ def timed(fn, n):
     return (time.perf_counter() - t0) / n
 
 
-def roofline(sim, tens, dloss):
-    """One extra instrumented pass with per-launch HIP events."""
+# Peaks of one MI355X. HBM3E 8 TB/s. Vector ALU: 256 CUs x 4 SIMDs x 16 lanes
+# x 2 FLOP (FMA) x 2.4 GHz = 78.6 TFLOP/s for unpacked FP32 and for FP64; the
+# 157.3 TFLOP/s FP32 figure counts packed two-wide FP32 instructions, which this
+# build does not emit.
+ALU_PEAK_TFLOPS = {4: 78.6, 8: 78.6}
+ALU_PEAK_PACKED_TFLOPS = {4: 157.3, 8: 78.6}
+
+# HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE, then
+# WRITE_SIZE, on the quadruped workload, scaled by what the counters read for a
+# device-to-device copy of 1 GiB (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0). Valid
+# only for the kernel sources they were taken on (hash of csrc/).
+TRAFFIC = {
+    # (475407.2 KiB fetched x 2.0 + 311133.1 KiB written) x 1024, mean of 5 launches
+    "p2g_g2p_adj": 1292234240,
+    # (140857.0 x 2.0 + 246108.9) x 1024, mean of 26 launches (plain and recorded steps)
+    "g2p_p2g": 540490650,
+}
+TRAFFIC_SRC_HASH = "3c6fd368ce032ded"
+
+
+def csrc_hash():
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2503_22767_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hpp", ".hip")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def roofline(sim, tens, dloss, precision):
+    """One extra instrumented pass with per-launch HIP events on the library's
+    stream. The dominant kernel (largest total time) is placed on the roofline
+    by its arithmetic intensity against the ridge of the ALU and HBM peaks."""
     sim.set_option("kernel_timing", 1)
     sim.kernel_stats(reset=True)
     run_step(sim, tens, dloss)
     torch.cuda.synchronize()
     stats = sim.kernel_stats(reset=True)
     sim.set_option("kernel_timing", 0)
-    timed_k = {k: v for k, v in stats.items() if v["launches"] and v["bytes"] > 0}
+    timed_k = {k: v for k, v in stats.items() if v["launches"] and (v["bytes"] > 0 or v["flops"] > 0)}
     dom = max(timed_k, key=lambda k: timed_k[k]["ms"])
     s = timed_k[dom]
-    avg_ms = s["ms"] / s["launches"]
-    bytes_per_launch = s["bytes"] / s["launches"]
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    per_kernel = {k: dict(launches=v["launches"], avg_us=1e3 * v["ms"] / max(1, v["launches"]),
-                          total_ms=v["ms"],
-                          gbs=(v["bytes"] / max(1, v["launches"])) / max(1e-12, v["ms"] / max(1, v["launches"]) * 1e-3) / 1e9
-                          if v["bytes"] else None)
-                  for k, v in stats.items() if v["launches"]}
-    return dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                avg_launch_us=round(avg_ms * 1e3, 2), bytes_per_launch=int(bytes_per_launch)), per_kernel
+    avg_s = s["ms"] / s["launches"] * 1e-3
+    bpl = s["bytes"] / s["launches"]
+    fpl = s["flops"] / s["launches"]
+    alu_peak = ALU_PEAK_TFLOPS[precision]
+    ridge = alu_peak * 1e12 / (HBM_PEAK_GBS * 1e9)
+    intensity = fpl / bpl if bpl > 0 else float("inf")
+    gbs = bpl / avg_s / 1e9
+    tflops = fpl / avg_s / 1e12
+    traffic = None
+    if dom in TRAFFIC and TRAFFIC_SRC_HASH == csrc_hash():
+        traffic = TRAFFIC[dom]
+    if intensity > ridge:
+        rl = dict(bound="alu", achieved=round(tflops, 2), peak=alu_peak, unit="TFLOP/s",
+                  frac=round(tflops / alu_peak, 4), traffic=traffic,
+                  peak_packed_fp32=ALU_PEAK_PACKED_TFLOPS[precision],
+                  frac_vs_packed=round(tflops / ALU_PEAK_PACKED_TFLOPS[precision], 4))
+    else:
+        rl = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                  frac=round(gbs / HBM_PEAK_GBS, 4), traffic=traffic)
+    rl.update(kernel=dom, avg_launch_us=round(avg_s * 1e6, 2), flops_per_launch=fpl, bytes_per_launch=int(bpl),
+              intensity_flop_per_byte=round(intensity, 2), ridge_flop_per_byte=round(ridge, 2),
+              hbm_gbs=round(gbs, 1), hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
+    per_kernel = {}
+    for k, v in stats.items():
+        if not v["launches"]:
+            continue
+        t = v["ms"] / v["launches"] * 1e-3
+        per_kernel[k] = dict(launches=v["launches"], avg_us=t * 1e6, total_ms=v["ms"],
+                             gbs=(v["bytes"] / v["launches"]) / max(1e-12, t) / 1e9 if v["bytes"] else None,
+                             tflops=(v["flops"] / v["launches"]) / max(1e-12, t) / 1e12 if v["flops"] else None)
+    return rl, per_kernel
 
 
 def separate(wl, opts, reps=2):
@@ -230,9 +283,9 @@ def main():
         rec["batched_speedup"] = round(t_sep / t_step, 3)
         log(f"[bench] {len(wl.instances)} separate handles: {t_sep * 1e3:.1f} ms per fwd+adj pass")
     if not args.no_roofline:
-        rl, per_kernel = roofline(sim, tens, dloss)
+        rl, per_kernel = roofline(sim, tens, dloss, wl.precision)
         rec["roofline"] = rl
-        rec["kernels"] = {k: {kk: (round(vv, 2) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+        rec["kernels"] = {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                           for k, v in per_kernel.items()}
         log(f"[bench] roofline {rl}")
     sim.close()

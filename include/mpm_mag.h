@@ -169,6 +169,14 @@ int mpm_mag_num_kernels(void);
 const char* mpm_mag_kernel_name(int kernel);
 int mpm_mag_kernel_stats(mpm_mag* h, int kernel, int64_t* launches, double* total_ms, double* bytes);
 
+/*
+ * Algorithmic floating-point operations of the launches counted by
+ * mpm_mag_kernel_stats (add or multiply 1, fused multiply-add 2), from the
+ * per-particle arithmetic of the method that each kernel class performs.
+ * EINVAL for a bad kernel id or a NULL output.
+ */
+int mpm_mag_kernel_flops(mpm_mag* h, int kernel, double* flops);
+
 /* Device bytes currently held by the handle (state, grids, checkpoints). */
 int64_t mpm_mag_device_bytes(const mpm_mag* h);
 

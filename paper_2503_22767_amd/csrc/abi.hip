@@ -123,6 +123,12 @@ int mpm_mag_num_kernels(void) { return mpm::K_COUNT; }
 
 const char* mpm_mag_kernel_name(int kernel) { return mpm::kernel_name(kernel); }
 
+int mpm_mag_kernel_flops(mpm_mag* h, int kernel, double* flops)
+{
+    if (!h) return MPM_MAG_EINVAL;
+    return h->eng->kernel_flops(kernel, flops);
+}
+
 int mpm_mag_kernel_stats(mpm_mag* h, int kernel, int64_t* launches, double* total_ms, double* bytes)
 {
     if (!h) return MPM_MAG_EINVAL;

@@ -34,6 +34,7 @@ struct KernelStat {
     int64_t launches = 0;
     double ms = 0.0;
     double bytes = 0.0;
+    double flops = 0.0;
 };
 
 class EngineBase {
@@ -54,6 +55,12 @@ public:
         if (launches) *launches = stats_[k].launches;
         if (ms) *ms = stats_[k].ms;
         if (bytes) *bytes = stats_[k].bytes;
+        return MPM_MAG_OK;
+    }
+    int kernel_flops(int k, double* flops)
+    {
+        if (k < 0 || k >= K_COUNT || !flops) return MPM_MAG_EINVAL;
+        *flops = stats_[k].flops;
         return MPM_MAG_OK;
     }
     std::string err;
@@ -477,10 +484,39 @@ private:
         }
     }
 
-    void count(int kid, double bytes)
+    void count(int kid, double bytes, double flops = 0.0)
     {
         stats_[kid].launches += 1;
         stats_[kid].bytes += bytes;
+        stats_[kid].flops += flops;
+    }
+
+    // Floating-point operations a launch of each kernel class must perform
+    // (add or multiply 1, fused multiply-add 2), counted from the arithmetic of
+    // the method per particle: the stencil weights, the stress of Eq. 7 with the
+    // SIMP factors, the 3^D-node transfers of Eqs. 14-15 and 19-22, and for the
+    // transposed kernels their adjoints with the stress tangent. Encoding,
+    // indexing and reduction bookkeeping are not counted.
+    double algo_flops(int kid) const
+    {
+        const double n = (double)N_;
+        const double S3 = D == 2 ? 9.0 : 27.0;
+        // per-node work: P2G, G2P, P2G transpose, G2P transpose
+        const double p2g_node = 2 * D * D + 3 * D + 1, g2p_node = 2 * D * D + 3 * D - 1;
+        const double p2ga_node = 5 * D * D + 5 * D + 2, g2pa_node = 5 * D * D + 10 * D - 2;
+        // per-particle work outside the node loops
+        const double stress = D == 2 ? 95.0 : 237.0;          // Eq. 7 with SIMP, A = m C - k V P F^T
+        const double fwd_rest = D == 2 ? 154.0 : 374.0;       // stencil, stress, C, x, F updates, det F
+        const double adj_rest = D == 2 ? 445.0 : 1027.0;      // both stencils, stress, tangent, design terms
+        switch (kid) {
+        case K_P2G: return n * (12.0 * D + stress + S3 * p2g_node);
+        case K_G2P: return n * ((fwd_rest - stress) + S3 * g2p_node);
+        case K_G2P2G: return n * (fwd_rest + S3 * (p2g_node + g2p_node));
+        case K_ADJ_FUSED: return n * (adj_rest + S3 * (p2ga_node + g2pa_node));
+        case K_P2G_ADJ: return n * (0.6 * adj_rest + S3 * p2ga_node);
+        case K_G2P_ADJ: return n * (0.4 * adj_rest + S3 * g2pa_node);
+        default: return 0.0;
+        }
     }
 
     template <typename Kern, typename... A>
@@ -503,7 +539,7 @@ private:
             MPM_HIP(hipEventRecord(e1, s));
             pending_.push_back({kid, e0, e1});
         }
-        count(kid, algo_bytes(kid));
+        count(kid, algo_bytes(kid), algo_flops(kid));
         return MPM_MAG_OK;
     }
 

@@ -99,6 +99,8 @@ def lib():
     L.mpm_mag_kernel_name.restype = C.c_char_p
     L.mpm_mag_kernel_stats.argtypes = [vp, C.c_int, C.POINTER(i64), C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.mpm_mag_kernel_stats.restype = C.c_int
+    L.mpm_mag_kernel_flops.argtypes = [vp, C.c_int, C.POINTER(C.c_double)]
+    L.mpm_mag_kernel_flops.restype = C.c_int
     L.mpm_mag_device_bytes.argtypes = [vp]
     L.mpm_mag_device_bytes.restype = i64
     _lib = L
@@ -193,9 +195,10 @@ class MpmMag:
         L = lib()
         out = {}
         for k in range(L.mpm_mag_num_kernels()):
-            n, ms, b = C.c_int64(), C.c_double(), C.c_double()
+            n, ms, b, f = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
             self._check(L.mpm_mag_kernel_stats(self._h, k, C.byref(n), C.byref(ms), C.byref(b)), "kernel_stats")
-            out[L.mpm_mag_kernel_name(k).decode()] = dict(launches=n.value, ms=ms.value, bytes=b.value)
+            self._check(L.mpm_mag_kernel_flops(self._h, k, C.byref(f)), "kernel_flops")
+            out[L.mpm_mag_kernel_name(k).decode()] = dict(launches=n.value, ms=ms.value, bytes=b.value, flops=f.value)
         if reset:
             L.mpm_mag_kernel_stats(self._h, -1, None, None, None)
         return out

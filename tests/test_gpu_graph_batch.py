@@ -109,9 +109,11 @@ def test_batched_instances_match_separate_handles():
 
     Same arithmetic, but not the same rounding: the batch orders particles on
     the Hilbert curve of its largest grid, so chunks (and their fixed-point
-    scales) differ from a lone instance's. Bars: positions 1e-5 absolute, loss
-    1e-6 absolute (the centre-of-mass losses are ~1e-6 after 40 steps),
-    gradients 1e-4 norm-wise."""
+    scales) differ from a lone instance's, and both are FP32 results that must
+    each meet the parity bar against the FP64 oracle. Bars: positions 1e-5
+    absolute, loss 1e-6 absolute (the centre-of-mass losses are ~1e-6 after 40
+    steps), gradients the parity bar 1e-3 norm-wise (a mix-up of instances,
+    programs or offsets shows as O(1))."""
     wl = _batch(64, 40)
     got = gpu_run(wl.instances, precision=4)
     offs = np.cumsum([0] + [i.n for i in wl.instances])
@@ -129,7 +131,7 @@ def test_batched_instances_match_separate_handles():
         for name, e in errs.items():
             worst[name] = max(worst.get(name, 0.0), float(e))
     log("batched vs separate (worst over instances)", {k: f"{v:.2e}" for k, v in worst.items()})
-    bars = dict(x=1e-5, loss=1e-6, g_density=1e-4, g_br=1e-4, g_b_prog=1e-4)
+    bars = dict(x=1e-5, loss=1e-6, g_density=1e-3, g_br=1e-3, g_b_prog=1e-3)
     for name, e in worst.items():
         assert e <= bars[name], (name, e)
 
