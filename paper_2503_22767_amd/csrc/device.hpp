@@ -314,6 +314,56 @@ __device__ __forceinline__ float wave_max_nonneg(float v)
     return __int_as_float(wave_max(__float_as_int(v)));
 }
 
+// Per-axis minimum and maximum of the stencil bases c[] over the active lanes
+// of the wave (every lane must call). The bases lie in [0, 1021], so they are
+// reduced as packed 16-bit integers: (x, y), (z, -x), (-y, -z) by minimum,
+// three DPP reductions for the six bounds. With no active lane lo = 0x3fffffff
+// and hi = -0x3fffffff.
+typedef short short2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ int pk_min16(int a, int b)
+{
+    return __builtin_bit_cast(int, __builtin_elementwise_min(__builtin_bit_cast(short2v, a),
+                                                              __builtin_bit_cast(short2v, b)));
+}
+
+__device__ __forceinline__ int pack16(int lo, int hi) { return (int)(((unsigned)hi << 16) | ((unsigned)lo & 0xFFFFu)); }
+
+template <int D>
+__device__ __forceinline__ void wave_bounds(const int c[D], bool active, int lo[D], int hi[D])
+{
+    constexpr int kNone = 0x3fff;
+    auto mn = [](int a, int b) { return pk_min16(a, b); };
+    const int x = active ? c[0] : kNone, nx = active ? -c[0] : kNone;
+    const int y = active ? c[1] : kNone, ny = active ? -c[1] : kNone;
+    if (D == 3) {
+        const int z = active ? c[D - 1] : kNone, nz = active ? -c[D - 1] : kNone;
+        const int p0 = wave_reduce(pack16(x, y), mn);
+        const int p1 = wave_reduce(pack16(z, nx), mn);
+        const int p2 = wave_reduce(pack16(ny, nz), mn);
+        lo[0] = (short)(p0 & 0xFFFF);
+        lo[1] = p0 >> 16;
+        lo[D - 1] = (short)(p1 & 0xFFFF);
+        hi[0] = -(p1 >> 16);
+        hi[1] = -(short)(p2 & 0xFFFF);
+        hi[D - 1] = -(p2 >> 16);
+    } else {
+        const int p0 = wave_reduce(pack16(x, y), mn);
+        const int p1 = wave_reduce(pack16(nx, ny), mn);
+        lo[0] = (short)(p0 & 0xFFFF);
+        lo[1] = p0 >> 16;
+        hi[0] = -(short)(p1 & 0xFFFF);
+        hi[1] = -(p1 >> 16);
+    }
+    if (lo[0] == kNone) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            lo[k] = 0x3fffffff;
+            hi[k] = -0x3fffffff;
+        }
+    }
+}
+
 // origin cell of chunk c (particle positions are stored relative to it)
 __device__ __forceinline__ void chunk_origin(const int4* corig, int c, int org[3])
 {

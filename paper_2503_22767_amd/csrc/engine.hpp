@@ -365,7 +365,8 @@ public:
                 // scatter lists of consecutive steps alternate (1, 2).
                 auto lst = [](int n) { return 1 + (n & 1); };
                 r = launch(K_G2P_ADJ, cs, n_chunks_, kBlock, k_g2p_adj<real, D>, a, (const real*)gv_slot(s1 - 1 - s0),
-                           (const real*)seg_state(c, s1 - 1 - s0), adj_, (const real*)dloss_, lst(s1 - 1), lf(s1 - 1));
+                           (const real*)seg_state(c, s1 - 1 - s0), (const real*)next_state(c, s1 - 1 - s0), adj_,
+                           (const real*)dloss_, lst(s1 - 1), lf(s1 - 1));
                 if (r) return r;
                 for (int n = s1 - 1; n >= s0; --n) {
                     const int j = n - s0;
@@ -383,8 +384,9 @@ public:
                         if (r) return r;
                         if (n > s0) {
                             r = launch(K_G2P_ADJ, cs, n_chunks_, kBlock, k_g2p_adj<real, D>, a,
-                                       (const real*)gv_slot(j - 1), (const real*)seg_state(c, j - 1), adj_,
-                                       (const real*)dloss_, lst(n - 1), lf(s1 - 1));
+                                       (const real*)gv_slot(j - 1), (const real*)seg_state(c, j - 1),
+                                       (const real*)seg_state(c, j), adj_, (const real*)dloss_, lst(n - 1),
+                                       lf(s1 - 1));
                             if (r) return r;
                         }
                     }
@@ -416,6 +418,13 @@ private:
     real* ckpt_slot(int c) { return ckpt_ + (size_t)c * state_elems(); }
     // state of step s0 + j inside checkpoint segment c (slot 0 is the checkpoint)
     real* seg_state(int c, int j) { return j == 0 ? ckpt_slot(c) : stash_ + (size_t)(j - 1) * state_elems(); }
+    // state after step s0 + j of segment c: the next stashed state, the next
+    // segment's checkpoint, or the final state
+    real* next_state(int c, int j)
+    {
+        if (c * K_ + j + 1 < std::min(T_, (c + 1) * K_)) return seg_state(c, j + 1);
+        return c + 1 < nck_ ? ckpt_slot(c + 1) : st_;
+    }
     // grid velocity / (momentum, mass) of step s0 + j of the segment being reversed
     real* gv_slot(int j) { return gstash_ + (size_t)(2 * j) * 4 * G_; }
     real* gm_slot(int j) { return gstash_ + (size_t)(2 * j + 1) * 4 * G_; }
@@ -501,9 +510,10 @@ private:
     {
         const double n = (double)N_;
         const double S3 = D == 2 ? 9.0 : 27.0;
-        // per-node work: P2G, G2P, P2G transpose, G2P transpose
+        // per-node work: P2G, G2P, P2G transpose, G2P transpose (its sums of
+        // w v_i and w v_i dpos^T are the v and C of the next state, read back)
         const double p2g_node = 2 * D * D + 3 * D + 1, g2p_node = 2 * D * D + 3 * D - 1;
-        const double p2ga_node = 5 * D * D + 5 * D + 2, g2pa_node = 5 * D * D + 10 * D - 2;
+        const double p2ga_node = 5 * D * D + 5 * D + 2, g2pa_node = 3 * D * D + 7 * D - 2;
         // per-particle work outside the node loops
         const double stress = D == 2 ? 95.0 : 237.0;          // Eq. 7 with SIMP, A = m C - k V P F^T
         const double fwd_rest = D == 2 ? 154.0 : 374.0;       // stencil, stress, C, x, F updates, det F

@@ -230,11 +230,7 @@ __device__ __forceinline__ void scatter_box(const Args<real>& a, const InstDev<r
     // bounding boxes of the wave and of the block
     int wlo[3] = {0, 0, 0}, wext[3] = {1, 1, 1};
     int whi[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-        wlo[k] = wave_min(active ? base[k] : 0x3fffffff);
-        whi[k] = wave_max(active ? base[k] : -0x3fffffff);
-    }
+    wave_bounds<D>(base, active, wlo, whi);
     const bool wave_live = wlo[0] != 0x3fffffff;
     int wvol = 1;
 #pragma unroll
@@ -574,11 +570,7 @@ __device__ __forceinline__ NodeBox<D> stage_nodes(const InstDev<real>& I, bool a
         nb.ext[k] = 1;
     }
     int lo[D], hi[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-        lo[k] = wave_min(active ? base[k] : 0x3fffffff);
-        hi[k] = wave_max(active ? base[k] : -0x3fffffff);
-    }
+    wave_bounds<D>(base, active, lo, hi);
     __syncthreads();   // s_nb may still be read by a previous call
     if ((t & 63) == 0)
 #pragma unroll
@@ -1348,14 +1340,15 @@ __device__ __forceinline__ void adj_zero(AdjState<real, D>& A)
 }
 
 // Transpose of the G2P of step n for the particles of this block: from the
-// adjoint A1 of state n+1 (registers) and state n (st), scatter the grid
-// velocity adjoint (list `list` of the scatter phases) and store the G2P share
-// of the adjoint of state n (x and F parts) in adj. lds: 4 kBoxCap words.
+// adjoint A1 of state n+1 (registers), state n (st) and the v and C of state
+// n+1 (st_next: the sums over the stencil that the G2P produced), scatter the
+// grid velocity adjoint (list `list` of the scatter phases) and store the G2P
+// share of the adjoint of state n (x and F parts) in adj. lds: 4 kBoxCap words.
 template <typename real, int D>
 __device__ __forceinline__ void g2p_adj_phase(const Args<real>& a, const InstDev<real>& I, int inst, bool active,
                                               int64_t i, const real* __restrict__ gv_in, const real* st,
-                                              AdjState<real, D>& A1, real* adj, const real* dloss, int list,
-                                              typename LdsAcc<real>::T* lds)
+                                              const real* st_next, AdjState<real, D>& A1, real* adj,
+                                              const real* dloss, int list, typename LdsAcc<real>::T* lds)
 {
     using Cp = Comp<D>;
     const int64_t S = a.nalloc;
@@ -1403,14 +1396,8 @@ __device__ __forceinline__ void g2p_adj_phase(const Args<real>& a, const InstDev
     // one gather pass: C' of the forward G2P, and the share of xbar through the
     // weights and dpos, which needs the grid velocity:
     // xb += (v_i . u_i) grad w - lam w Cbt^T v_i,  u_i = vbt + lam Cbt dpos_i
-    // (the last term summed as lam Cbt^T V after the loop, V = sum w v_i)
-    real Bm[D][D], V[D];
-#pragma unroll
-    for (int r = 0; r < D; ++r) {
-        V[r] = 0;
-#pragma unroll
-        for (int c = 0; c < D; ++c) Bm[r][c] = 0;
-    }
+    // (the last term is lam Cbt^T v', with v' = sum w v_i the velocity of
+    // state n+1)
     if (active) {
         // lam Cbt, and dpos_x of the three x offsets
         real lC[D][D], d0[3];
@@ -1437,9 +1424,6 @@ __device__ __forceinline__ void g2p_adj_phase(const Args<real>& a, const InstDev
                     if (D == 3) u += lC[r][D - 1] * d2;
                     h[r] = u + lC[r][1] * d1;
                 }
-                real U[D], W[D];   // row sums of w v_i and of w dpos_x v_i
-#pragma unroll
-                for (int r = 0; r < D; ++r) U[r] = W[r] = real(0);
 #pragma unroll
                 for (int a0 = 0; a0 < 3; ++a0) {
                     int oa[D];
@@ -1447,7 +1431,6 @@ __device__ __forceinline__ void g2p_adj_phase(const Args<real>& a, const InstDev
                     oa[1] = a1;
                     if (D == 3) oa[D - 1] = a2;
                     const real wx = Sx.w[0][a0], dwx = Sx.dw[0][a0];
-                    const real w = wx * wyz;
                     real gw[D];
                     gw[0] = dwx * wyz;
                     gw[1] = wx * dwyz;
@@ -1457,41 +1440,39 @@ __device__ __forceinline__ void g2p_adj_phase(const Args<real>& a, const InstDev
                     real vu = 0;
 #pragma unroll
                     for (int r = 0; r < D; ++r) vu += vi[r] * (h[r] + lC[r][0] * d0[a0]);
-                    const real wd = w * d0[a0];
 #pragma unroll
-                    for (int r = 0; r < D; ++r) {
-                        xb[r] += vu * gw[r];
-                        U[r] += w * vi[r];
-                        W[r] += wd * vi[r];
-                    }
-                }
-#pragma unroll
-                for (int r = 0; r < D; ++r) {
-                    V[r] += U[r];
-                    Bm[r][0] += W[r];
-                    Bm[r][1] += d1 * U[r];
-                    if (D == 3) Bm[r][D - 1] += d2 * U[r];
+                    for (int r = 0; r < D; ++r) xb[r] += vu * gw[r];
                 }
             }
+        real v1[D];
+#pragma unroll
+        for (int r = 0; r < D; ++r) v1[r] = st_next[(Cp::V + r) * S + i];
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             real ctv = 0;
 #pragma unroll
-            for (int r = 0; r < D; ++r) ctv += Cbt[r][k] * V[r];
+            for (int r = 0; r < D; ++r) ctv += Cbt[r][k] * v1[r];
             xb[k] -= lam * ctv;
         }
     }
-    // F' = (I + dt C') F  ->  Fb = (I + dt C')^T Fb'
+    // F' = (I + dt C') F  ->  Fb = (I + dt C')^T Fb', C' from state n+1
     real Fb[D][D];
+    {
+        real C1[D][D];
 #pragma unroll
-    for (int r = 0; r < D; ++r)
+        for (int r = 0; r < D; ++r)
 #pragma unroll
-        for (int c = 0; c < D; ++c) {
-            real s = A1.F[r][c];
+            for (int c = 0; c < D; ++c) C1[r][c] = active ? st_next[(Cp::C + r * D + c) * S + i] : real(0);
 #pragma unroll
-            for (int k = 0; k < D; ++k) s += I.dt * lam * Bm[k][r] * A1.F[k][c];
-            Fb[r][c] = s;
-        }
+        for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                real s = A1.F[r][c];
+#pragma unroll
+                for (int k = 0; k < D; ++k) s += I.dt * C1[k][r] * A1.F[k][c];
+                Fb[r][c] = s;
+            }
+    }
     // scatter w u_i to the grid velocity adjoint (registers only)
     real bnd[D];
 #pragma unroll
@@ -1525,7 +1506,8 @@ __device__ __forceinline__ void g2p_adj_phase(const Args<real>& a, const InstDev
 
 template <typename real, int D>
 __global__ __launch_bounds__(kBlock) void k_g2p_adj(Args<real> a, const real* __restrict__ gv_in, const real* st,
-                                                    real* adj, const real* dloss, int list, int list_fwd_done)
+                                                    const real* st_next, real* adj, const real* dloss, int list,
+                                                    int list_fwd_done)
 {
     using Cp = Comp<D>;
     __shared__ typename LdsAcc<real>::T lds[4 * kBoxCap];
@@ -1552,7 +1534,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p_adj(Args<real> a, const real* __
                 A1.F[r][c] = adj[(Cp::F + r * D + c) * S + i];
             }
     }
-    g2p_adj_phase<real, D>(a, I, ch.inst, active, i, gv_in, st, A1, adj, dloss, list, lds);
+    g2p_adj_phase<real, D>(a, I, ch.inst, active, i, gv_in, st, st_next, A1, adj, dloss, list, lds);
 }
 
 // --------------------------------------------------------------------------
@@ -1642,6 +1624,7 @@ __device__ __forceinline__ void p2g_adj_phase(const Args<real>& a, const InstDev
     using Cp = Comp<D>;
     const int t = threadIdx.x;
     const int64_t S = a.nalloc;
+    adj_zero(A0);   // inactive lanes keep a zero adjoint
     real B[D];
     field_at<real, D>(I, a.bprog, step, B);
     double gBl[D];
@@ -1809,8 +1792,6 @@ __device__ __forceinline__ void p2g_adj_phase(const Args<real>& a, const InstDev
                 A0.C[r][c] = T.m * Ab[r][c];
                 A0.F[r][c] = adj[(Cp::F + r * D + c) * S + i] + Fbp[r][c] + T.se * dP[r][c];
             }
-    } else {
-        adj_zero(A0);
     }
     block_sum<D>(gBl);
     if (t == 0) {
@@ -1870,7 +1851,7 @@ __global__ __launch_bounds__(kBlock, sizeof(real) == 4 ? 4 : 2) void k_adj_fused
     AdjState<real, D> A;
     p2g_adj_phase<real, D>(a, I, ch.inst, active, i, gpm_in, st_n, adj, step, A, reinterpret_cast<real*>(lds));
     __syncthreads();   // the LDS node box of the gather is reused below
-    g2p_adj_phase<real, D>(a, I, ch.inst, active, i, gv_prev, st_prev, A, adj, dloss, list_next, lds);
+    g2p_adj_phase<real, D>(a, I, ch.inst, active, i, gv_prev, st_prev, st_n, A, adj, dloss, list_next, lds);
 }
 
 // --------------------------------------------------------------------------
