@@ -44,7 +44,7 @@ typedef enum {
     MPM_MAG_EHIP = 3,        /* a HIP runtime call or kernel launch failed                  */
     MPM_MAG_EDOMAIN = 4,     /* a particle's 3^d stencil left the grid [0, n_grid)^d         */
     MPM_MAG_EINVERT = 5,     /* det F <= 0 for some particle                                */
-    MPM_MAG_ENONFINITE = 6,  /* NaN or Inf in the particle state                            */
+    MPM_MAG_ENONFINITE = 6,  /* NaN or Inf in the inputs or the particle state              */
     MPM_MAG_ESTATE = 7       /* backward without a preceding successful record=1 rollout    */
 } mpm_mag_status;
 

@@ -339,6 +339,7 @@ public:
             for (int c = nck_ - 1; c >= 0; --c) {
                 const int s0 = c * K_;
                 const int s1 = std::min(T_, s0 + K_);
+                if (s1 <= s0) continue;   // no step to reverse (T = 0)
                 // recompute the segment, keeping every step's grid (sparse: only
                 // the active coarse blocks are written)
                 for (int n = s0; n < s1; ++n) {
@@ -652,7 +653,7 @@ private:
         Args<real> a = args();
         return launch(K_GATHER, s, n_chunks_, kBlock, k_gather<real, D>, a, (const int*)vals_[cur],
                       (const int64_t*)caller_start_d_, st_, x0s_, phi_, br_, tgt_, mask_, id_, corig_, x0, phi, br, tgt,
-                      mask);
+                      mask, (int64_t)S_tot_ * D);
     }
 
     int finish(hipStream_t s)

@@ -1863,7 +1863,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(Args<real> a, const int* __re
                                                    const int64_t* __restrict__ caller_start, real* st, real* x0s,
                                                    real* phi, real* br, real* tgt, uint8_t* mask, int* id,
                                                    int4* corig, const real* x0_in, const real* phi_in,
-                                                   const real* br_in, const real* tgt_in, const uint8_t* mask_in)
+                                                   const real* br_in, const real* tgt_in, const uint8_t* mask_in,
+                                                   int64_t n_prog)
 {
     using Cp = Comp<D>;
     __shared__ int s_min[kWaves][3];
@@ -1898,7 +1899,20 @@ __global__ __launch_bounds__(kBlock) void k_gather(Args<real> a, const int* __re
         org[k] = (m == 0x3fffffff) ? 0 : m;
     }
     if (t == 0) corig[blockIdx.x] = make_int4(org[0], org[1], org[2], 0);
+    // inputs must be finite: a NaN mass would otherwise read as an empty node
+    if (blockIdx.x == 0)
+        for (int64_t j = t; j < n_prog; j += kBlock)
+            if (!rfinite(a.bprog[j])) atomicOr(a.err, kErrNonFinite);
     if (!active) return;
+    {
+        bool fin = rfinite(phi_in[q]);
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            fin = fin && isfinite(xa[k]) && rfinite(br_in[(int64_t)q * D + k]);
+            if (tgt_in) fin = fin && rfinite(tgt_in[(int64_t)q * D + k]);
+        }
+        if (!fin) atomicOr(a.err, kErrNonFinite);
+    }
     id[i] = q;
 #pragma unroll
     for (int k = 0; k < D; ++k) {

@@ -52,6 +52,16 @@ def test_create_rejects_bad_arguments_without_touching_the_device():
     descs[0].dim = 2
     assert L.mpm_mag_create(descs, 1, counts, 5, ctypes.byref(h)) == M.EINVAL
     assert L.mpm_mag_create(descs, 0, counts, 4, ctypes.byref(h)) == M.EINVAL
+    descs[0].n_grid = 32
+    descs[0].n_segments = 1
+    descs[0].dt = 1e-3
+    descs[0].particle_volume = 1e-4
+    descs[0].mu0 = descs[0].rho = 1.0
+    descs[0].nu = 0.3
+    zero = (ctypes.c_int64 * 1)(0)
+    assert L.mpm_mag_create(descs, 1, zero, 4, ctypes.byref(h)) == M.EINVAL   # no particles
+    descs[0].n_steps = -1
+    assert L.mpm_mag_create(descs, 1, counts, 4, ctypes.byref(h)) == M.EINVAL  # negative step count
     assert L.mpm_mag_rollout(None, None, None, None, None, None, None, None, None, None, 0) == M.EINVAL
     assert L.mpm_mag_backward(None, None, None, None, None, None) == M.EINVAL
     L.mpm_mag_destroy(None)

@@ -1,0 +1,101 @@
+"""Degenerate inputs and error paths of the device library, through the C ABI.
+
+* A rollout of zero steps (loss of the initial state; the gradient is the
+  loss's direct dependence on the design), and a single particle, against the
+  FP64 oracle.
+* A particle whose stencil lies partly outside the grid: the stencils are
+  clamped so every access stays in bounds, and the call reports EDOMAIN.
+* A non-finite design value: the call reports a non-finite (or derived domain /
+  inversion) error instead of returning numbers.
+* backward after a plain (record=0) rollout reports ESTATE.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2503_22767_amd import mpm_mag as M
+from paper_2503_22767_amd import workloads as W
+
+from gpu_util import compare, gpu_run, log, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+def _block(dim, steps, kind=W.LOSS_COM_DISP, floor=True, seed=3):
+    size = (0.4, 0.2, 0.2) if dim == 2 else (0.3, 0.2, 0.25)
+    return W.make_tiny(seed=seed, dim=dim, n_steps=steps, loss_kind=kind, floor=floor, gravity=1.0 if floor else 0.0,
+                       size=size, n_grid=16, n_segments=2)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("kind", [W.LOSS_COM_DISP, W.LOSS_FINAL_MSE], ids=["com", "mse"])
+def test_zero_steps_matches_oracle(dim, kind):
+    inst = _block(dim, 0, kind=kind, floor=kind == W.LOSS_COM_DISP)
+    ref = oracle_run([inst])
+    got = gpu_run([inst], precision=8)
+    # the gradients vanish or nearly so at T = 0 (the centre-of-mass loss is
+    # zero whatever the design): compare absolutely
+    errs = {k: float(np.max(np.abs(got[k] - ref[k]))) for k in ("x", "loss", "g_density", "g_br", "g_b_prog")}
+    log("T=0", dim, kind, {k: f"{v:.2e}" for k, v in errs.items()})
+    assert errs["x"] <= 1e-14 and errs["loss"] <= 1e-12, errs
+    for k in ("g_density", "g_br", "g_b_prog"):
+        assert errs[k] <= 1e-10 * max(1.0, float(np.max(np.abs(ref[k])))), (k, errs)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_single_particle_matches_oracle(dim):
+    inst = _block(dim, 12)
+    one = W.Instance(dict(inst.params), inst.x0[:1], inst.density[:1], inst.br[:1], inst.b_prog,
+                     inst.target[:1] if inst.target is not None else None, None)
+    ref = oracle_run([one])
+    got = gpu_run([one], precision=8)
+    compare(got, ref, pos_tol=1e-10, grad_tol=1e-9, loss_tol=1e-9, label=f"N=1 d{dim}")
+    got = gpu_run([one], precision=4)
+    compare(got, ref, pos_tol=1e-4, grad_tol=1e-3, label=f"N=1 d{dim} fp32")
+
+
+def _status_of(fn):
+    try:
+        fn()
+    except M.MpmMagError as e:
+        return e.status
+    return M.OK
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_particle_outside_the_grid_reports_edomain(dim):
+    inst = _block(dim, 4, floor=False)
+    x0 = inst.x0.copy()
+    x0[0, 0] = 0.004   # base cell -1 at 16 nodes per axis: the stencil leaves the grid
+    bad = W.Instance(dict(inst.params), x0, inst.density, inst.br, inst.b_prog, inst.target, inst.mask)
+    for prec in (8, 4):
+        st = _status_of(lambda: gpu_run([bad], precision=prec, backward=False))
+        log("outside grid", dim, prec, st)
+        assert st == M.EDOMAIN, st
+
+
+def test_nonfinite_design_value_reports_an_error():
+    inst = _block(3, 4, floor=False)
+    dens = inst.density.copy()
+    dens[5] = np.nan
+    bad = W.Instance(dict(inst.params), inst.x0, dens, inst.br, inst.b_prog, inst.target, inst.mask)
+    for prec in (8, 4):
+        st = _status_of(lambda: gpu_run([bad], precision=prec, backward=False))
+        log("nan density", prec, st)
+        assert st in (M.ENONFINITE, M.EDOMAIN, M.EINVERT), st
+
+
+def test_backward_needs_a_recorded_rollout():
+    inst = _block(2, 4)
+    sim = M.MpmMag([inst.params], [inst.n], precision=8)
+    try:
+        tens = M.instance_tensors([inst], dtype=torch.float64)
+        sim.rollout(*tens, record=False)
+        st = _status_of(lambda: sim.backward(torch.ones(1, dtype=torch.float64, device="cuda")))
+        assert st == M.ESTATE, st
+        # a recorded rollout then makes it work, and the handle stays usable
+        sim.rollout(*tens, record=True)
+        g = sim.backward(torch.ones(1, dtype=torch.float64, device="cuda"))
+        assert all(torch.isfinite(x).all() for x in g)
+    finally:
+        sim.close()
