@@ -103,16 +103,20 @@ def csrc_hash():
     return h.hexdigest()[:16]
 
 
-def roofline(sim, tens, dloss, precision):
+def roofline(sim, tens, dloss, precision, streams=0):
     """One extra instrumented pass with per-launch HIP events on the library's
     stream. The dominant kernel (largest total time) is placed on the roofline
     by its arithmetic intensity against the ridge of the ALU and HBM peaks."""
+    # one stream, so that launches do not overlap and each launch's time is
+    # its own (the timed passes may run instance groups on several streams)
+    sim.set_option("streams", 1)
     sim.set_option("kernel_timing", 1)
     sim.kernel_stats(reset=True)
     run_step(sim, tens, dloss)
     torch.cuda.synchronize()
     stats = sim.kernel_stats(reset=True)
     sim.set_option("kernel_timing", 0)
+    sim.set_option("streams", streams)
     timed_k = {k: v for k, v in stats.items() if v["launches"] and (v["bytes"] > 0 or v["flops"] > 0)}
     dom = max(timed_k, key=lambda k: timed_k[k]["ms"])
     s = timed_k[dom]
@@ -135,7 +139,8 @@ def roofline(sim, tens, dloss, precision):
     else:
         rl = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                   frac=round(gbs / HBM_PEAK_GBS, 4), traffic=traffic)
-    rl.update(kernel=dom, avg_launch_us=round(avg_s * 1e6, 2), flops_per_launch=fpl, bytes_per_launch=int(bpl),
+    rl.update(kernel=dom, avg_launch_us=round(avg_s * 1e6, 2), timed_on_one_stream=True, flops_per_launch=fpl,
+              bytes_per_launch=int(bpl),
               intensity_flop_per_byte=round(intensity, 2), ridge_flop_per_byte=round(ridge, 2),
               hbm_gbs=round(gbs, 1), hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
     per_kernel = {}
@@ -283,7 +288,7 @@ def main():
         rec["batched_speedup"] = round(t_sep / t_step, 3)
         log(f"[bench] {len(wl.instances)} separate handles: {t_sep * 1e3:.1f} ms per fwd+adj pass")
     if not args.no_roofline:
-        rl, per_kernel = roofline(sim, tens, dloss, wl.precision)
+        rl, per_kernel = roofline(sim, tens, dloss, wl.precision, opts.get("streams", 0))
         rec["roofline"] = rl
         rec["kernels"] = {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                           for k, v in per_kernel.items()}

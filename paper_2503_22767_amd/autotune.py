@@ -8,6 +8,7 @@ The knobs are options of the library:
   p2g_lds     LDS-staged scatter vs direct global atomics
   fuse_fwd    G2P of one step and P2G of the next in one kernel, or two
   fuse_adj    the same pairing for the transposed kernels of the reverse sweep
+  streams     instance groups advanced on separate streams (0: automatic)
 
 Each candidate setting is timed on the workload's own instances over a short
 horizon (20 steps by default): a recorded rollout and its backward, median of
@@ -29,7 +30,7 @@ import time
 from typing import Callable, Dict, List, Sequence, Tuple
 
 DEFAULTS: Dict[str, int] = dict(sort_curve=0, box_cap=1024, grid_wgs=2048, graph=0, p2g_lds=1, fuse_fwd=1,
-                                fuse_adj=1)
+                                fuse_adj=1, streams=0)
 SPACE: Dict[str, List[int]] = dict(
     sort_curve=[0, 1, 2],
     box_cap=[256, 512, 1024],
@@ -38,6 +39,7 @@ SPACE: Dict[str, List[int]] = dict(
     p2g_lds=[1, 0],
     fuse_fwd=[1, 0],
     fuse_adj=[1, 0],
+    streams=[0, 1, 2, 4],
 )
 CACHE_ENV = "MPM_MAG_TUNE_CACHE"
 

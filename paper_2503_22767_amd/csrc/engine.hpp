@@ -6,6 +6,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -189,7 +190,10 @@ public:
         if (max_cell_bits + inst_bits > 32) return fail(MPM_MAG_EINVAL, "too many grid cells x instances for the sort key");
         sort_passes_ = (max_cell_bits + inst_bits + 7) / 8;
         sort_blocks_ = (int)((N_ + kSortTile - 1) / kSortTile);
-        return allocate();
+        int st_alloc = allocate();
+        if (st_alloc) return st_alloc;
+        plan_chains();
+        return MPM_MAG_OK;
     }
 
     int set_option(const char* key, int64_t value) override
@@ -202,6 +206,13 @@ public:
             return MPM_MAG_OK;
         }
         if (k == "kernel_timing") { timing_ = value != 0; return MPM_MAG_OK; }
+        if (k == "streams") {
+            if (value < 0 || value > kMaxChains) return fail(MPM_MAG_EINVAL, "streams must be in [0, 8]");
+            streams_opt_ = (int)value;
+            plan_chains();
+            ++plan_gen_;
+            return MPM_MAG_OK;
+        }
         if (k == "fuse_fwd") {
             fuse_fwd_ = value != 0;
             ++plan_gen_;
@@ -263,43 +274,19 @@ public:
         MPM_HIP(hipMemsetAsync(acc_, 0, sizeof(double) * kAccCount * n_inst_, s));
         MPM_HIP(hipMemsetAsync(gm_, 0, sizeof(real) * 4 * G_, s));
         MPM_HIP(hipMemsetAsync(reg_count_, 0, sizeof(int) * n_cb_, s));
-        MPM_HIP(hipMemsetAsync(active_, 0, sizeof(int) * 4, s));
+        MPM_HIP(hipMemsetAsync(active_, 0, sizeof(int) * 4 * kMaxChains, s));
         MPM_HIP(hipMemcpyAsync(bprog_, b_prog, sizeof(real) * S_tot_ * D, hipMemcpyDeviceToDevice, s));
         int st = sort_and_gather(s, (const real*)x0, (const real*)density, (const real*)br, (const real*)target, mask);
         if (st) return st;
         auto steps = [&](hipStream_t cs) -> int {
-            Args<real> a = args();
-            for (int n = 0; n < T_; ++n) {
-                const bool ck = record && n % K_ == 0;
-                if (n == 0 || !fuse_fwd_) {
-                    if (ck) {
-                        MPM_HIP(hipMemcpyAsync(ckpt_slot(n / K_), st_, state_bytes(), hipMemcpyDeviceToDevice, cs));
-                        count(K_CKPT, 2.0 * state_bytes());
-                    }
-                    int r = launch(K_P2G, cs, n_chunks_, kBlock, k_p2g<real, D>, a, (const real*)st_, n, lf(n));
+            int r = fork(cs);
+            if (r) return r;
+            for (int n = 0; n < T_; ++n)
+                for (int q = 0; q < n_chains(); ++q) {
+                    r = fwd_step(q, stream_of(q, cs), n, record != 0);
                     if (r) return r;
                 }
-                int r = launch(K_GRID, cs, grid_blocks(), kGridBlock, k_grid<real, D>, a, gv_, (real*)nullptr, lf(n));
-                if (r) return r;
-                if (n + 1 < T_ && fuse_fwd_) {
-                    // G2P of step n with P2G of step n + 1; v and C are stored
-                    // only for the checkpoint taken before step n + 1
-                    const bool ck1 = record && (n + 1) % K_ == 0;
-                    r = launch(K_G2P2G, cs, n_chunks_, kBlock, k_g2p2g<real, D>, a, (const real*)gv_, (const real*)st_,
-                               st_, n, 1, ck1 ? 1 : 0, lf(n), lf(n + 1));
-                    if (r) return r;
-                    if (ck1) {
-                        MPM_HIP(hipMemcpyAsync(ckpt_slot((n + 1) / K_), st_, state_bytes(), hipMemcpyDeviceToDevice,
-                                               cs));
-                        count(K_CKPT, 2.0 * state_bytes());
-                    }
-                } else {
-                    r = launch(K_G2P, cs, n_chunks_, kBlock, k_g2p<real, D>, a, (const real*)gv_, (const real*)st_, st_,
-                               n, 1, lf(n));
-                    if (r) return r;
-                }
-            }
-            return MPM_MAG_OK;
+            return join(cs);
         };
         st = use_graph() ? replay(s, gfwd_[record ? 1 : 0], steps) : steps(s);
         if (st) return st;
@@ -329,71 +316,37 @@ public:
         MPM_HIP(hipMemsetAsync(err_d_, 0, sizeof(int), s));
         MPM_HIP(hipMemsetAsync(gB_, 0, sizeof(double) * S_tot_ * D, s));
         MPM_HIP(hipMemcpyAsync(dloss_, dloss, sizeof(real) * n_inst_, hipMemcpyDeviceToDevice, s));
-        MPM_HIP(hipMemsetAsync(active_, 0, sizeof(int) * 4, s));
+        MPM_HIP(hipMemsetAsync(active_, 0, sizeof(int) * 4 * kMaxChains, s));
         Args<real> a = args();
         int st = launch(K_SEED, s, n_chunks_, kBlock, k_seed<real, D>, a, (const real*)st_, adj_,
                         (const real*)x0s_, (const real*)tgt_, (const uint8_t*)mask_, (const real*)dloss_);
         if (st) return st;
         auto sweep = [&](hipStream_t cs) -> int {
-            int r = MPM_MAG_OK;
+            int r = fork(cs);
+            if (r) return r;
             for (int c = nck_ - 1; c >= 0; --c) {
                 const int s0 = c * K_;
                 const int s1 = std::min(T_, s0 + K_);
                 if (s1 <= s0) continue;   // no step to reverse (T = 0)
                 // recompute the segment, keeping every step's grid (sparse: only
                 // the active coarse blocks are written)
-                for (int n = s0; n < s1; ++n) {
-                    const int j = n - s0;
-                    if (n == s0 || !fuse_fwd_) {
-                        r = launch(K_P2G, cs, n_chunks_, kBlock, k_p2g<real, D>, a, (const real*)seg_state(c, j), n,
-                                   lf(n));
+                for (int n = s0; n < s1; ++n)
+                    for (int q = 0; q < n_chains(); ++q) {
+                        r = recompute_step(q, stream_of(q, cs), c, n);
                         if (r) return r;
                     }
-                    r = launch(K_GRID, cs, grid_blocks(), kGridBlock, k_grid<real, D>, a, gv_slot(j), gm_slot(j), lf(n));
+                // transpose of every step, last first
+                for (int q = 0; q < n_chains(); ++q) {
+                    r = reverse_first(q, stream_of(q, cs), c);
                     if (r) return r;
-                    if (n + 1 < s1) {
-                        if (fuse_fwd_)
-                            r = launch(K_G2P2G, cs, n_chunks_, kBlock, k_g2p2g<real, D>, a, (const real*)gv_slot(j),
-                                       (const real*)seg_state(c, j), seg_state(c, j + 1), n, 0, 1, lf(n), lf(n + 1));
-                        else
-                            r = launch(K_G2P, cs, n_chunks_, kBlock, k_g2p<real, D>, a, (const real*)gv_slot(j),
-                                       (const real*)seg_state(c, j), seg_state(c, j + 1), n, 0, lf(n));
+                }
+                for (int n = s1 - 1; n >= s0; --n)
+                    for (int q = 0; q < n_chains(); ++q) {
+                        r = reverse_step(q, stream_of(q, cs), c, n);
                         if (r) return r;
                     }
-                }
-                // transpose of every step, last first. The P2G transpose of
-                // step n runs fused with the G2P transpose of step n - 1; the
-                // scatter lists of consecutive steps alternate (1, 2).
-                auto lst = [](int n) { return 1 + (n & 1); };
-                r = launch(K_G2P_ADJ, cs, n_chunks_, kBlock, k_g2p_adj<real, D>, a, (const real*)gv_slot(s1 - 1 - s0),
-                           (const real*)seg_state(c, s1 - 1 - s0), (const real*)next_state(c, s1 - 1 - s0), adj_,
-                           (const real*)dloss_, lst(s1 - 1), lf(s1 - 1));
-                if (r) return r;
-                for (int n = s1 - 1; n >= s0; --n) {
-                    const int j = n - s0;
-                    r = launch(K_GRID_ADJ, cs, grid_blocks(), kGridBlock, k_grid_adj<real, D>, a, (const real*)gm_slot(j),
-                               gpm_, lst(n));
-                    if (r) return r;
-                    if (n > s0 && fuse_adj_) {
-                        r = launch(K_ADJ_FUSED, cs, n_chunks_, kBlock, k_adj_fused<real, D>, a, (const real*)gpm_,
-                                   (const real*)seg_state(c, j), n, (const real*)gv_slot(j - 1),
-                                   (const real*)seg_state(c, j - 1), adj_, (const real*)dloss_, lst(n), lst(n - 1));
-                        if (r) return r;
-                    } else {
-                        r = launch(K_P2G_ADJ, cs, n_chunks_, kBlock, k_p2g_adj<real, D>, a, (const real*)gpm_,
-                                   (const real*)seg_state(c, j), adj_, n, lst(n));
-                        if (r) return r;
-                        if (n > s0) {
-                            r = launch(K_G2P_ADJ, cs, n_chunks_, kBlock, k_g2p_adj<real, D>, a,
-                                       (const real*)gv_slot(j - 1), (const real*)seg_state(c, j - 1),
-                                       (const real*)seg_state(c, j), adj_, (const real*)dloss_, lst(n - 1),
-                                       lf(s1 - 1));
-                            if (r) return r;
-                        }
-                    }
-                }
             }
-            return MPM_MAG_OK;
+            return join(cs);
         };
         st = use_graph() ? replay(s, gbwd_, sweep) : sweep(s);
         if (st) return st;
@@ -412,6 +365,199 @@ public:
     }
 
 private:
+    // ---------------------------------------------------------------- chains
+    // Instances are split into up to kMaxChains groups of consecutive
+    // instances (balanced by particle count). Each group advances on its own
+    // stream with its own scatter lists, so one group's latency-bound grid
+    // kernels overlap another group's particle kernels. One group runs on the
+    // caller's stream directly.
+    static constexpr int kMaxChains = 8;
+    struct Chain {
+        int c0 = 0, nc = 0;     // chunk range
+        int ncb = 0;            // coarse blocks of its instances
+        int64_t p0 = 0, np = 0; // particle slots (chunks * kBlock)
+        hipStream_t s = nullptr;
+        hipEvent_t done = nullptr;
+    };
+
+    int n_chains() const { return (int)chains_.size(); }
+
+    void plan_chains()
+    {
+        const int n_inst = n_inst_;
+        int want = streams_opt_ > 0 ? streams_opt_ : std::min(3, n_inst);
+        want = std::max(1, std::min({want, n_inst, kMaxChains}));
+        std::vector<int> inst_chunks(n_inst), inst_cb(n_inst);
+        for (int k = 0; k < n_inst; ++k) {
+            const int next = k + 1 < n_inst ? inst_h_[k + 1].chunk_off : n_chunks_;
+            inst_chunks[k] = next - inst_h_[k].chunk_off;
+            const int nb = inst_h_[k].nb;
+            inst_cb[k] = D == 2 ? nb * nb : nb * nb * nb;
+        }
+        std::vector<Chain> ch;
+        int k = 0, done_chunks = 0;
+        for (int q = 0; q < want && k < n_inst; ++q) {
+            Chain c;
+            c.c0 = inst_h_[k].chunk_off;
+            const double target = (double)(n_chunks_ - done_chunks) / (double)(want - q);
+            do {
+                c.nc += inst_chunks[k];
+                c.ncb += inst_cb[k];
+                ++k;
+            } while (k < n_inst && (q == want - 1 || c.nc + inst_chunks[k] / 2 < target));
+            done_chunks += c.nc;
+            c.p0 = (int64_t)c.c0 * kBlock;
+            c.np = (int64_t)c.nc * kBlock;
+            ch.push_back(c);
+        }
+        // keep existing streams and events
+        for (size_t q = 0; q < ch.size() && q < chains_.size(); ++q) {
+            ch[q].s = chains_[q].s;
+            ch[q].done = chains_[q].done;
+        }
+        for (size_t q = ch.size(); q < chains_.size(); ++q) {
+            if (chains_[q].s) (void)hipStreamDestroy(chains_[q].s);
+            if (chains_[q].done) (void)hipEventDestroy(chains_[q].done);
+        }
+        chains_ = ch;
+    }
+
+    hipStream_t stream_of(int q, hipStream_t cs) const { return n_chains() > 1 ? chains_[q].s : cs; }
+
+    // the chain streams start after the work queued on cs, and cs continues
+    // after theirs
+    int fork(hipStream_t cs)
+    {
+        if (n_chains() <= 1) return MPM_MAG_OK;
+        if (!fork_ev_) MPM_HIP(hipEventCreateWithFlags(&fork_ev_, hipEventDisableTiming));
+        for (auto& c : chains_) {
+            if (!c.s) MPM_HIP(hipStreamCreateWithFlags(&c.s, hipStreamNonBlocking));
+            if (!c.done) MPM_HIP(hipEventCreateWithFlags(&c.done, hipEventDisableTiming));
+        }
+        MPM_HIP(hipEventRecord(fork_ev_, cs));
+        for (auto& c : chains_) MPM_HIP(hipStreamWaitEvent(c.s, fork_ev_, 0));
+        return MPM_MAG_OK;
+    }
+
+    int join(hipStream_t cs)
+    {
+        if (n_chains() <= 1) return MPM_MAG_OK;
+        for (auto& c : chains_) {
+            MPM_HIP(hipEventRecord(c.done, c.s));
+            MPM_HIP(hipStreamWaitEvent(cs, c.done, 0));
+        }
+        return MPM_MAG_OK;
+    }
+
+    Args<real> args_of(int q)
+    {
+        Args<real> a = args();
+        a.chunk_base = chains_[q].c0;
+        a.active = active_ + 4 * q;
+        a.active_list = active_list_ + (size_t)4 * q * n_cb_;
+        return a;
+    }
+
+    int grid_blocks_of(int q) const { return (int)std::min<int64_t>(chains_[q].ncb, grid_wgs_); }
+
+    // copy of the chain's particle state (all components) from src to dst
+    int copy_state(int q, hipStream_t cs, real* dst, const real* src)
+    {
+        const Chain& c = chains_[q];
+        const size_t pitch = sizeof(real) * (size_t)nalloc_;
+        MPM_HIP(hipMemcpy2DAsync(dst + c.p0, pitch, src + c.p0, pitch, sizeof(real) * (size_t)c.np, Cp::NC,
+                                 hipMemcpyDeviceToDevice, cs));
+        count(K_CKPT, 2.0 * sizeof(real) * (double)c.np * Cp::NC);
+        return MPM_MAG_OK;
+    }
+
+    // step n of the forward for chain q (checkpoints taken before steps
+    // 0, K, 2K, ... when recording)
+    int fwd_step(int q, hipStream_t cs, int n, bool record)
+    {
+        Args<real> a = args_of(q);
+        const int nc = chains_[q].nc;
+        int r;
+        if (n == 0 || !fuse_fwd_) {
+            if (record && n % K_ == 0) {
+                r = copy_state(q, cs, ckpt_slot(n / K_), st_);
+                if (r) return r;
+            }
+            r = launch(K_P2G, cs, nc, kBlock, k_p2g<real, D>, a, (const real*)st_, n, lf(n));
+            if (r) return r;
+        }
+        r = launch(K_GRID, cs, grid_blocks_of(q), kGridBlock, k_grid<real, D>, a, gv_, (real*)nullptr, lf(n));
+        if (r) return r;
+        if (n + 1 < T_ && fuse_fwd_) {
+            // G2P of step n with P2G of step n + 1; v and C are stored only for
+            // the checkpoint taken before step n + 1
+            const bool ck1 = record && (n + 1) % K_ == 0;
+            r = launch(K_G2P2G, cs, nc, kBlock, k_g2p2g<real, D>, a, (const real*)gv_, (const real*)st_, st_, n, 1,
+                       ck1 ? 1 : 0, lf(n), lf(n + 1));
+            if (r) return r;
+            if (ck1) return copy_state(q, cs, ckpt_slot((n + 1) / K_), st_);
+            return MPM_MAG_OK;
+        }
+        return launch(K_G2P, cs, nc, kBlock, k_g2p<real, D>, a, (const real*)gv_, (const real*)st_, st_, n, 1, lf(n));
+    }
+
+    // step n of segment c, recomputed from its checkpoint for chain q, keeping
+    // the step's grid (v, (p, m)) and the next state
+    int recompute_step(int q, hipStream_t cs, int c, int n)
+    {
+        Args<real> a = args_of(q);
+        const int nc = chains_[q].nc;
+        const int s0 = c * K_, s1 = std::min(T_, s0 + K_), j = n - s0;
+        int r;
+        if (n == s0 || !fuse_fwd_) {
+            r = launch(K_P2G, cs, nc, kBlock, k_p2g<real, D>, a, (const real*)seg_state(c, j), n, lf(n));
+            if (r) return r;
+        }
+        r = launch(K_GRID, cs, grid_blocks_of(q), kGridBlock, k_grid<real, D>, a, gv_slot(j), gm_slot(j), lf(n));
+        if (r) return r;
+        if (n + 1 >= s1) return MPM_MAG_OK;
+        if (fuse_fwd_)
+            return launch(K_G2P2G, cs, nc, kBlock, k_g2p2g<real, D>, a, (const real*)gv_slot(j),
+                          (const real*)seg_state(c, j), seg_state(c, j + 1), n, 0, 1, lf(n), lf(n + 1));
+        return launch(K_G2P, cs, nc, kBlock, k_g2p<real, D>, a, (const real*)gv_slot(j), (const real*)seg_state(c, j),
+                      seg_state(c, j + 1), n, 0, lf(n));
+    }
+
+    // scatter lists of the G2P transpose alternate between consecutive steps
+    static int lst(int n) { return 1 + (n & 1); }
+
+    // transpose of the G2P of the last step of segment c
+    int reverse_first(int q, hipStream_t cs, int c)
+    {
+        Args<real> a = args_of(q);
+        const int s0 = c * K_, s1 = std::min(T_, s0 + K_), j = s1 - 1 - s0;
+        return launch(K_G2P_ADJ, cs, chains_[q].nc, kBlock, k_g2p_adj<real, D>, a, (const real*)gv_slot(j),
+                      (const real*)seg_state(c, j), (const real*)next_state(c, j), adj_, (const real*)dloss_,
+                      lst(s1 - 1), lf(s1 - 1));
+    }
+
+    // grid transpose of step n, then the P2G transpose of step n (fused with
+    // the G2P transpose of step n - 1 inside the segment)
+    int reverse_step(int q, hipStream_t cs, int c, int n)
+    {
+        Args<real> a = args_of(q);
+        const int nc = chains_[q].nc;
+        const int s0 = c * K_, s1 = std::min(T_, s0 + K_), j = n - s0;
+        int r = launch(K_GRID_ADJ, cs, grid_blocks_of(q), kGridBlock, k_grid_adj<real, D>, a, (const real*)gm_slot(j),
+                       gpm_, lst(n));
+        if (r) return r;
+        if (n > s0 && fuse_adj_)
+            return launch(K_ADJ_FUSED, cs, nc, kBlock, k_adj_fused<real, D>, a, (const real*)gpm_,
+                          (const real*)seg_state(c, j), n, (const real*)gv_slot(j - 1), (const real*)seg_state(c, j - 1),
+                          adj_, (const real*)dloss_, lst(n), lst(n - 1));
+        r = launch(K_P2G_ADJ, cs, nc, kBlock, k_p2g_adj<real, D>, a, (const real*)gpm_, (const real*)seg_state(c, j),
+                   adj_, n, lst(n));
+        if (r || n == s0) return r;
+        return launch(K_G2P_ADJ, cs, nc, kBlock, k_g2p_adj<real, D>, a, (const real*)gv_slot(j - 1),
+                      (const real*)seg_state(c, j - 1), (const real*)seg_state(c, j), adj_, (const real*)dloss_,
+                      lst(n - 1), lf(s1 - 1));
+    }
+
     // workgroups of the grid kernels, which stride over the active coarse blocks
     int grid_blocks() const { return (int)std::min<int64_t>(n_cb_, grid_wgs_); }
     size_t state_elems() const { return (size_t)Cp::NC * nalloc_; }
@@ -468,6 +614,7 @@ private:
 
         a.use_lds = use_lds_ ? 1 : 0;
         a.box_cap = box_cap_;
+        a.chunk_base = 0;
         return a;
     }
 
@@ -737,8 +884,8 @@ private:
         st |= dalloc(&reg_count_, (size_t)n_cb_);
         st |= dalloc(&reg_list_, (size_t)n_cb_ * Coarse<D>::cap);
         st |= dalloc(&cb_inst_d_, (size_t)n_cb_);
-        st |= dalloc(&active_, 4);
-        st |= dalloc(&active_list_, (size_t)4 * n_cb_);
+        st |= dalloc(&active_, 4 * kMaxChains);
+        st |= dalloc(&active_list_, (size_t)4 * kMaxChains * n_cb_);
         st |= dalloc(&gpm_, (size_t)4 * G_);
         st |= dalloc(&gm_, (size_t)4 * G_);
         st |= dalloc(&gv_, (size_t)4 * G_);
@@ -763,7 +910,7 @@ private:
                           hipMemcpyHostToDevice));
         MPM_HIP(hipMemcpy(cb_inst_d_, cb_inst_h_.data(), sizeof(int) * cb_inst_h_.size(), hipMemcpyHostToDevice));
         MPM_HIP(hipMemset(reg_count_, 0, sizeof(int) * n_cb_));
-        MPM_HIP(hipMemset(active_, 0, sizeof(int) * 4));
+        MPM_HIP(hipMemset(active_, 0, sizeof(int) * 4 * kMaxChains));
         MPM_HIP(hipMemset(gm_, 0, sizeof(real) * 4 * G_));
         MPM_HIP(hipMemset(gv_, 0, sizeof(real) * 4 * G_));
         MPM_HIP(hipMemset(gbar_, 0, sizeof(real) * 4 * G_));
@@ -781,6 +928,13 @@ private:
         drop(gbwd_);
         if (cap_) (void)hipStreamDestroy(cap_);
         cap_ = nullptr;
+        for (auto& c : chains_) {
+            if (c.s) (void)hipStreamDestroy(c.s);
+            if (c.done) (void)hipEventDestroy(c.done);
+        }
+        chains_.clear();
+        if (fork_ev_) (void)hipEventDestroy(fork_ev_);
+        fork_ev_ = nullptr;
         for (void* p : allocs_) (void)hipFree(p);
         allocs_.clear();
         if (ckpt_) (void)hipFree(ckpt_);
@@ -853,6 +1007,9 @@ private:
     // captured graphs: forward step loop (plain, recorded) and reverse sweep
     Graph gfwd_[2], gbwd_;
     hipStream_t cap_ = nullptr;
+    std::vector<Chain> chains_;
+    hipEvent_t fork_ev_ = nullptr;
+    int streams_opt_ = 0;
     int64_t plan_gen_ = 0;
     std::vector<Pending> pending_;
 };

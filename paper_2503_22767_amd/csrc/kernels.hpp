@@ -91,6 +91,7 @@ struct Args {
     int* active_list;    // [4][n_coarse]
     int n_coarse;
     int use_lds;
+    int chunk_base;      // first chunk of the launch (launches may cover a range of instances)
     int box_cap;         // largest block staging box (nodes, <= kBoxCap)
 };
 
@@ -225,7 +226,7 @@ __device__ __forceinline__ void scatter_box(const Args<real>& a, const InstDev<r
     __shared__ float s_bmax[kWaves][4];
     const int t = threadIdx.x;
     const int w = t >> 6;
-    const int c = blockIdx.x;
+    const int c = a.chunk_base + blockIdx.x;
     const int n_grid = I.n_grid;
     // bounding boxes of the wave and of the block
     int wlo[3] = {0, 0, 0}, wext[3] = {1, 1, 1};
@@ -858,7 +859,7 @@ __device__ __forceinline__ void p2g_scatter(const Args<real>& a, const InstDev<r
     real B[D];
     field_at<real, D>(I, a.bprog, step, B);
     int org[3];
-    chunk_origin(a.corig, blockIdx.x, org);
+    chunk_origin(a.corig, a.chunk_base + blockIdx.x, org);
     Stencil<real, D> Sx;
     int err = make_stencil<real, D>(q.x, org, I.inv_dx, I.n_grid, Sx);
     if (active && err) atomicOr(a.err, err);
@@ -912,11 +913,11 @@ template <typename real, int D>
 __global__ __launch_bounds__(kBlock) void k_p2g(Args<real> a, const real* __restrict__ st, int step, int list)
 {
     __shared__ typename LdsAcc<real>::T lds[4 * kBoxCap];
-    const ChunkDev ch = a.chunks[blockIdx.x];
+    const ChunkDev ch = a.chunks[a.chunk_base + blockIdx.x];
     const InstDev<real>& I = a.inst[ch.inst];
     const int t = threadIdx.x;
     const bool active = t < ch.count;
-    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+    const int64_t i = (int64_t)(a.chunk_base + blockIdx.x) * kBlock + t;
     Particle<real, D> q;
     if (active)
         load_particle<real, D>(st, a.x0s, a.nalloc, i, q);
@@ -1140,16 +1141,16 @@ template <typename real, int D>
 __global__ __launch_bounds__(kBlock) void k_g2p(Args<real> a, const real* __restrict__ gv_in, const real* sin,
                                                 real* sout, int step, int traj_on, int list_done)
 {
-    const ChunkDev ch = a.chunks[blockIdx.x];
+    const ChunkDev ch = a.chunks[a.chunk_base + blockIdx.x];
     const InstDev<real>& I = a.inst[ch.inst];
     const int t = threadIdx.x;
     const bool active = t < ch.count;
-    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+    const int64_t i = (int64_t)(a.chunk_base + blockIdx.x) * kBlock + t;
     if (blockIdx.x == 0 && t == 0) a.active[list_done] = 0;   // the grid update has consumed this list
     Particle<real, D> q;
     if (active) {
         int org[3];
-        chunk_origin(a.corig, blockIdx.x, org);
+        chunk_origin(a.corig, a.chunk_base + blockIdx.x, org);
         real x1[D];
         const int err = g2p_update<real, D>(a, I, i, gv_in, sin, org, q, x1);
         if (err) atomicOr(a.err, err);
@@ -1168,17 +1169,17 @@ __global__ __launch_bounds__(kBlock, 5) void k_g2p2g(Args<real> a, const real* _
 {
     using Cp = Comp<D>;
     __shared__ typename LdsAcc<real>::T lds[4 * kBoxCap];
-    const ChunkDev ch = a.chunks[blockIdx.x];
+    const ChunkDev ch = a.chunks[a.chunk_base + blockIdx.x];
     const InstDev<real>& I = a.inst[ch.inst];
     const int t = threadIdx.x;
     const bool active = t < ch.count;
-    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+    const int64_t i = (int64_t)(a.chunk_base + blockIdx.x) * kBlock + t;
     const int64_t S = a.nalloc;
     if (blockIdx.x == 0 && t == 0) a.active[list_done] = 0;
     Particle<real, D> q;
     if (active) {
         int org[3];
-        chunk_origin(a.corig, blockIdx.x, org);
+        chunk_origin(a.corig, a.chunk_base + blockIdx.x, org);
         real x1[D];
         const int err = g2p_update<real, D>(a, I, i, gv_in, sin, org, q, x1);
         if (err) atomicOr(a.err, err);
@@ -1215,10 +1216,10 @@ template <typename real, int D>
 __global__ __launch_bounds__(kBlock) void k_loss_sums(Args<real> a, const real* st, const real* x0s,
                                                       const real* target, const uint8_t* mask, int has_target)
 {
-    const ChunkDev ch = a.chunks[blockIdx.x];
+    const ChunkDev ch = a.chunks[a.chunk_base + blockIdx.x];
     const InstDev<real>& I = a.inst[ch.inst];
     const int t = threadIdx.x;
-    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+    const int64_t i = (int64_t)(a.chunk_base + blockIdx.x) * kBlock + t;
     const int64_t S = a.nalloc;
     double v[5] = {0, 0, 0, 0, 0};
     if (t < ch.count) {
@@ -1278,11 +1279,11 @@ __global__ __launch_bounds__(kBlock) void k_seed(Args<real> a, const real* st, r
                                                  const real* target, const uint8_t* mask, const real* dloss)
 {
     using Cp = Comp<D>;
-    const ChunkDev ch = a.chunks[blockIdx.x];
+    const ChunkDev ch = a.chunks[a.chunk_base + blockIdx.x];
     const InstDev<real>& I = a.inst[ch.inst];
     const int t = threadIdx.x;
     if (t >= ch.count) return;
-    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+    const int64_t i = (int64_t)(a.chunk_base + blockIdx.x) * kBlock + t;
     const int64_t S = a.nalloc;
     const double* acc = a.acc + ch.inst * kAccCount;
     const double dl = (double)dloss[ch.inst];
@@ -1370,7 +1371,7 @@ __device__ __forceinline__ void g2p_adj_phase(const Args<real>& a, const InstDev
         }
     }
     int org[3];
-    chunk_origin(a.corig, blockIdx.x, org);
+    chunk_origin(a.corig, a.chunk_base + blockIdx.x, org);
     Stencil<real, D> Sx;
     make_stencil<real, D>(x, org, I.inv_dx, I.n_grid, Sx);
     const real* gv = gv_in + 4 * (int64_t)I.grid_off;
@@ -1511,11 +1512,11 @@ __global__ __launch_bounds__(kBlock) void k_g2p_adj(Args<real> a, const real* __
 {
     using Cp = Comp<D>;
     __shared__ typename LdsAcc<real>::T lds[4 * kBoxCap];
-    const ChunkDev ch = a.chunks[blockIdx.x];
+    const ChunkDev ch = a.chunks[a.chunk_base + blockIdx.x];
     const InstDev<real>& I = a.inst[ch.inst];
     const int t = threadIdx.x;
     const bool active = t < ch.count;
-    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+    const int64_t i = (int64_t)(a.chunk_base + blockIdx.x) * kBlock + t;
     const int64_t S = a.nalloc;
     if (blockIdx.x == 0 && t == 0) a.active[list_fwd_done] = 0;   // the grid update has consumed this P2G list
     AdjState<real, D> A1;
@@ -1633,7 +1634,7 @@ __device__ __forceinline__ void p2g_adj_phase(const Args<real>& a, const InstDev
     Particle<real, D> q;
     real phi = 0, br[D];
     int org[3];
-    chunk_origin(a.corig, blockIdx.x, org);
+    chunk_origin(a.corig, a.chunk_base + blockIdx.x, org);
     Stencil<real, D> Sx;
     if (active) {
         load_particle<real, D>(st, a.x0s, S, i, q);
@@ -1808,11 +1809,11 @@ __global__ __launch_bounds__(kBlock, sizeof(real) == 4 ? 3 : 2) void k_p2g_adj(A
 {
     using Cp = Comp<D>;
     __shared__ real lds[4 * kBoxCap];
-    const ChunkDev ch = a.chunks[blockIdx.x];
+    const ChunkDev ch = a.chunks[a.chunk_base + blockIdx.x];
     const InstDev<real>& I = a.inst[ch.inst];
     const int t = threadIdx.x;
     const bool active = t < ch.count;
-    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+    const int64_t i = (int64_t)(a.chunk_base + blockIdx.x) * kBlock + t;
     const int64_t S = a.nalloc;
     if (blockIdx.x == 0 && t == 0) a.active[list_done] = 0;   // the grid transpose has consumed this list
     AdjState<real, D> A0;
@@ -1842,11 +1843,11 @@ __global__ __launch_bounds__(kBlock, sizeof(real) == 4 ? 4 : 2) void k_adj_fused
     const real* st_prev, real* adj, const real* dloss, int list_done, int list_next)
 {
     __shared__ typename LdsAcc<real>::T lds[4 * kBoxCap];
-    const ChunkDev ch = a.chunks[blockIdx.x];
+    const ChunkDev ch = a.chunks[a.chunk_base + blockIdx.x];
     const InstDev<real>& I = a.inst[ch.inst];
     const int t = threadIdx.x;
     const bool active = t < ch.count;
-    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+    const int64_t i = (int64_t)(a.chunk_base + blockIdx.x) * kBlock + t;
     if (blockIdx.x == 0 && t == 0) a.active[list_done] = 0;
     AdjState<real, D> A;
     p2g_adj_phase<real, D>(a, I, ch.inst, active, i, gpm_in, st_n, adj, step, A, reinterpret_cast<real*>(lds));
@@ -1868,13 +1869,13 @@ __global__ __launch_bounds__(kBlock) void k_gather(Args<real> a, const int* __re
 {
     using Cp = Comp<D>;
     __shared__ int s_min[kWaves][3];
-    const ChunkDev ch = a.chunks[blockIdx.x];
+    const ChunkDev ch = a.chunks[a.chunk_base + blockIdx.x];
     const InstDev<real>& I = a.inst[ch.inst];
     const int t = threadIdx.x;
     const bool active = t < ch.count;
-    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+    const int64_t i = (int64_t)(a.chunk_base + blockIdx.x) * kBlock + t;
     const int64_t S = a.nalloc;
-    const int64_t local = (int64_t)(blockIdx.x - I.chunk_off) * kBlock + t;
+    const int64_t local = (int64_t)(a.chunk_base + blockIdx.x - I.chunk_off) * kBlock + t;
     const int q = active ? sorted_ids[caller_start[ch.inst] + local] : 0;
     // origin cell of the chunk: lowest cell index over its particles per axis
     double xa[D];
@@ -1898,7 +1899,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(Args<real> a, const int* __re
         for (int w = 1; w < kWaves; ++w) m = min(m, s_min[w][k]);
         org[k] = (m == 0x3fffffff) ? 0 : m;
     }
-    if (t == 0) corig[blockIdx.x] = make_int4(org[0], org[1], org[2], 0);
+    if (t == 0) corig[a.chunk_base + blockIdx.x] = make_int4(org[0], org[1], org[2], 0);
     // inputs must be finite: a NaN mass would otherwise read as an empty node
     if (blockIdx.x == 0)
         for (int64_t j = t; j < n_prog; j += kBlock)
@@ -1939,15 +1940,15 @@ template <typename real, int D>
 __global__ __launch_bounds__(kBlock) void k_scatter_out(Args<real> a, const int* __restrict__ id, const real* st,
                                                         real* x_out, real* g_phi, real* g_br)
 {
-    const ChunkDev ch = a.chunks[blockIdx.x];
+    const ChunkDev ch = a.chunks[a.chunk_base + blockIdx.x];
     const int t = threadIdx.x;
     if (t >= ch.count) return;
-    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+    const int64_t i = (int64_t)(a.chunk_base + blockIdx.x) * kBlock + t;
     const int64_t S = a.nalloc;
     const int64_t q = id[i];
     const InstDev<real>& I = a.inst[ch.inst];
     int org[3];
-    chunk_origin(a.corig, blockIdx.x, org);
+    chunk_origin(a.corig, a.chunk_base + blockIdx.x, org);
     if (x_out)
 #pragma unroll
         for (int k = 0; k < D; ++k)

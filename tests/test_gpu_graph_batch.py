@@ -153,3 +153,23 @@ def test_batched_instances_match_oracle():
         sub = dict(x=got["x"][sl], loss=got["loss"][k:k + 1], g_density=got["g_density"][sl],
                    g_br=got["g_br"][sl], g_b_prog=got["g_b_prog"][sp])
         compare(sub, ref, pos_tol=1e-4, grad_tol=1e-3, label=f"batch instance {k} (N={inst.n})")
+
+
+@pytest.mark.parametrize("streams", [2, 3])
+def test_instance_groups_on_streams_match_one_stream(streams):
+    """Instances advanced in groups on separate streams give the one-stream
+    results (FP64, only summation order may differ) and the oracle's."""
+    insts = [W.make_tiny(seed=30, dim=2, n_steps=18, loss_kind=W.LOSS_COM_DISP, floor=True, gravity=1.0,
+                         size=(0.3, 0.2, 0.25), n_grid=16, n_segments=3)]
+    insts += [W.make_tiny(seed=40 + k, dim=2, n_steps=18, loss_kind=W.LOSS_FINAL_MSE, clamp=True,
+                          size=(0.3 + 0.05 * k, 0.15, 0.2), n_grid=16 + 8 * k, n_segments=2) for k in range(2)]
+    one = gpu_run(insts, precision=8, options={"streams": 1})
+    many = gpu_run(insts, precision=8, options={"streams": streams})
+    errs = _max_rel(many, one)
+    log("streams", streams, {k: f"{v:.2e}" for k, v in errs.items()})
+    assert all(v <= 1e-12 for v in errs.values()), errs
+    ref = oracle_run(insts)
+    compare(many, ref, pos_tol=1e-10, grad_tol=1e-9, loss_tol=1e-9, label=f"streams={streams} fp64")
+    # and with graph replay of the grouped launches
+    g = gpu_run(insts, precision=4, options={"streams": streams, "graph": 1})
+    compare(g, ref, pos_tol=1e-4, grad_tol=1e-3, label=f"streams={streams} graph fp32")
