@@ -148,9 +148,12 @@ def roofline(sim, tens, dloss, precision, streams=0):
         if not v["launches"]:
             continue
         t = v["ms"] / v["launches"] * 1e-3
+        if t <= 0.0:   # counted but not timed (the checkpoint copies are runtime copies)
+            per_kernel[k] = dict(launches=v["launches"], avg_us=None, total_ms=None, gbs=None, tflops=None)
+            continue
         per_kernel[k] = dict(launches=v["launches"], avg_us=t * 1e6, total_ms=v["ms"],
-                             gbs=(v["bytes"] / v["launches"]) / max(1e-12, t) / 1e9 if v["bytes"] else None,
-                             tflops=(v["flops"] / v["launches"]) / max(1e-12, t) / 1e12 if v["flops"] else None)
+                             gbs=(v["bytes"] / v["launches"]) / t / 1e9 if v["bytes"] else None,
+                             tflops=(v["flops"] / v["launches"]) / t / 1e12 if v["flops"] else None)
     return rl, per_kernel
 
 
