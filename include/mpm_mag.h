@@ -156,6 +156,10 @@ const char* mpm_mag_last_error(const mpm_mag* h);
  *   "fuse_fwd"      1: G2P of step n and P2G of step n+1 in one kernel (default), 0: separate
  *   "fuse_adj"      1: P2G transpose of step n and G2P transpose of step n-1 in one
  *                   kernel (default), 0: separate
+ *   "lane_sort"     1: at the start of every checkpoint segment, group the lanes of each
+ *                   chunk of the forward kernels by the particles' current stencil base
+ *                   cell (default), so the scatter's lanes that share a base stay
+ *                   adjacent; 0: slot order. Results do not depend on it.
  *   "ckpt_every"    checkpoint spacing K (0: automatic); takes effect at the next recorded rollout
  * Returns EINVAL for an unknown key or value.
  */

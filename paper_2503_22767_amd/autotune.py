@@ -10,6 +10,10 @@ The knobs are options of the library:
   fuse_adj    the same pairing for the transposed kernels of the reverse sweep
   streams     instance groups advanced on separate streams (0: automatic)
 
+The lane order option (lane_sort) is left at the library default: it pays
+once particles have moved across cell boundaries, which a short timing
+horizon does not reach.
+
 Each candidate setting is timed on the workload's own instances over a short
 horizon (20 steps by default): a recorded rollout and its backward, median of
 a few repetitions after one untimed run, which also sorts and captures. The

@@ -223,6 +223,18 @@ public:
             ++plan_gen_;   // changes the captured launch sequence
             return MPM_MAG_OK;
         }
+        if (k == "lane_sort") {
+            lane_sort_ = value != 0;
+            ++plan_gen_;   // changes the captured launch sequence
+            if (!lane_sort_) {
+                // back to the identity order, once queued work has finished with it
+                MPM_HIP(hipDeviceSynchronize());
+                std::vector<uint8_t> ident((size_t)nalloc_);
+                for (size_t j = 0; j < ident.size(); ++j) ident[j] = (uint8_t)(j % kBlock);
+                MPM_HIP(hipMemcpy(lperm_, ident.data(), ident.size(), hipMemcpyHostToDevice));
+            }
+            return MPM_MAG_OK;
+        }
         if (k == "p2g_lds") {
             use_lds_ = value != 0;
             ++plan_gen_;   // kernel arguments of captured launches
@@ -478,6 +490,10 @@ private:
         Args<real> a = args_of(q);
         const int nc = chains_[q].nc;
         int r;
+        if (n % lane_every() == 0) {
+            r = sort_lanes(q, cs, st_);
+            if (r) return r;
+        }
         if (n == 0 || !fuse_fwd_) {
             if (record && n % K_ == 0) {
                 r = copy_state(q, cs, ckpt_slot(n / K_), st_);
@@ -509,6 +525,10 @@ private:
         const int nc = chains_[q].nc;
         const int s0 = c * K_, s1 = std::min(T_, s0 + K_), j = n - s0;
         int r;
+        if (n == s0) {
+            r = sort_lanes(q, cs, seg_state(c, 0));
+            if (r) return r;
+        }
         if (n == s0 || !fuse_fwd_) {
             r = launch(K_P2G, cs, nc, kBlock, k_p2g<real, D>, a, (const real*)seg_state(c, j), n, lf(n));
             if (r) return r;
@@ -521,6 +541,21 @@ private:
                           (const real*)seg_state(c, j), seg_state(c, j + 1), n, 0, 1, lf(n), lf(n + 1));
         return launch(K_G2P, cs, nc, kBlock, k_g2p<real, D>, a, (const real*)gv_slot(j), (const real*)seg_state(c, j),
                       seg_state(c, j + 1), n, 0, lf(n));
+    }
+
+    // Lane order of chain q's chunks by the stencil base cells of state st,
+    // used by the forward particle kernels. It is refreshed at the start of
+    // every checkpoint segment, in the forward pass and in the recompute of
+    // the reverse sweep.
+    int lane_every() const
+    {
+        return K_ > 0 ? K_ : std::max(1, (int)std::ceil(std::sqrt((double)std::max(1, T_))));
+    }
+
+    int sort_lanes(int q, hipStream_t cs, const real* st)
+    {
+        if (!lane_sort_) return MPM_MAG_OK;
+        return launch(K_SORT, cs, chains_[q].nc, kBlock, k_lane_sort<real, D>, args_of(q), st, lperm_);
     }
 
     // scatter lists of the G2P transpose alternate between consecutive steps
@@ -615,6 +650,7 @@ private:
         a.use_lds = use_lds_ ? 1 : 0;
         a.box_cap = box_cap_;
         a.chunk_base = 0;
+        a.lperm = lperm_;
         return a;
     }
 
@@ -877,6 +913,7 @@ private:
         st |= dalloc(&gphi_, (size_t)nalloc_);
         st |= dalloc(&gbr_, (size_t)D * nalloc_);
         st |= dalloc(&mask_, (size_t)nalloc_);
+        st |= dalloc(&lperm_, (size_t)nalloc_);
         st |= dalloc(&id_, (size_t)nalloc_);
         st |= dalloc(&corig_, (size_t)n_chunks_);
         st |= dalloc(&part_, (size_t)n_chunks_ * kBoxCap * 4);
@@ -917,6 +954,12 @@ private:
         MPM_HIP(hipMemset(st_, 0, state_bytes()));
         MPM_HIP(hipMemset(adj_, 0, state_bytes()));
         MPM_HIP(hipMemset(tgt_, 0, sizeof(real) * D * nalloc_));
+        {
+            // identity lane order until the first rollout sorts the lanes
+            std::vector<uint8_t> ident((size_t)nalloc_);
+            for (size_t j = 0; j < ident.size(); ++j) ident[j] = (uint8_t)(j % kBlock);
+            MPM_HIP(hipMemcpy(lperm_, ident.data(), ident.size(), hipMemcpyHostToDevice));
+        }
         MPM_HIP(hipDeviceSynchronize());
         return MPM_MAG_OK;
     }
@@ -969,6 +1012,7 @@ private:
     real *st_ = nullptr, *adj_ = nullptr, *x0s_ = nullptr, *tgt_ = nullptr, *br_ = nullptr, *phi_ = nullptr;
     real *gphi_ = nullptr, *gbr_ = nullptr, *gm_ = nullptr, *gv_ = nullptr, *gbar_ = nullptr, *bprog_ = nullptr;
     uint8_t* mask_ = nullptr;
+    uint8_t* lperm_ = nullptr;   // lane order of the particle kernels (k_lane_sort)
     int* id_ = nullptr;
     int4* corig_ = nullptr;
     real* part_ = nullptr;
@@ -1001,7 +1045,7 @@ private:
     // options
     bool graph_ = false, timing_ = false, use_lds_ = true;
     int box_cap_ = kBoxCap, grid_wgs_ = 2048;
-    bool fuse_adj_ = true, fuse_fwd_ = true;
+    bool fuse_adj_ = true, fuse_fwd_ = true, lane_sort_ = true;
     std::vector<hipEvent_t> events_;
     size_t ev_used_ = 0;
     // captured graphs: forward step loop (plain, recorded) and reverse sweep

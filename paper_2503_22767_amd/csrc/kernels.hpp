@@ -93,7 +93,22 @@ struct Args {
     int use_lds;
     int chunk_base;      // first chunk of the launch (launches may cover a range of instances)
     int box_cap;         // largest block staging box (nodes, <= kBoxCap)
+    const uint8_t* lperm;  // [nalloc]: lane t of chunk c works on slot c * kBlock + lperm[c * kBlock + t]
 };
+
+// Slot of the particle that lane t of this block works on. The forward
+// particle kernels take a chunk's particles grouped by their current stencil
+// base cell (k_lane_sort), so that lanes sharing a base are adjacent and the
+// scatter's segments stay long after particles change cells; every order gives
+// the same sums. The transposed kernels keep slot order: they move more data
+// per particle, and for them the permuted loads cost more than the longer
+// segments save.
+template <typename real>
+__device__ __forceinline__ int64_t lane_slot(const Args<real>& a, int t)
+{
+    const int64_t c0 = (int64_t)(a.chunk_base + blockIdx.x) * kBlock;
+    return c0 + a.lperm[c0 + t];
+}
 
 // --------------------------------------------------------------------------
 // block scatter through LDS
@@ -909,6 +924,61 @@ __device__ __forceinline__ void neutral_particle(Particle<real, D>& q)
     }
 }
 
+// Orders the lanes of each chunk so that particles sharing their current
+// stencil base cell are adjacent, moving as few as possible: a particle's
+// group is led by the first slot of the chunk with the same base cell, groups
+// keep the order of their leaders and members their slot order. While the
+// particles of each cell are contiguous (as the initial sort leaves them) the
+// order is the identity. Writes the lane order used by the particle kernels.
+// st: the particle state.
+template <typename real, int D>
+__global__ __launch_bounds__(kBlock) void k_lane_sort(Args<real> a, const real* st, uint8_t* lperm)
+{
+    __shared__ uint32_t cell[kBlock];
+    __shared__ int lead[kBlock];
+    const int c = a.chunk_base + blockIdx.x;
+    const ChunkDev ch = a.chunks[c];
+    const InstDev<real>& I = a.inst[ch.inst];
+    const int t = threadIdx.x;
+    const int n = ch.count;
+    const int64_t c0 = (int64_t)c * kBlock;
+    const int64_t S = a.nalloc;
+    uint32_t key = 0xFFFFFFFFu;
+    if (t < n) {
+        int org[3];
+        chunk_origin(a.corig, c, org);
+        real x[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) x[k] = a.x0s[k * S + c0 + t] + st[(Comp<D>::X + k) * S + c0 + t];
+        Stencil<real, D> Sx;
+        make_stencil<real, D>(x, org, I.inv_dx, I.n_grid, Sx);
+        const uint32_t g = (uint32_t)I.n_grid;
+        key = (uint32_t)Sx.base[0] + g * ((uint32_t)Sx.base[1] + (D == 3 ? g * (uint32_t)Sx.base[D - 1] : 0u));
+    }
+    cell[t] = key;
+    __syncthreads();
+    int first = t;
+    if (t < n) {
+        for (int j = 0; j < t; ++j)
+            if (cell[j] == key) {
+                first = j;
+                break;
+            }
+    }
+    lead[t] = first;
+    __syncthreads();
+    if (t < n) {
+        int rank = 0;
+        for (int j = 0; j < n; ++j) {
+            const int fj = lead[j];
+            rank += (fj < first || (fj == first && j < t)) ? 1 : 0;
+        }
+        lperm[c0 + rank] = (uint8_t)t;
+    } else {
+        lperm[c0 + t] = (uint8_t)t;
+    }
+}
+
 template <typename real, int D>
 __global__ __launch_bounds__(kBlock) void k_p2g(Args<real> a, const real* __restrict__ st, int step, int list)
 {
@@ -917,7 +987,7 @@ __global__ __launch_bounds__(kBlock) void k_p2g(Args<real> a, const real* __rest
     const InstDev<real>& I = a.inst[ch.inst];
     const int t = threadIdx.x;
     const bool active = t < ch.count;
-    const int64_t i = (int64_t)(a.chunk_base + blockIdx.x) * kBlock + t;
+    const int64_t i = lane_slot(a, t);
     Particle<real, D> q;
     if (active)
         load_particle<real, D>(st, a.x0s, a.nalloc, i, q);
@@ -1145,7 +1215,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(Args<real> a, const real* __rest
     const InstDev<real>& I = a.inst[ch.inst];
     const int t = threadIdx.x;
     const bool active = t < ch.count;
-    const int64_t i = (int64_t)(a.chunk_base + blockIdx.x) * kBlock + t;
+    const int64_t i = lane_slot(a, t);
     if (blockIdx.x == 0 && t == 0) a.active[list_done] = 0;   // the grid update has consumed this list
     Particle<real, D> q;
     if (active) {
@@ -1173,7 +1243,7 @@ __global__ __launch_bounds__(kBlock, 5) void k_g2p2g(Args<real> a, const real* _
     const InstDev<real>& I = a.inst[ch.inst];
     const int t = threadIdx.x;
     const bool active = t < ch.count;
-    const int64_t i = (int64_t)(a.chunk_base + blockIdx.x) * kBlock + t;
+    const int64_t i = lane_slot(a, t);
     const int64_t S = a.nalloc;
     if (blockIdx.x == 0 && t == 0) a.active[list_done] = 0;
     Particle<real, D> q;

@@ -10,7 +10,8 @@ from gpu_util import compare, gpu_run, log, oracle_run
 pytestmark = pytest.mark.gpu
 
 OPTION_CASES = [("sort_curve", 1), ("sort_curve", 2), ("box_cap", 64), ("box_cap", 256),
-                ("grid_wgs", 16), ("graph", 1), ("fuse_fwd", 0), ("fuse_adj", 0), ("streams", 2)]
+                ("grid_wgs", 16), ("graph", 1), ("fuse_fwd", 0), ("fuse_adj", 0), ("streams", 2),
+                ("lane_sort", 0)]
 
 
 def _case(dim):

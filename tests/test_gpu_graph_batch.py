@@ -173,3 +173,23 @@ def test_instance_groups_on_streams_match_one_stream(streams):
     # and with graph replay of the grouped launches
     g = gpu_run(insts, precision=4, options={"streams": streams, "graph": 1})
     compare(g, ref, pos_tol=1e-4, grad_tol=1e-3, label=f"streams={streams} graph fp32")
+
+
+def test_lane_order_leaves_fp32_results_unchanged():
+    """The lane order of the particle kernels only changes which lane works on
+    which particle: in FP32 the grid sums are exact integers, so positions and
+    per-particle gradients are bit-identical with and without it, and the
+    block-summed loss and program gradient agree to FP64 rounding. The 3D
+    block falls under gravity for 60 steps, so particles change cells and the
+    order is not the identity."""
+    inst = W.make_tiny(seed=21, dim=3, n_steps=60, loss_kind=W.LOSS_COM_DISP, floor=True, gravity=4.0,
+                       size=(0.3, 0.2, 0.25), n_grid=16, n_segments=4)
+    on = gpu_run([inst], precision=4, options={"lane_sort": 1, "ckpt_every": 7})
+    off = gpu_run([inst], precision=4, options={"lane_sort": 0, "ckpt_every": 7})
+    for k in ("x", "g_density", "g_br"):
+        assert np.array_equal(on[k], off[k]), (k, float(np.max(np.abs(on[k] - off[k]))))
+    errs = _max_rel(dict(loss=on["loss"], g_b_prog=on["g_b_prog"]), dict(loss=off["loss"], g_b_prog=off["g_b_prog"]))
+    log("lane order on/off", {k: f"{v:.2e}" for k, v in errs.items()})
+    assert all(v <= 1e-6 for v in errs.values()), errs
+    ref = oracle_run([inst])
+    compare(on, ref, pos_tol=1e-4, grad_tol=1e-3, label="lane order fp32")
