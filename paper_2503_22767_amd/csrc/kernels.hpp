@@ -929,50 +929,94 @@ __device__ __forceinline__ void neutral_particle(Particle<real, D>& q)
 // group is led by the first slot of the chunk with the same base cell, groups
 // keep the order of their leaders and members their slot order. While the
 // particles of each cell are contiguous (as the initial sort leaves them) the
-// order is the identity. Writes the lane order used by the particle kernels.
-// st: the particle state.
+// order is the identity. Groups are found in an LDS table over the chunk's box
+// of base cells; a chunk whose box exceeds the table keeps slot order. Writes
+// the lane order used by the particle kernels. st: the particle state.
+constexpr int kLaneSortCells = 2048;
 template <typename real, int D>
 __global__ __launch_bounds__(kBlock) void k_lane_sort(Args<real> a, const real* st, uint8_t* lperm)
 {
-    __shared__ uint32_t cell[kBlock];
-    __shared__ int lead[kBlock];
+    __shared__ int lead[kLaneSortCells];   // first slot of each cell of the box
+    __shared__ int cnt[kLaneSortCells];    // particles per cell
+    __shared__ int cellof[kBlock];         // box cell of each slot
+    __shared__ int scan[kBlock];
+    __shared__ int s_bb[kWaves][6];
     const int c = a.chunk_base + blockIdx.x;
     const ChunkDev ch = a.chunks[c];
     const InstDev<real>& I = a.inst[ch.inst];
     const int t = threadIdx.x;
     const int n = ch.count;
+    const bool active = t < n;
     const int64_t c0 = (int64_t)c * kBlock;
     const int64_t S = a.nalloc;
-    uint32_t key = 0xFFFFFFFFu;
-    if (t < n) {
+    int base[D];
+    {
         int org[3];
         chunk_origin(a.corig, c, org);
         real x[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) x[k] = a.x0s[k * S + c0 + t] + st[(Comp<D>::X + k) * S + c0 + t];
+        for (int k = 0; k < D; ++k) x[k] = active ? a.x0s[k * S + c0 + t] + st[(Comp<D>::X + k) * S + c0 + t] : real(0.5);
         Stencil<real, D> Sx;
         make_stencil<real, D>(x, org, I.inv_dx, I.n_grid, Sx);
-        const uint32_t g = (uint32_t)I.n_grid;
-        key = (uint32_t)Sx.base[0] + g * ((uint32_t)Sx.base[1] + (D == 3 ? g * (uint32_t)Sx.base[D - 1] : 0u));
+#pragma unroll
+        for (int k = 0; k < D; ++k) base[k] = Sx.base[k];
     }
-    cell[t] = key;
-    __syncthreads();
-    int first = t;
-    if (t < n) {
-        for (int j = 0; j < t; ++j)
-            if (cell[j] == key) {
-                first = j;
-                break;
-            }
-    }
-    lead[t] = first;
-    __syncthreads();
-    if (t < n) {
-        int rank = 0;
-        for (int j = 0; j < n; ++j) {
-            const int fj = lead[j];
-            rank += (fj < first || (fj == first && j < t)) ? 1 : 0;
+    // the block's box of base cells
+    int wlo[D], whi[D];
+    wave_bounds<D>(base, active, wlo, whi);
+    if ((t & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            s_bb[t >> 6][k] = wlo[k];
+            s_bb[t >> 6][3 + k] = whi[k];
         }
+    __syncthreads();
+    int lo[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
+    int vol = 1;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        int l = s_bb[0][k], h = s_bb[0][3 + k];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) {
+            l = min(l, s_bb[w][k]);
+            h = max(h, s_bb[w][3 + k]);
+        }
+        lo[k] = l;
+        ext[k] = max(h - l + 1, 1);
+        vol *= ext[k];
+    }
+    if (vol > kLaneSortCells) {   // block-uniform
+        lperm[c0 + t] = (uint8_t)t;
+        return;
+    }
+    for (int j = t; j < vol; j += kBlock) {
+        lead[j] = kBlock;
+        cnt[j] = 0;
+    }
+    __syncthreads();
+    int li = -1;
+    if (active) {
+        li = (base[0] - lo[0]) + ext[0] * ((base[1] - lo[1]) + (D == 3 ? ext[1] * (base[D - 1] - lo[D - 1]) : 0));
+        atomicMin(&lead[li], t);
+        atomicAdd(&cnt[li], 1);
+    }
+    cellof[t] = li;
+    __syncthreads();
+    const int first = active ? lead[li] : t;
+    // offsets of the groups: exclusive prefix over slots of the leaders' group sizes
+    int v = (active && first == t) ? cnt[li] : 0;
+    scan[t] = v;
+    __syncthreads();
+    for (int d = 1; d < kBlock; d <<= 1) {
+        const int u = t >= d ? scan[t - d] : 0;
+        __syncthreads();
+        scan[t] += u;
+        __syncthreads();
+    }
+    if (active) {
+        // members of the group at slots first .. t - 1 come before this one
+        int rank = scan[first] - cnt[li];
+        for (int j = first; j < t; ++j) rank += cellof[j] == li ? 1 : 0;
         lperm[c0 + rank] = (uint8_t)t;
     } else {
         lperm[c0 + t] = (uint8_t)t;
