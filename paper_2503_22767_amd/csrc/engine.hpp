@@ -525,7 +525,7 @@ private:
         const int nc = chains_[q].nc;
         const int s0 = c * K_, s1 = std::min(T_, s0 + K_), j = n - s0;
         int r;
-        if (n == s0) {
+        if (n == s0 && s0 % lane_every() == 0) {
             r = sort_lanes(q, cs, seg_state(c, 0));
             if (r) return r;
         }
@@ -544,12 +544,18 @@ private:
     }
 
     // Lane order of chain q's chunks by the stencil base cells of state st,
-    // used by the forward particle kernels. It is refreshed at the start of
-    // every checkpoint segment, in the forward pass and in the recompute of
-    // the reverse sweep.
+    // used by the forward particle kernels. It is refreshed every lane_every()
+    // steps: in the forward pass, and in the recompute of the reverse sweep
+    // at the segments that start on those steps (the other segments use the
+    // last order made, which is as valid: every order gives the same sums).
+    // steps between lane sorts: the smallest multiple of the checkpoint
+    // spacing that is at least kLaneSortSteps (an order stays useful for a few
+    // hundred steps; a sort is one more launch)
+    static constexpr int kLaneSortSteps = 128;
     int lane_every() const
     {
-        return K_ > 0 ? K_ : std::max(1, (int)std::ceil(std::sqrt((double)std::max(1, T_))));
+        const int k = K_ > 0 ? K_ : std::max(1, (int)std::ceil(std::sqrt((double)std::max(1, T_))));
+        return k * ((kLaneSortSteps + k - 1) / k);
     }
 
     int sort_lanes(int q, hipStream_t cs, const real* st)
