@@ -345,9 +345,14 @@ __device__ __forceinline__ void scatter_box(const Args<real>& a, const InstDev<r
 #pragma unroll
         for (int j = 0; j < 4; ++j) msk[j] = seg_d >= (1 << j) ? -1 : 0;
         // FP32 (integer sums): a segment's sum is the row prefix at its tail
-        // minus the row prefix just before its head, so the tail adds the one
-        // and the head subtracts the other (exact in modular arithmetic)
-        const bool head_sub = active && seg_d == 0 && (t & 15) != 0;
+        // minus the row prefix just before its head, which is the prefix of
+        // the previous segment's tail. So every tail adds its prefix at its
+        // own node and, unless it ends the row or the active lanes, subtracts
+        // the same prefix at the next lane's node (exact in modular
+        // arithmetic); the next lane's node offset comes by one row shift
+        const int next_active = __builtin_amdgcn_update_dpp(0, active ? 1 : 0, 0x101, 0xF, 0xF, true);   // row_shl:1
+        const bool sub_next = emit && (t & 15) != 15 && next_active != 0;
+        const int lrel_next = __builtin_amdgcn_update_dpp(0, lrel, 0x101, 0xF, 0xF, true);
         real sq[NV];
 #pragma unroll
         for (int q = 0; q < NV; ++q) sq[q] = scl[value_slot<D, NV>(q)];
@@ -365,16 +370,16 @@ __device__ __forceinline__ void scatter_box(const Args<real>& a, const InstDev<r
             const int li = lrel + oa[0] + bext[0] * (oa[1] + (D == 3 ? bext[1] * oa[D - 1] : 0));
             if constexpr (sizeof(acc_t) == 4) {
                 row_prefix_sums<NV>(e);
-                acc_t pm[NV];   // minus the prefix of the lane before
-#pragma unroll
-                for (int q = 0; q < NV; ++q) pm[q] = (int)(0u - (unsigned)dpp_shr(e[q], 1));
                 if (emit) {
 #pragma unroll
                     for (int q = 0; q < NV; ++q) atomicAdd(&blds[4 * li + value_slot<D, NV>(q)], e[q]);
                 }
-                if (head_sub) {
+                if (sub_next) {
+                    const int ln = li - lrel + lrel_next;
 #pragma unroll
-                    for (int q = 0; q < NV; ++q) atomicAdd(&blds[4 * li + value_slot<D, NV>(q)], pm[q]);
+                    for (int q = 0; q < NV; ++q)
+                        __hip_atomic_fetch_sub(&blds[4 * ln + value_slot<D, NV>(q)], e[q], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
             } else {
                 seg_row_sums<NV>(e, msk);
