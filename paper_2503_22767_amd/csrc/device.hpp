@@ -283,19 +283,21 @@ __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
-// Reductions over the 64 lanes of a wave with DPP moves (pairs, quads, half
-// rows, rows, then row broadcasts 15 and 31), result read from lane 63 and
-// returned to every lane. Every lane must take part.
+// Reductions over the 64 lanes of a wave: DPP moves inside each row of 16
+// lanes (pairs, quads, half rows, rows; every source lane is in the row, so
+// no old value is kept), after which every lane holds its row's result; the
+// four rows are then combined on values read from lanes 0, 16, 32 and 48.
+// The result is returned to every lane. Every lane must take part.
 template <typename Op>
 __device__ __forceinline__ int wave_reduce(int v, Op op)
 {
-    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));    // quad_perm [1,0,3,2]
-    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));    // quad_perm [2,3,0,1]
-    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));   // row_half_mirror
-    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));   // row_mirror
-    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));   // row_bcast:15 into rows 1, 3
-    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));   // row_bcast:31 into rows 2, 3
-    return __builtin_amdgcn_readlane(v, 63);
+    v = op(v, __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true));    // quad_perm [1,0,3,2]
+    v = op(v, __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true));    // quad_perm [2,3,0,1]
+    v = op(v, __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, true));   // row_half_mirror
+    v = op(v, __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, true));   // row_mirror
+    const int r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+    const int r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+    return op(op(r0, r1), op(r2, r3));
 }
 
 __device__ __forceinline__ int wave_min(int v)
