@@ -123,11 +123,33 @@ constexpr int kWaveBoxCap = kBoxCap / kWaves;   // staging box of one wave when 
 // storage offset (nodes) of staged box `id` = chunk * kWaves + wave inside `part`
 __device__ __forceinline__ int64_t box_offset(int id) { return (int64_t)(id / kWaves) * kBoxCap + (id % kWaves) * kWaveBoxCap; }
 
+// Node records of a staged box. In FP32 the P2G scatter (momentum and mass)
+// sums its values in pairs with 64-bit LDS atomics: word 0 holds the mass and
+// word 1 the first momentum component of one 64-bit integer (the mass sum is
+// never negative, so word 1 is that component's sum); in 3D words 2 and 3 hold
+// the second and third components of another, whose high word carries the
+// sign of the low one; in 2D word 2 is the second component alone. Otherwise
+// word q is record slot q.
+template <typename real, int D, bool kPacked>
+__device__ __forceinline__ void decode_node(const typename LdsAcc<real>::T* w, const real inv[4], real out[4])
+{
+    using Acc = LdsAcc<real>;
+    if constexpr (kPacked) {
+        out[0] = Acc::dec(w[1], inv[0]);
+        out[1] = Acc::dec(w[2], inv[1]);
+        out[2] = D == 3 ? Acc::dec(w[3] + (w[2] < 0 ? 1 : 0), inv[2]) : Acc::dec(w[3], inv[2]);
+        out[3] = Acc::dec(w[0], inv[3]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[q] = Acc::dec(w[q], inv[q]);
+    }
+}
+
 // Registers box `id` (node range lo .. lo + ext - 1) with every coarse block it
 // overlaps; the lanes lane0, lane0 + stride, ... share the work. A coarse block
 // whose list is full gets the staged values of its part of the box added to
 // the dense accumulator fb instead.
-template <typename real, int D>
+template <typename real, int D, bool kPacked>
 __device__ __forceinline__ void register_box(const Args<real>& a, const InstDev<real>& I, int id, const int lo[3],
                                              const int ext[3], const typename LdsAcc<real>::T* box_lds,
                                              const real inv[4], bool staged, real* fb, int phase, int lane0,
@@ -162,11 +184,11 @@ __device__ __forceinline__ void register_box(const Args<real>& a, const InstDev<
                         int l = x + ext[0] * (y + ext[1] * z);
                         int64_t g = (int64_t)I.grid_off + (int64_t)(lo[0] + x) +
                                     (int64_t)I.n_grid * ((lo[1] + y) + (D == 3 ? (int64_t)I.n_grid * (lo[D - 1] + z) : 0));
+                        real rec[4];
+                        decode_node<real, D, kPacked>(box_lds + 4 * l, inv, rec);
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            real v = LdsAcc<real>::dec(box_lds[4 * l + q], inv[q]);
-                            if (v != real(0)) atomic_add(&fb[4 * g + q], v);
-                        }
+                        for (int q = 0; q < 4; ++q)
+                            if (rec[q] != real(0)) atomic_add(&fb[4 * g + q], rec[q]);
                     }
         }
     }
@@ -237,6 +259,7 @@ __device__ __forceinline__ void scatter_box(const Args<real>& a, const InstDev<r
     using Acc = LdsAcc<real>;
     using acc_t = typename Acc::T;
     constexpr int S3 = Comp<D>::S3;
+    constexpr bool kPacked = NV == D + 1 && sizeof(acc_t) == 4;   // see decode_node
     __shared__ int s_bb[kWaves][6];
     __shared__ float s_bmax[kWaves][4];
     const int t = threadIdx.x;
@@ -368,7 +391,29 @@ __device__ __forceinline__ void scatter_box(const Args<real>& a, const InstDev<r
 #pragma unroll
             for (int q = 0; q < NV; ++q) e[q] = Acc::enc(wgt, u[q]);
             const int li = lrel + oa[0] + bext[0] * (oa[1] + (D == 3 ? bext[1] * oa[D - 1] : 0));
-            if constexpr (sizeof(acc_t) == 4) {
+            if constexpr (kPacked) {
+                row_prefix_sums<NV>(e);
+                // (mass | momentum 0) and, in 3D, (momentum 1 | momentum 2)
+                // with the sign of the low word carried into the high one
+                const uint64_t pa = ((uint64_t)(uint32_t)e[0] << 32) | (uint32_t)e[D];
+                uint64_t pb = 0;
+                if constexpr (D == 3) pb = ((uint64_t)(uint32_t)(e[2] + (e[1] >> 31)) << 32) | (uint32_t)e[1];
+                if (emit) {
+                    atomicAdd(reinterpret_cast<unsigned long long*>(&blds[4 * li]), (unsigned long long)pa);
+                    if constexpr (D == 3) atomicAdd(reinterpret_cast<unsigned long long*>(&blds[4 * li + 2]), (unsigned long long)pb);
+                    else atomicAdd(&blds[4 * li + 2], e[1]);
+                }
+                if (sub_next) {
+                    const int ln = li - lrel + lrel_next;
+                    __hip_atomic_fetch_sub(reinterpret_cast<unsigned long long*>(&blds[4 * ln]), (unsigned long long)pa,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if constexpr (D == 3)
+                        __hip_atomic_fetch_sub(reinterpret_cast<unsigned long long*>(&blds[4 * ln + 2]), (unsigned long long)pb,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    else
+                        __hip_atomic_fetch_sub(&blds[4 * ln + 2], e[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            } else if constexpr (sizeof(acc_t) == 4) {
                 row_prefix_sums<NV>(e);
                 if (emit) {
 #pragma unroll
@@ -406,14 +451,14 @@ __device__ __forceinline__ void scatter_box(const Args<real>& a, const InstDev<r
     __syncthreads();
     // write the staged boxes and their descriptors
     real* dst = a.part + box_offset(id) * 4;
-    if (block_mode) {
-        for (int l = t; l < vol; l += kBlock)
+    if (block_mode || staged) {
+        const int n_write = block_mode ? vol : wvol, l0 = block_mode ? t : (t & 63), step = block_mode ? kBlock : 64;
+        for (int l = l0; l < n_write; l += step) {
+            real rec[4];
+            decode_node<real, D, kPacked>(blds + 4 * l, inv, rec);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) dst[4 * l + q] = Acc::dec(blds[4 * l + q], inv[q]);
-    } else if (staged) {
-        for (int l = t & 63; l < wvol; l += 64)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) dst[4 * l + q] = Acc::dec(blds[4 * l + q], inv[q]);
+            for (int q = 0; q < 4; ++q) dst[4 * l + q] = rec[q];
+        }
     }
     // one writer per descriptor: thread t < kWaves in block mode, lane 0 of each wave otherwise
     if (block_mode ? (t < kWaves) : ((t & 63) == 0)) {
@@ -430,9 +475,9 @@ __device__ __forceinline__ void scatter_box(const Args<real>& a, const InstDev<r
     // register the boxes (also the ranges of waves that fell back, so the
     // grid update visits their coarse blocks)
     if (block_mode) {
-        register_box<real, D>(a, I, id, lo, ext, blds, inv, true, fb, phase, t, kBlock);
+        register_box<real, D, kPacked>(a, I, id, lo, ext, blds, inv, true, fb, phase, t, kBlock);
     } else if (wave_live) {
-        register_box<real, D>(a, I, id, wlo, wext, blds, inv, staged, fb, phase, t & 63, 64);
+        register_box<real, D, kPacked>(a, I, id, wlo, wext, blds, inv, staged, fb, phase, t & 63, 64);
     }
 }
 
