@@ -1215,34 +1215,45 @@ __device__ __forceinline__ int g2p_update(const Args<real>& a, const InstDev<rea
     // the stencil's first node; the others are at small 32-bit offsets
     const int n = I.n_grid;
     const real* g0 = gv_in + 4 * ((int64_t)I.grid_off + node_index<real, D>(Sx.base, kZero3, n));
-    real vn[D], Bm[D][D];
+    // sums over the 3^D nodes (all unrolled, by rows along x) of w v and of
+    // w v b_c with centred node offsets b_c = a_c - 1 in {-1, 0, 1}; with
+    // dpos = (a - f) dx, sum w v dpos_c = dx (sum w v b_c - (f_c - 1) sum w v),
+    // where |f_c - 1| <= 1/2 keeps the cancellation small in FP32
+    real vn[D], Ba[D][D];
 #pragma unroll
     for (int r = 0; r < D; ++r) {
         vn[r] = 0;
 #pragma unroll
-        for (int c = 0; c < D; ++c) Bm[r][c] = 0;
+        for (int c = 0; c < D; ++c) Ba[r][c] = 0;
     }
-    // all 3^D nodes unrolled; dpos per axis is one of three values
-    real d0[3];
+    const real wx0 = Sx.w[0][0], wx1 = Sx.w[0][1], wx2 = Sx.w[0][2];
 #pragma unroll
-    for (int a0 = 0; a0 < 3; ++a0) d0[a0] = (real(a0) - Sx.f[0]) * I.dx;
+    for (int a2 = 0; a2 < (D == 3 ? 3 : 1); ++a2)
 #pragma unroll
-    for (int o = 0; o < Comp<D>::S3; ++o) {
-        const int a0 = o % 3, a1 = (o / 3) % 3, a2 = o / 9;
-        const real d1 = (real(a1) - Sx.f[1]) * I.dx;
-        const real d2 = D == 3 ? (real(a2) - Sx.f[D - 1]) * I.dx : real(0);
-        const real w = Sx.w[0][a0] * Sx.w[1][a1] * (D == 3 ? Sx.w[D - 1][a2] : real(1));
-        real vi[D];
-        load_vec<real, D>(g0 + 4 * (a0 + n * (a1 + (D == 3 ? n * a2 : 0))), vi);
+        for (int a1 = 0; a1 < 3; ++a1) {
+            const real wyz = Sx.w[1][a1] * (D == 3 ? Sx.w[D - 1][a2] : real(1));
+            const real* row = g0 + 4 * n * (a1 + (D == 3 ? n * a2 : 0));
+            real v0[D], v1[D], v2[D];
+            load_vec<real, D>(row, v0);
+            load_vec<real, D>(row + 4, v1);
+            load_vec<real, D>(row + 8, v2);
 #pragma unroll
-        for (int r = 0; r < D; ++r) {
-            const real wv = w * vi[r];
-            vn[r] += wv;
-            Bm[r][0] += wv * d0[a0];
-            Bm[r][1] += wv * d1;
-            if (D == 3) Bm[r][D - 1] += wv * d2;
+            for (int r = 0; r < D; ++r) {
+                const real p0 = wx0 * v0[r], p2 = wx2 * v2[r];
+                const real sw = wyz * fma(wx1, v1[r], p0 + p2);      // row sum of w v
+                vn[r] += sw;
+                Ba[r][0] = fma(wyz, p2 - p0, Ba[r][0]);
+                if (a1 == 0) Ba[r][1] -= sw;
+                if (a1 == 2) Ba[r][1] += sw;
+                if (D == 3 && a2 == 0) Ba[r][D - 1] -= sw;
+                if (D == 3 && a2 == 2) Ba[r][D - 1] += sw;
+            }
         }
-    }
+    real Bm[D][D];
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+        for (int c = 0; c < D; ++c) Bm[r][c] = I.dx * fma(real(1) - Sx.f[c], vn[r], Ba[r][c]);
     real IdC[D][D];
 #pragma unroll
     for (int r = 0; r < D; ++r) {
@@ -1327,7 +1338,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(Args<real> a, const real* __rest
 // registers for the scatter. x and F are always stored; v and C only when a
 // later pass reads them (checkpoints, stashed states).
 template <typename real, int D>
-__global__ __launch_bounds__(kBlock, 5) void k_g2p2g(Args<real> a, const real* __restrict__ gv_in, const real* sin,
+__global__ __launch_bounds__(kBlock, 6) void k_g2p2g(Args<real> a, const real* __restrict__ gv_in, const real* sin,
                                                   real* sout, int step, int traj_on, int store_vc, int list_done,
                                                   int list_next)
 {
