@@ -84,12 +84,12 @@ ALU_PEAK_PACKED_TFLOPS = {4: 157.3, 8: 78.6}
 # device-to-device copy of 1 GiB (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0). Valid
 # only for the kernel sources they were taken on (hash of csrc/).
 TRAFFIC = {
-    # (530535.1 KiB fetched x 2.0 + 257419.4 KiB written) x 1024, mean of 5 launches
-    "p2g_g2p_adj": 1350133280,
-    # (142583.1 x 2.0 + 246091.5) x 1024, mean of 26 launches (plain and recorded steps)
-    "g2p_p2g": 544007918,
+    # (529896.7 KiB fetched x 2.0 + 257413.1 KiB written) x 1024, mean of 5 launches
+    "p2g_g2p_adj": 1348819392,
+    # (142512.8 x 2.0 + 246111.5) x 1024, mean of 26 launches (plain and recorded steps)
+    "g2p_p2g": 543884457,
 }
-TRAFFIC_SRC_HASH = "549117c6e27e4b1d"
+TRAFFIC_SRC_HASH = "4ee398ac941afb74"
 
 
 def csrc_hash():
