@@ -20,14 +20,14 @@ namespace mpm {
 
 enum KernelId {
     K_SORT = 0, K_GATHER, K_P2G, K_GRID, K_G2P, K_LOSS, K_CKPT, K_SEED,
-    K_G2P_ADJ, K_GRID_ADJ, K_P2G_ADJ, K_OUT, K_ADJ_FUSED, K_G2P2G, K_COUNT
+    K_G2P_ADJ, K_GRID_ADJ, K_P2G_ADJ, K_OUT, K_ADJ_FUSED, K_G2P2G, K_RESTORE, K_COUNT
 };
 
 inline const char* kernel_name(int k)
 {
     static const char* names[K_COUNT] = {"sort", "gather", "p2g", "grid_update", "g2p", "loss", "checkpoint",
                                          "seed", "g2p_adj", "grid_adj", "p2g_adj", "output",
-                                         "p2g_g2p_adj", "g2p_p2g"};
+                                         "p2g_g2p_adj", "g2p_p2g", "grid_restore"};
     return (k >= 0 && k < K_COUNT) ? names[k] : "";
 }
 
@@ -154,6 +154,13 @@ public:
             }
             I.floor_mu = I.floor_noslip ? (real)0 : (real)d.floor_mu;
             inst_h_.push_back(I);
+            {
+                // grid-store sizing before the first recorded rollout: coarse
+                // blocks a step may touch, from the cells the particles fill
+                const double cells = (double)np[k] * d.particle_volume / std::pow(dx, (double)D);
+                const double est = 4.0 * std::ceil(cells / Coarse<D>::nodes) + 27.0;
+                est_cb_inst_.push_back((int64_t)std::min<double>(est, (double)ncb));
+            }
             caller_start_h_.push_back(caller);
             int n_ch = (int)((np[k] + kBlock - 1) / kBlock);
             for (int c = 0; c < n_ch; ++c) {
@@ -210,6 +217,7 @@ public:
             if (value < 0 || value > kMaxChains) return fail(MPM_MAG_EINVAL, "streams must be in [0, 8]");
             streams_opt_ = (int)value;
             plan_chains();
+            gs_valid_ = false;   // the store is laid out per chain
             ++plan_gen_;
             return MPM_MAG_OK;
         }
@@ -257,6 +265,11 @@ public:
             ++plan_gen_;   // baked into captured launches
             return MPM_MAG_OK;
         }
+        if (k == "grid_store") {
+            if (value < -1 || value > ((int64_t)1 << 30)) return fail(MPM_MAG_EINVAL, "grid_store must be -1, 0 or MiB");
+            gs_budget_mib_ = value;   // applied at the next recorded rollout
+            return MPM_MAG_OK;
+        }
         if (k == "ckpt_every") {
             if (value < 0 || value > (1 << 30)) return fail(MPM_MAG_EINVAL, "bad ckpt_every");
             ckpt_opt_ = (int)value;
@@ -280,6 +293,8 @@ public:
         has_target_ = target != nullptr;
         if (record) {
             int st = ensure_checkpoints();
+            if (st) return st;
+            st = ensure_store();
             if (st) return st;
         }
         MPM_HIP(hipMemsetAsync(err_d_, 0, sizeof(int), s));
@@ -315,6 +330,12 @@ public:
         }
         st = finish(s);
         if (st) return st;
+        if (record && gstore_) {
+            gs_base_h_.assign((size_t)gs_chains_ * (T_ + 1), 0);
+            MPM_HIP(hipMemcpy(gs_base_h_.data(), gs_base_, sizeof(int) * gs_base_h_.size(), hipMemcpyDeviceToHost));
+            gs_count_chains_ = gs_chains_;
+            gs_valid_ = true;
+        }
         recorded_ = record != 0;
         return MPM_MAG_OK;
     }
@@ -360,7 +381,14 @@ public:
             }
             return join(cs);
         };
-        st = use_graph() ? replay(s, gbwd_, sweep) : sweep(s);
+        std::vector<char> sig;
+        for (int c = 0; c < nck_; ++c)
+            for (int q = 0; q < n_chains(); ++q) sig.push_back(seg_stored(q, c) ? 1 : 0);
+        if (sig != bwd_sig_) {
+            bwd_sig_ = sig;
+            ++bwd_gen_;   // another mix of stored and recomputed segments
+        }
+        st = use_graph() ? replay(s, gbwd_, sweep, (plan_gen_ << 24) ^ bwd_gen_) : sweep(s);
         if (st) return st;
         if (g_density || g_br) {
             st = launch(K_OUT, s, n_chunks_, kBlock, k_scatter_out<real, D>, a, (const int*)id_, (const real*)st_,
@@ -502,7 +530,8 @@ private:
             r = launch(K_P2G, cs, nc, kBlock, k_p2g<real, D>, a, (const real*)st_, n, lf(n));
             if (r) return r;
         }
-        r = launch(K_GRID, cs, grid_blocks_of(q), kGridBlock, k_grid<real, D>, a, gv_, (real*)nullptr, lf(n));
+        r = launch(K_GRID, cs, grid_blocks_of(q), kGridBlock, k_grid<real, D>, a, gv_, (real*)nullptr, lf(n),
+                   store_of(q, n, record));
         if (r) return r;
         if (n + 1 < T_ && fuse_fwd_) {
             // G2P of step n with P2G of step n + 1; v and C are stored only for
@@ -518,7 +547,8 @@ private:
     }
 
     // step n of segment c, recomputed from its checkpoint for chain q, keeping
-    // the step's grid (v, (p, m)) and the next state
+    // the step's grid (v, (p, m)) and the next state. When the recorded forward
+    // stored the segment's grids, they are copied back and only the G2P runs.
     int recompute_step(int q, hipStream_t cs, int c, int n)
     {
         Args<real> a = args_of(q);
@@ -529,11 +559,19 @@ private:
             r = sort_lanes(q, cs, seg_state(c, 0));
             if (r) return r;
         }
+        if (seg_stored(q, c)) {
+            r = launch(K_RESTORE, cs, grid_blocks_of(q), kGridBlock, k_grid_restore<real, D>, a, store_of(q, n, true),
+                       gv_slot(j), gm_slot(j));
+            if (r || n + 1 >= s1) return r;
+            return launch(K_G2P, cs, nc, kBlock, k_g2p<real, D>, a, (const real*)gv_slot(j),
+                          (const real*)seg_state(c, j), seg_state(c, j + 1), n, 0, lf(n));
+        }
         if (n == s0 || !fuse_fwd_) {
             r = launch(K_P2G, cs, nc, kBlock, k_p2g<real, D>, a, (const real*)seg_state(c, j), n, lf(n));
             if (r) return r;
         }
-        r = launch(K_GRID, cs, grid_blocks_of(q), kGridBlock, k_grid<real, D>, a, gv_slot(j), gm_slot(j), lf(n));
+        r = launch(K_GRID, cs, grid_blocks_of(q), kGridBlock, k_grid<real, D>, a, gv_slot(j), gm_slot(j), lf(n),
+                   store_of(q, n, false));
         if (r) return r;
         if (n + 1 >= s1) return MPM_MAG_OK;
         if (fuse_fwd_)
@@ -775,9 +813,9 @@ private:
     }
 
     template <typename Body>
-    int replay(hipStream_t s, Graph& g, Body body)
+    int replay(hipStream_t s, Graph& g, Body body, int64_t key = -2)
     {
-        const int64_t key = plan_gen_;
+        if (key == -2) key = plan_gen_;
         if (!g.exec || g.key != key) {
             drop(g);
             if (!cap_) MPM_HIP(hipStreamCreateWithFlags(&cap_, hipStreamNonBlocking));
@@ -862,6 +900,141 @@ private:
         if (e & kErrNonFinite) return fail(MPM_MAG_ENONFINITE, "non-finite particle state");
         if (e & kErrInvert) return fail(MPM_MAG_EINVERT, "det F <= 0");
         if (e & kErrDomain) return fail(MPM_MAG_EDOMAIN, "a particle stencil left the grid");
+        return MPM_MAG_OK;
+    }
+
+    // ------------------------------------------------------------ grid store
+    // The recorded forward keeps every step's active coarse blocks (GridStore)
+    // in one arena, split between the chains. Its size comes from the block
+    // counts of the last recorded rollout (a particle-count estimate before the
+    // first), within a budget: the grid_store option in MiB, or by default the
+    // free device memory less an eighth of the total. Steps beyond the arena
+    // are not kept; their segments are recomputed in full by the reverse sweep.
+    size_t store_block_bytes() const { return sizeof(real) * 8 * Coarse<D>::nodes; }
+
+    GridStore<real> store_of(int q, int n, bool on) const
+    {
+        GridStore<real> g;
+        g.data = nullptr;
+        g.blk = nullptr;
+        g.base = nullptr;
+        g.cap = 0;
+        g.step = n;
+        if (!on || !gstore_ || q >= gs_chains_) return g;
+        g.data = gstore_ + (size_t)gs_off_[q] * 8 * Coarse<D>::nodes;
+        g.blk = gs_blk_ + gs_off_[q];
+        g.base = gs_base_ + (size_t)q * (T_ + 1);
+        g.cap = (int)gs_cap_[q];
+        return g;
+    }
+
+    // the last recorded rollout kept every step of segment c for chain q
+    bool seg_stored(int q, int c) const
+    {
+        if (!gs_valid_ || !gstore_ || q >= gs_chains_) return false;
+        const int s1 = std::min(T_, (c + 1) * K_);
+        return gs_base_h_[(size_t)q * (T_ + 1) + s1] <= gs_cap_[q];
+    }
+
+    void free_store()
+    {
+        if (gstore_) (void)hipFree(gstore_);
+        if (gs_blk_) (void)hipFree(gs_blk_);
+        bytes_ -= gstore_bytes_;
+        gstore_ = nullptr;
+        gs_blk_ = nullptr;
+        gstore_bytes_ = 0;
+        gs_chains_ = 0;
+        gs_valid_ = false;
+        ++plan_gen_;   // store addresses are baked into captured launches
+    }
+
+    int ensure_store()
+    {
+        gs_valid_ = false;
+        const int nq = n_chains();
+        if (gs_budget_mib_ == 0 || T_ == 0) {
+            if (gstore_) free_store();
+            return MPM_MAG_OK;
+        }
+        if (!gs_base_) {
+            if (hipMalloc(&gs_base_, sizeof(int) * (size_t)kMaxChains * (T_ + 1)) != hipSuccess) {
+                gs_base_ = nullptr;
+                return fail(MPM_MAG_ENOMEM, "grid store counters");
+            }
+            bytes_ += sizeof(int) * (size_t)kMaxChains * (T_ + 1);
+        }
+        // slots wanted per chain: the last count with a tenth more, else the estimate
+        const bool known = !gs_base_h_.empty() && gs_count_chains_ == nq;
+        std::vector<int64_t> want(nq, 0);
+        int64_t total = 0;
+        for (int q = 0; q < nq; ++q) {
+            if (known) {
+                const int64_t need = gs_base_h_[(size_t)q * (T_ + 1) + T_];
+                want[q] = need + need / 10 + 8;
+            } else {
+                int64_t per_step = 0;
+                for (int k = 0; k < n_inst_; ++k)
+                    if (inst_h_[k].chunk_off >= chains_[q].c0 && inst_h_[k].chunk_off < chains_[q].c0 + chains_[q].nc)
+                        per_step += est_cb_inst_[k];
+                want[q] = per_step * T_;
+            }
+            want[q] = std::min<int64_t>(want[q], kStoreCountMax);
+            total += want[q];
+        }
+        const size_t bb = store_block_bytes();
+        int64_t budget;
+        if (gs_budget_mib_ > 0) {
+            budget = gs_budget_mib_ << 20;
+        } else {
+            size_t fr = 0, tot = 0;
+            if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+                (void)hipGetLastError();
+                fr = tot = 0;
+            }
+            budget = (int64_t)fr + (int64_t)gstore_bytes_ - (int64_t)(tot / 8);
+        }
+        const int64_t max_slots = std::max<int64_t>(0, budget) / (int64_t)(bb + sizeof(int));
+        if (total > max_slots) {
+            int64_t t2 = 0;
+            for (int q = 0; q < nq; ++q) {
+                want[q] = (int64_t)((double)want[q] * (double)max_slots / (double)total);
+                t2 += want[q];
+            }
+            total = t2;
+        }
+        // keep the arena when it fits every chain and is not more than twice the need
+        bool keep = gstore_ && gs_chains_ == nq;
+        int64_t cur = 0;
+        for (int q = 0; keep && q < nq; ++q) {
+            keep = gs_cap_[q] >= want[q];
+            cur += gs_cap_[q];
+        }
+        if (keep && cur <= 2 * total + 64) return MPM_MAG_OK;
+        if (gstore_) free_store();
+        if (total <= 0) return MPM_MAG_OK;
+        if (hipMalloc(&gstore_, bb * (size_t)total) != hipSuccess) {
+            (void)hipGetLastError();   // no arena: every segment is recomputed
+            gstore_ = nullptr;
+            return MPM_MAG_OK;
+        }
+        if (hipMalloc(&gs_blk_, sizeof(int) * (size_t)total) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipFree(gstore_);
+            gstore_ = nullptr;
+            gs_blk_ = nullptr;
+            return MPM_MAG_OK;
+        }
+        gstore_bytes_ = (bb + sizeof(int)) * (size_t)total;
+        bytes_ += gstore_bytes_;
+        int64_t off = 0;
+        for (int q = 0; q < nq; ++q) {
+            gs_off_[q] = off;
+            gs_cap_[q] = want[q];
+            off += want[q];
+        }
+        gs_chains_ = nq;
+        ++plan_gen_;
         return MPM_MAG_OK;
     }
 
@@ -990,6 +1163,11 @@ private:
         if (stash_) (void)hipFree(stash_);
         if (gstash_) (void)hipFree(gstash_);
         ckpt_ = stash_ = gstash_ = nullptr;
+        if (gstore_) (void)hipFree(gstore_);
+        if (gs_blk_) (void)hipFree(gs_blk_);
+        if (gs_base_) (void)hipFree(gs_base_);
+        gstore_ = nullptr;
+        gs_blk_ = gs_base_ = nullptr;
         if (err_h_) (void)hipHostFree(err_h_);
         err_h_ = nullptr;
         for (auto e : events_) (void)hipEventDestroy(e);
@@ -1030,6 +1208,20 @@ private:
     int* active_list_ = nullptr;
     real* gpm_ = nullptr;      // (pbar, mbar) of the grid transpose
     real* gstash_ = nullptr;   // per-step grid of the segment being reversed
+    // grid store: chain q owns slots [gs_off_[q], gs_off_[q] + gs_cap_[q])
+    real* gstore_ = nullptr;
+    int* gs_blk_ = nullptr;
+    int* gs_base_ = nullptr;          // [kMaxChains][T + 1]
+    size_t gstore_bytes_ = 0;
+    int64_t gs_off_[kMaxChains] = {}, gs_cap_[kMaxChains] = {};
+    int gs_chains_ = 0;               // chains the arena is laid out for
+    int gs_count_chains_ = 0;         // chains of the counts in gs_base_h_
+    std::vector<int> gs_base_h_;      // step bases of the last recorded rollout
+    bool gs_valid_ = false;           // they describe the recorded rollout
+    int64_t gs_budget_mib_ = -1;      // option grid_store
+    std::vector<int64_t> est_cb_inst_;
+    std::vector<char> bwd_sig_;       // stored segments of the captured reverse sweep
+    int64_t bwd_gen_ = 0;
     size_t gstash_bytes_ = 0;
     std::vector<int> cb_inst_h_;
     int64_t n_cb_ = 0;

@@ -96,6 +96,22 @@ struct Args {
     const uint8_t* lperm;  // [nalloc]: lane t of chunk c works on slot c * kBlock + lperm[c * kBlock + t]
 };
 
+// Grid store: the recorded forward keeps each step's active coarse blocks
+// (node velocity, then the summed (momentum, mass) record: 8 values per node),
+// packed step after step, so that the reverse sweep can rebuild a step's
+// grid without recomputing its P2G. Step n of one chain owns the slots
+// [base[n], base[n + 1]); blk names the coarse block in each slot. base keeps
+// counting past cap, so a step is stored iff base[n + 1] <= cap.
+constexpr int kStoreCountMax = 1 << 30;
+template <typename real>
+struct GridStore {
+    real* data;   // [cap][Coarse<D>::nodes][8], nullptr: not kept
+    int* blk;     // [cap]
+    int* base;    // [n_steps + 1]
+    int cap;      // slots
+    int step;
+};
+
 // Slot of the particle that lane t of this block works on. The forward
 // particle kernels take a chunk's particles grouped by their current stencil
 // base cell (k_lane_sort), so that lanes sharing a base are adjacent and the
@@ -606,7 +622,7 @@ __device__ __forceinline__ void gather_coarse(const Args<real>& a, const InstDev
             acc[q] = fb[4 * g + q] + (real)s_acc[q][ln];
             fb[4 * g + q] = real(0);
         }
-        node_fn(g, g3, acc);
+        node_fn(g, g3, ln, acc);
     }
     __syncthreads();
     if (t == 0) a.reg_count[b] = 0;
@@ -1162,15 +1178,29 @@ __device__ __forceinline__ int node_velocity(const InstDev<real>& I, const int i
 // Grid-stride over the coarse blocks the P2G registered: gathers the staged
 // boxes, applies Eqs. 16-18 and writes the node velocity to gv_out. When gmd_out
 // is given (reverse sweep) the summed (momentum, mass) records are kept there
-// for the grid transpose.
+// for the grid transpose. When gs.data is given (recorded forward) the step's
+// blocks also go to the grid store, if they fit (GridStore).
 template <typename real, int D>
-__global__ __launch_bounds__(kGridBlock) void k_grid(Args<real> a, real* gv_out, real* gmd_out, int list)
+__global__ __launch_bounds__(kGridBlock) void k_grid(Args<real> a, real* gv_out, real* gmd_out, int list,
+                                                     GridStore<real> gs)
 {
   const int n_act = a.active[list];
+  int sbase = -1;   // first store slot of this step, -1 when not kept
+  if (gs.data) {
+      const int s0 = gs.step == 0 ? 0 : gs.base[gs.step];
+      if ((int64_t)s0 + n_act <= gs.cap) sbase = s0;
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+          if (gs.step == 0) gs.base[0] = 0;
+          const int64_t s1 = (int64_t)s0 + n_act;
+          gs.base[gs.step + 1] = s1 < kStoreCountMax ? (int)s1 : kStoreCountMax;
+      }
+  }
   for (int ai = blockIdx.x; ai < n_act; ai += gridDim.x) {
     const int b = a.active_list[list * a.n_coarse + ai];
     const InstDev<real>& I = a.inst[a.cb_inst[b]];
-    gather_coarse<real, D>(a, I, b, a.gm, [&](int64_t g, const int g3[3], const real node[4]) {
+    real* keep = sbase >= 0 ? gs.data + (size_t)(sbase + ai) * Coarse<D>::nodes * 8 : nullptr;
+    if (keep && threadIdx.x == 0) gs.blk[sbase + ai] = b;
+    gather_coarse<real, D>(a, I, b, a.gm, [&](int64_t g, const int g3[3], int ln, const real node[4]) {
         real v[D];
         if (node[3] > real(0)) {
             int ijk[D];
@@ -1189,7 +1219,46 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Args<real> a, real* gv_out,
         if (gmd_out)
 #pragma unroll
             for (int q = 0; q < 4; ++q) gmd_out[4 * g + q] = node[q];
+        if (keep) {
+            real* o = keep + (size_t)ln * 8;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) o[k] = k < D ? v[k] : real(0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) o[4 + q] = node[q];
+        }
     });
+  }
+}
+
+// Copies the blocks the recorded forward kept for one step back into the dense
+// velocity and (momentum, mass) arrays of the reverse sweep: the same nodes,
+// with the same values, that k_grid writes there when it recomputes the step.
+template <typename real, int D>
+__global__ __launch_bounds__(kGridBlock) void k_grid_restore(Args<real> a, GridStore<real> gs, real* gv_out,
+                                                             real* gmd_out)
+{
+  using CB = Coarse<D>;
+  const int s0 = gs.step == 0 ? 0 : gs.base[gs.step];
+  const int s1 = gs.base[gs.step + 1];
+  for (int sl = s0 + blockIdx.x; sl < s1; sl += gridDim.x) {
+    const int b = gs.blk[sl];
+    const InstDev<real>& I = a.inst[a.cb_inst[b]];
+    const int lb = b - I.cb_off;
+    const int co[3] = {(lb % I.nb) * CB::edge, (D == 3 ? (lb / I.nb) % I.nb : lb / I.nb) * CB::edge,
+                       D == 3 ? (lb / (I.nb * I.nb)) * CB::edge : 0};
+    const real* src = gs.data + (size_t)sl * CB::nodes * 8;
+    for (int ln = threadIdx.x; ln < CB::nodes; ln += blockDim.x) {
+        const int g3[3] = {co[0] + ln % CB::edge, co[1] + (ln / CB::edge) % CB::edge,
+                           D == 3 ? co[2] + ln / (CB::edge * CB::edge) : 0};
+        if (g3[0] >= I.n_grid || g3[1] >= I.n_grid || (D == 3 && g3[2] >= I.n_grid)) continue;
+        const int64_t g = (int64_t)I.grid_off + g3[0] +
+                          (int64_t)I.n_grid * (g3[1] + (D == 3 ? (int64_t)I.n_grid * g3[2] : 0));
+        const real* r = src + (size_t)ln * 8;
+#pragma unroll
+        for (int k = 0; k < D; ++k) gv_out[4 * g + k] = r[k];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) gmd_out[4 * g + q] = r[4 + q];
+    }
   }
 }
 
@@ -1725,7 +1794,7 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_adj(Args<real> a, const rea
   for (int ai = blockIdx.x; ai < n_act; ai += gridDim.x) {
     const int b = a.active_list[list * a.n_coarse + ai];
     const InstDev<real>& I = a.inst[a.cb_inst[b]];
-    gather_coarse<real, D>(a, I, b, a.gbar, [&](int64_t g, const int g3[3], const real vb[4]) {
+    gather_coarse<real, D>(a, I, b, a.gbar, [&](int64_t g, const int g3[3], int, const real vb[4]) {
         real node[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) node[q] = gmd_in[4 * g + q];
