@@ -543,7 +543,7 @@ private:
             if (ck1) return copy_state(q, cs, ckpt_slot((n + 1) / K_), st_);
             return MPM_MAG_OK;
         }
-        return launch(K_G2P, cs, nc, kBlock, k_g2p<real, D>, a, (const real*)gv_, (const real*)st_, st_, n, 1, lf(n));
+        return launch(K_G2P, cs, nc, kBlock, k_g2p<real, D>, a, (const real*)gv_, (const real*)st_, st_, n, 1, lf(n), 0);
     }
 
     // step n of segment c, recomputed from its checkpoint for chain q, keeping
@@ -555,16 +555,17 @@ private:
         const int nc = chains_[q].nc;
         const int s0 = c * K_, s1 = std::min(T_, s0 + K_), j = n - s0;
         int r;
-        if (n == s0 && s0 % lane_every() == 0) {
+        const bool stored = seg_stored(q, c);
+        if (!stored && n == s0 && s0 % lane_every() == 0) {   // the lane order serves the fused forward only
             r = sort_lanes(q, cs, seg_state(c, 0));
             if (r) return r;
         }
-        if (seg_stored(q, c)) {
+        if (stored) {
             r = launch(K_RESTORE, cs, grid_blocks_of(q), kGridBlock, k_grid_restore<real, D>, a, store_of(q, n, true),
                        gv_slot(j), gm_slot(j));
             if (r || n + 1 >= s1) return r;
             return launch(K_G2P, cs, nc, kBlock, k_g2p<real, D>, a, (const real*)gv_slot(j),
-                          (const real*)seg_state(c, j), seg_state(c, j + 1), n, 0, lf(n));
+                          (const real*)seg_state(c, j), seg_state(c, j + 1), n, 0, lf(n), 1);
         }
         if (n == s0 || !fuse_fwd_) {
             r = launch(K_P2G, cs, nc, kBlock, k_p2g<real, D>, a, (const real*)seg_state(c, j), n, lf(n));
@@ -578,7 +579,7 @@ private:
             return launch(K_G2P2G, cs, nc, kBlock, k_g2p2g<real, D>, a, (const real*)gv_slot(j),
                           (const real*)seg_state(c, j), seg_state(c, j + 1), n, 0, 1, lf(n), lf(n + 1));
         return launch(K_G2P, cs, nc, kBlock, k_g2p<real, D>, a, (const real*)gv_slot(j), (const real*)seg_state(c, j),
-                      seg_state(c, j + 1), n, 0, lf(n));
+                      seg_state(c, j + 1), n, 0, lf(n), 0);
     }
 
     // Lane order of chain q's chunks by the stencil base cells of state st,

@@ -1266,24 +1266,17 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_restore(Args<real> a, GridS
 // G2P (Eqs. 19-22)
 // --------------------------------------------------------------------------
 
-// G2P (Eqs. 19-22) of one active particle: gather the grid velocity at its
-// stencil, update v, C, F and the displacement (stored in q.x); x1 gets the
-// new position relative to the chunk origin. Returns the error flags.
+// G2P (Eqs. 19-22) of one active particle from the velocities of its stencil's
+// nodes, node (base + a) at g0 + 4 a_x + sy a_y + sz a_z (the instance grid,
+// or a box of it in LDS): update v, C, F and the displacement (stored in q.x);
+// x1 gets the new position relative to the chunk origin. Returns the error flags.
 template <typename real, int D>
-__device__ __forceinline__ int g2p_update(const Args<real>& a, const InstDev<real>& I, int64_t i,
-                                          const real* __restrict__ gv_in, const real* sin, const int org[3],
-                                          Particle<real, D>& q, real x1[D])
+__device__ __forceinline__ int g2p_from_nodes(const Args<real>& a, const InstDev<real>& I, int64_t i,
+                                              const Stencil<real, D>& Sx, const real* g0, int sy, int sz,
+                                              const real F[D][D], const real u[D], const int org[3],
+                                              Particle<real, D>& q, real x1[D])
 {
     const int64_t S = a.nalloc;
-    real x[D], F[D][D], u[D];
-    load_xF<real, D>(sin, a.x0s, S, i, x, F);
-#pragma unroll
-    for (int k = 0; k < D; ++k) u[k] = sin[(Comp<D>::X + k) * S + i];
-    Stencil<real, D> Sx;
-    make_stencil<real, D>(x, org, I.inv_dx, I.n_grid, Sx);
-    // the stencil's first node; the others are at small 32-bit offsets
-    const int n = I.n_grid;
-    const real* g0 = gv_in + 4 * ((int64_t)I.grid_off + node_index<real, D>(Sx.base, kZero3, n));
     // sums over the 3^D nodes (all unrolled, by rows along x) of w v and of
     // w v b_c with centred node offsets b_c = a_c - 1 in {-1, 0, 1}; with
     // dpos = (a - f) dx, sum w v dpos_c = dx (sum w v b_c - (f_c - 1) sum w v),
@@ -1301,7 +1294,7 @@ __device__ __forceinline__ int g2p_update(const Args<real>& a, const InstDev<rea
 #pragma unroll
         for (int a1 = 0; a1 < 3; ++a1) {
             const real wyz = Sx.w[1][a1] * (D == 3 ? Sx.w[D - 1][a2] : real(1));
-            const real* row = g0 + 4 * n * (a1 + (D == 3 ? n * a2 : 0));
+            const real* row = g0 + sy * a1 + (D == 3 ? sz * a2 : 0);
             real v0[D], v1[D], v2[D];
             load_vec<real, D>(row, v0);
             load_vec<real, D>(row + 4, v1);
@@ -1363,6 +1356,25 @@ __device__ __forceinline__ int g2p_update(const Args<real>& a, const InstDev<rea
     return err;
 }
 
+// G2P of one active particle, gathering from the instance grid
+template <typename real, int D>
+__device__ __forceinline__ int g2p_update(const Args<real>& a, const InstDev<real>& I, int64_t i,
+                                          const real* __restrict__ gv_in, const real* sin, const int org[3],
+                                          Particle<real, D>& q, real x1[D])
+{
+    const int64_t S = a.nalloc;
+    real x[D], F[D][D], u[D];
+    load_xF<real, D>(sin, a.x0s, S, i, x, F);
+#pragma unroll
+    for (int k = 0; k < D; ++k) u[k] = sin[(Comp<D>::X + k) * S + i];
+    Stencil<real, D> Sx;
+    make_stencil<real, D>(x, org, I.inv_dx, I.n_grid, Sx);
+    // the stencil's first node; the others are at small 32-bit offsets
+    const int n = I.n_grid;
+    const real* g0 = gv_in + 4 * ((int64_t)I.grid_off + node_index<real, D>(Sx.base, kZero3, n));
+    return g2p_from_nodes<real, D>(a, I, i, Sx, g0, 4 * n, 4 * n * n, F, u, org, q, x1);
+}
+
 // mass-weighted velocity along the loss direction (trajectory loss, Eq. 39),
 // summed over the block into the instance accumulator
 template <typename real, int D>
@@ -1381,22 +1393,52 @@ __device__ __forceinline__ void traj_accumulate(const Args<real>& a, const InstD
     if (threadIdx.x == 0) unsafeAtomicAdd(&a.acc[inst * kAccCount + kAccTraj], v1[0]);
 }
 
+// G2P of one step (no scatter follows). slot_order: lanes take their own slots
+// rather than the lane order, which serves only the scatter of the forward
+// kernels (the recompute of a stored segment).
 template <typename real, int D>
 __global__ __launch_bounds__(kBlock) void k_g2p(Args<real> a, const real* __restrict__ gv_in, const real* sin,
-                                                real* sout, int step, int traj_on, int list_done)
+                                                real* sout, int step, int traj_on, int list_done, int slot_order)
 {
     const ChunkDev ch = a.chunks[a.chunk_base + blockIdx.x];
     const InstDev<real>& I = a.inst[ch.inst];
     const int t = threadIdx.x;
     const bool active = t < ch.count;
-    const int64_t i = lane_slot(a, t);
+    const int64_t i = slot_order ? (int64_t)(a.chunk_base + blockIdx.x) * kBlock + t : lane_slot(a, t);
     if (blockIdx.x == 0 && t == 0) a.active[list_done] = 0;   // the grid update has consumed this list
+    // the chunk's box of stencil nodes is staged in LDS once, so the 3^D node
+    // reads of every particle hit LDS rather than the L2
+    __shared__ real s_box[4 * kBoxCap];
+    const int64_t S = a.nalloc;
+    int org[3];
+    chunk_origin(a.corig, a.chunk_base + blockIdx.x, org);
+    real x[D], F[D][D], u[D];
+    if (active) {
+        load_xF<real, D>(sin, a.x0s, S, i, x, F);
+#pragma unroll
+        for (int k = 0; k < D; ++k) u[k] = sin[(Comp<D>::X + k) * S + i];
+    } else {
+#pragma unroll
+        for (int k = 0; k < D; ++k) x[k] = real(0.5);
+    }
+    Stencil<real, D> Sx;
+    make_stencil<real, D>(x, org, I.inv_dx, I.n_grid, Sx);
+    const real* gv = gv_in + 4 * (int64_t)I.grid_off;
+    const NodeBox<D> nb = stage_nodes<real, D>(I, active, Sx.base, gv, s_box, kBoxCap);
     Particle<real, D> q;
     if (active) {
-        int org[3];
-        chunk_origin(a.corig, a.chunk_base + blockIdx.x, org);
         real x1[D];
-        const int err = g2p_update<real, D>(a, I, i, gv_in, sin, org, q, x1);
+        int err;
+        if (nb.staged) {
+            const int l = (Sx.base[0] - nb.lo[0]) +
+                          nb.ext[0] * ((Sx.base[1] - nb.lo[1]) + (D == 3 ? nb.ext[1] * (Sx.base[D - 1] - nb.lo[D - 1]) : 0));
+            err = g2p_from_nodes<real, D>(a, I, i, Sx, s_box + 4 * l, 4 * nb.ext[0], 4 * nb.ext[0] * nb.ext[1], F, u,
+                                          org, q, x1);
+        } else {
+            const int n = I.n_grid;
+            err = g2p_from_nodes<real, D>(a, I, i, Sx, gv + 4 * node_index<real, D>(Sx.base, kZero3, n), 4 * n,
+                                          4 * n * n, F, u, org, q, x1);
+        }
         if (err) atomicOr(a.err, err);
         store_particle<real, D>(sout, a.nalloc, i, q);
     }
