@@ -84,12 +84,12 @@ ALU_PEAK_PACKED_TFLOPS = {4: 157.3, 8: 78.6}
 # device-to-device copy of 1 GiB (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0). Valid
 # only for the kernel sources they were taken on (hash of csrc/).
 TRAFFIC = {
-    # (529896.7 KiB fetched x 2.0 + 257413.1 KiB written) x 1024, mean of 5 launches
-    "p2g_g2p_adj": 1348819392,
-    # (142512.8 x 2.0 + 246111.5) x 1024, mean of 26 launches (plain and recorded steps)
-    "g2p_p2g": 543884457,
+    # (530261.2 KiB fetched x 2.0 + 257401.5 KiB written) x 1024, mean of 5 launches
+    "p2g_g2p_adj": 1349554112,
+    # (142456.4 x 2.0 + 221027.1) x 1024, mean of 21 launches (plain and recorded steps)
+    "g2p_p2g": 518082450,
 }
-TRAFFIC_SRC_HASH = "4ee398ac941afb74"
+TRAFFIC_SRC_HASH = "43ee8857a986a845"
 
 
 def csrc_hash():
