@@ -1,0 +1,130 @@
+"""FP64 CPU oracle of the design front end: the map from the design variables
+(topology variable phi, per-region magnetization magnitude and orientation
+vector) to the per-particle density and remanent field that the MPM step takes,
+and the transpose of its Jacobian.
+
+TEST INFRASTRUCTURE ONLY: tests, the smoke check and the benchmark's CPU
+baseline leg use this; the product path (the HIP library) never does, and the
+two share no code. Plain numpy in float64, written for checking by eye, not
+for speed: the filter is a brute-force double loop over particle pairs (in
+row blocks), with no neighbour search.
+
+What it computes (paper Sec. 3.1, "Design representation"):
+  - density filter (Eqs. 23-24): phit_p = sum_q w_pq phi_q / sum_q w_pq over the
+    particles q within distance R of p in the initial configuration, with
+    w_pq = 1 - |x_q(0) - x_p(0)| / R;
+  - Heaviside projection (Eq. 25):
+    phibar = (tanh(beta/2) + tanh(beta (phit - 1/2))) / (2 tanh(beta/2));
+  - magnetization (Eqs. 26-27): Br~_p = Br_max Br_p zeta_p / sqrt(|zeta_p|^2 + delta);
+  - region sharing (Eq. 28): Br_p and zeta_p are those of the particle's region.
+
+Readings (listed in the design notes):
+  - Eq. 23's numerator weights phi of the neighbour q (the printed phi_p would
+    make the filter the identity).
+  - The neighbourhood holds the q with |x_q - x_p| < R, p itself included; the
+    weight vanishes at distance R, so the strict or non-strict bound gives the
+    same sums.
+  - delta enters the orientation only (Eq. 27), so with delta > 0 the
+    orientation is slightly shorter than a unit vector.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+_ROWS = 512   # rows of the pair matrix held at once
+
+
+def filter_weights_rows(x0: np.ndarray, rows: np.ndarray, radius: float) -> np.ndarray:
+    """Weights w_pq (Eq. 24) of the particles p in `rows` against every q; zero
+    outside the radius."""
+    d = np.sqrt(((x0[rows, None, :] - x0[None, :, :]) ** 2).sum(-1))
+    return np.where(d < radius, 1.0 - d / radius, 0.0)
+
+
+def density_filter(x0: np.ndarray, phi: np.ndarray, radius: float, rows=None) -> np.ndarray:
+    """phit = W phi / (W 1) (Eq. 23) at the given rows (default all)."""
+    x0 = np.asarray(x0, dtype=np.float64)
+    phi = np.asarray(phi, dtype=np.float64)
+    rows = np.arange(len(phi)) if rows is None else np.asarray(rows)
+    out = np.empty(len(rows))
+    for s in range(0, len(rows), _ROWS):
+        r = rows[s:s + _ROWS]
+        w = filter_weights_rows(x0, r, radius)
+        out[s:s + _ROWS] = (w @ phi) / w.sum(1)
+    return out
+
+
+def density_filter_transpose(x0: np.ndarray, g: np.ndarray, radius: float) -> np.ndarray:
+    """Transpose of the filter: d phit_p / d phi_q = w_pq / s_p with s_p the row
+    sum, so g_phi_q = sum_p w_pq g_p / s_p."""
+    x0 = np.asarray(x0, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    n = len(g)
+    out = np.zeros(n)
+    for s in range(0, n, _ROWS):
+        r = np.arange(s, min(n, s + _ROWS))
+        w = filter_weights_rows(x0, r, radius)
+        out += (g[r] / w.sum(1)) @ w
+    return out
+
+
+def heaviside(phit: np.ndarray, beta: float) -> np.ndarray:
+    """Eq. 25."""
+    t = np.tanh(0.5 * beta)
+    return (t + np.tanh(beta * (np.asarray(phit, dtype=np.float64) - 0.5))) / (2.0 * t)
+
+
+def heaviside_derivative(phit: np.ndarray, beta: float) -> np.ndarray:
+    """d phibar / d phit of Eq. 25."""
+    th = np.tanh(beta * (np.asarray(phit, dtype=np.float64) - 0.5))
+    return beta * (1.0 - th * th) / (2.0 * np.tanh(0.5 * beta))
+
+
+def orientation(zeta: np.ndarray, delta: float) -> np.ndarray:
+    """Eq. 27 per row of zeta."""
+    zeta = np.asarray(zeta, dtype=np.float64)
+    return zeta / np.sqrt((zeta * zeta).sum(-1, keepdims=True) + delta)
+
+
+def magnetization(region: np.ndarray, br_mag: np.ndarray, zeta: np.ndarray, br_max: float,
+                  delta: float) -> np.ndarray:
+    """Eqs. 26-28: per-particle remanent field [N][d] from the region variables."""
+    region = np.asarray(region)
+    b = orientation(zeta, delta)
+    return br_max * np.asarray(br_mag, dtype=np.float64)[region, None] * b[region]
+
+
+def magnetization_transpose(region: np.ndarray, br_mag: np.ndarray, zeta: np.ndarray, br_max: float,
+                            delta: float, g_br: np.ndarray):
+    """Gradients of the region magnitudes [n_m] and orientation vectors [n_m][d]
+    from the per-particle gradient g_br [N][d]: region sums G_m = sum of g_br
+    over the region's particles, then g_mag_m = Br_max b_m . G_m and
+    g_zeta_m = Br_max Br_m (G_m / r_m - zeta_m (zeta_m . G_m) / r_m^3),
+    r_m = sqrt(|zeta_m|^2 + delta)."""
+    zeta = np.asarray(zeta, dtype=np.float64)
+    br_mag = np.asarray(br_mag, dtype=np.float64)
+    n_m, d = zeta.shape
+    G = np.zeros((n_m, d))
+    np.add.at(G, np.asarray(region), np.asarray(g_br, dtype=np.float64))
+    r = np.sqrt((zeta * zeta).sum(-1) + delta)
+    b = zeta / r[:, None]
+    g_mag = br_max * (b * G).sum(-1)
+    zg = (zeta * G).sum(-1)
+    g_zeta = br_max * br_mag[:, None] * (G / r[:, None] - zeta * (zg / r ** 3)[:, None])
+    return g_mag, g_zeta
+
+
+def front_end(x0, phi, radius, beta, region, br_mag, zeta, br_max, delta):
+    """The whole map: (phit, phibar, Br~) of every particle."""
+    phit = density_filter(x0, phi, radius)
+    return phit, heaviside(phit, beta), magnetization(region, br_mag, zeta, br_max, delta)
+
+
+def front_end_backward(x0, phi, radius, beta, region, br_mag, zeta, br_max, delta, g_density, g_br):
+    """Gradients of (phi, region magnitudes, region orientations) from the
+    gradients of the hot path's inputs (density = phibar, br = Br~)."""
+    phit = density_filter(x0, phi, radius)
+    g_phit = np.asarray(g_density, dtype=np.float64) * heaviside_derivative(phit, beta)
+    g_phi = density_filter_transpose(x0, g_phit, radius)
+    g_mag, g_zeta = magnetization_transpose(region, br_mag, zeta, br_max, delta, g_br)
+    return g_phi, g_mag, g_zeta
