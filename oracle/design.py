@@ -31,7 +31,9 @@ from __future__ import annotations
 
 import numpy as np
 
-_ROWS = 512   # rows of the pair matrix held at once
+def _rows_per_block(n: int) -> int:
+    """Rows of the pair matrix held at once (about 4M pairs)."""
+    return max(1, min(512, 4_000_000 // max(1, n)))
 
 
 def filter_weights_rows(x0: np.ndarray, rows: np.ndarray, radius: float) -> np.ndarray:
@@ -47,10 +49,11 @@ def density_filter(x0: np.ndarray, phi: np.ndarray, radius: float, rows=None) ->
     phi = np.asarray(phi, dtype=np.float64)
     rows = np.arange(len(phi)) if rows is None else np.asarray(rows)
     out = np.empty(len(rows))
-    for s in range(0, len(rows), _ROWS):
-        r = rows[s:s + _ROWS]
+    b = _rows_per_block(len(phi))
+    for s in range(0, len(rows), b):
+        r = rows[s:s + b]
         w = filter_weights_rows(x0, r, radius)
-        out[s:s + _ROWS] = (w @ phi) / w.sum(1)
+        out[s:s + b] = (w @ phi) / w.sum(1)
     return out
 
 
@@ -61,8 +64,9 @@ def density_filter_transpose(x0: np.ndarray, g: np.ndarray, radius: float) -> np
     g = np.asarray(g, dtype=np.float64)
     n = len(g)
     out = np.zeros(n)
-    for s in range(0, n, _ROWS):
-        r = np.arange(s, min(n, s + _ROWS))
+    b = _rows_per_block(n)
+    for s in range(0, n, b):
+        r = np.arange(s, min(n, s + b))
         w = filter_weights_rows(x0, r, radius)
         out += (g[r] / w.sum(1)) @ w
     return out

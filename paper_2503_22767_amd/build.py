@@ -1,7 +1,7 @@
 """Build the HIP library libmpm_mag.so for gfx950 (in-tree, next to this file).
 
 The engine is compiled once per (precision, dimension) variant in parallel, then
-linked with the C-ABI translation unit. All device code is built with packed
+linked with the C-ABI translation unit and the design front end. All device code is built with packed
 FP32 instructions disabled and hardware floating-point atomics enabled.
 """
 import concurrent.futures as cf
@@ -49,7 +49,8 @@ def build(verbose: bool = False) -> str:
         jobs.append([hipcc] + COMMON + [f"-DMPM_REAL={real}", f"-DMPM_DIM={dim}", f"-DMPM_FACTORY={fac}",
                                         "-c", os.path.join(CSRC, "engine_inst.hip"), "-o", obj])
     jobs.append([hipcc] + COMMON + ["-c", os.path.join(CSRC, "abi.hip"), "-o", os.path.join(BUILD, "abi.o")])
-    with cf.ThreadPoolExecutor(max_workers=min(5, os.cpu_count() or 1)) as ex:
+    jobs.append([hipcc] + COMMON + ["-c", os.path.join(CSRC, "design.hip"), "-o", os.path.join(BUILD, "design.o")])
+    with cf.ThreadPoolExecutor(max_workers=min(6, os.cpu_count() or 1)) as ex:
         for cmd in jobs:
             if verbose:
                 print(" ".join(cmd), flush=True)

@@ -1,24 +1,29 @@
-"""The C-ABI library loads on the host and exports every entry point that
-include/mpm_mag.h declares (no device calls)."""
+"""The C-ABI library loads on the host and exports every entry point that the
+headers under include/ declare (no device calls)."""
 import ctypes
+import glob
 import os
 import re
 
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "mpm_mag.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 def _declared():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(mpm_mag_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(mpm_mag_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
     names = _declared()
-    for need in ("mpm_mag_create", "mpm_mag_rollout", "mpm_mag_backward", "mpm_mag_destroy"):
+    for need in ("mpm_mag_create", "mpm_mag_rollout", "mpm_mag_backward", "mpm_mag_destroy",
+                 "mpm_mag_design_create", "mpm_mag_design_forward", "mpm_mag_design_backward",
+                 "mpm_mag_design_destroy"):
         assert need in names
 
 
