@@ -212,6 +212,62 @@ def grad_error(wl, insts, oracle_grads):
     return {k: float(np.linalg.norm(got[k] - ref[k]) / max(1e-300, np.linalg.norm(ref[k]))) for k in ref}
 
 
+def front_end(wl, reps=20):
+    """The design front end on the particle set of the workload's first
+    instance: filter radius 1.5 particle spacings, 8 regions by x slab, the
+    handle's precision. Times the neighbour-matrix build once, then forward and
+    backward calls with events on the stream they run on, and places each on
+    the HBM roofline by its algorithmic bytes:
+      forward:  matrix (4 B column + weight per entry), row offsets, 1/s, phi,
+                region ids, phit, density and br written: nnz (4 + r) + N (8 + 4r + d r)
+      backward: u = g H'/s (read g, phit, 1/s; write u), the matrix again with u
+                and g_phi, and the region sums (sorted ids and members, g_br):
+                nnz (4 + r) + N (12 + 6r + d r)."""
+    from paper_2503_22767_amd import design as PD
+    inst = wl.instances[0]
+    d, r = inst.params["dim"], (4 if wl.precision == 4 else 8)
+    h = inst.params["particle_volume"] ** (1.0 / d)
+    x0 = torch.as_tensor(inst.x0, device="cuda")
+    n = len(inst.x0)
+    xs = x0[:, 0]
+    region = ((xs - xs.min()) / (xs.max() - xs.min()) * 8).clamp(0, 7).to(torch.int32)
+    gen = torch.Generator(device="cpu").manual_seed(7)
+    dt = torch.float32 if wl.precision == 4 else torch.float64
+    rnd = lambda *shape: torch.rand(*shape, generator=gen, dtype=torch.float64).to(device="cuda", dtype=dt)
+    phi, mag, zeta = rnd(n), rnd(8), rnd(8, d) * 2 - 1
+    gd, gb = rnd(n) - 0.5, rnd(n, d) - 0.5
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fe = PD.MpmMagDesign(x0, 1.5 * h, region=region, n_regions=8, precision=wl.precision)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    try:
+        def ev_time(fn):
+            for _ in range(3):
+                fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) * 1e3 / reps   # us per call
+        f_us = ev_time(lambda: fe.forward(phi, mag, zeta, 8.0, 1.0, 1e-6))
+        b_us = ev_time(lambda: fe.backward(gd, gb))
+        nnz = fe.nnz
+    finally:
+        fe.close()
+    fb = nnz * (4 + r) + n * (8 + 4 * r + d * r)
+    bb = nnz * (4 + r) + n * (12 + 6 * r + d * r)
+    out = dict(particles=n, nnz=nnz, radius_spacings=1.5, regions=8, build_ms=round(build_ms, 2),
+               forward_us=round(f_us, 2), backward_us=round(b_us, 2), bytes_forward=fb, bytes_backward=bb,
+               bound="hbm", peak_gbs=HBM_PEAK_GBS,
+               forward_gbs=round(fb / f_us / 1e3, 1), backward_gbs=round(bb / b_us / 1e3, 1))
+    out["forward_frac"] = round(out["forward_gbs"] / HBM_PEAK_GBS, 4)
+    out["backward_frac"] = round(out["backward_gbs"] / HBM_PEAK_GBS, 4)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -226,6 +282,8 @@ def main():
                     help="pick launch options with the autotuner (cached) before timing")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized device buffer (reference kernel for HBM byte counters)")
+    ap.add_argument("--no-front-end", action="store_true", help="skip the design front-end leg")
+    ap.add_argument("--front-end-only", action="store_true", help="run only the design front-end leg")
     ap.add_argument("--compare-separate", action="store_true",
                     help="also time one handle per instance (default for the batched workload)")
     args = ap.parse_args()
@@ -254,6 +312,11 @@ def main():
         opts[k] = int(v)
     log(f"[bench] workload {wl.name}: {wl.description}; {len(wl.instances)} instance(s), "
         f"N={wl.n_particles}, T={wl.n_steps}")
+    if args.front_end_only:
+        fe = front_end(wl)
+        log(f"[bench] front end {fe}")
+        print(json.dumps(dict(front_end=fe)), flush=True)
+        return
     tuned = None
     if args.autotune:
         from paper_2503_22767_amd import autotune as A
@@ -297,6 +360,9 @@ def main():
                           for k, v in per_kernel.items()}
         log(f"[bench] roofline {rl}")
     sim.close()
+    if not args.no_front_end:
+        rec["front_end"] = front_end(wl)
+        log(f"[bench] front end {rec['front_end']}")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         cb, insts, grads = cpu_baseline(wl.name, wl)

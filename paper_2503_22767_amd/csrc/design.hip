@@ -23,10 +23,12 @@
 namespace mpm {
 namespace fe {
 
-constexpr int kRowLanes = 8;                     // lanes per matrix row
+constexpr int kRowLanes = 4;                     // lanes per matrix row
 constexpr int kRowsPerBlock = kBlock / kRowLanes;
 constexpr int kMaxCellBits = 24;                 // cell keys of the binning
 constexpr int kBoxBlocks = 1024;                 // blocks of the bounding-box pass
+constexpr int kChunk = 2048;                     // members per workgroup of the chunked region sums
+constexpr int kChunkedMinMean = 2048;            // mean region size from which region sums are chunked
 
 enum { kBadNonFinite = 1, kBadRegion = 2 };
 
@@ -291,8 +293,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const uint32_t* row_ptr, const 
     if (p >= 0 && g == 0) out[p] = acc;
 }
 
-// region sums G_m of g_br over the members, sorted by region: each wave sums
-// its runs of equal region and the run tails add them to the accumulators
+// region sums G_m of g_br over the members, sorted by region (many small
+// regions): each wave sums its runs of equal region and the run tails add them
+// to the accumulators
 template <typename real, int D>
 __global__ __launch_bounds__(kBlock) void k_region_sums(const uint32_t* reg_sorted, const uint32_t* members,
                                                         int64_t n, const real* g_br, double* G)
@@ -322,6 +325,38 @@ __global__ __launch_bounds__(kBlock) void k_region_sums(const uint32_t* reg_sort
         for (int k = 0; k < D; ++k) atomicAdd(&G[(int64_t)r * D + k], v[k]);
 }
 
+// Chunked region sums (few, large regions): chunk c covers sorted members
+// [c_lo[c], c_hi[c]) of one region; one workgroup sums it in double and writes
+// its partial, with no atomics.
+template <typename real, int D>
+__global__ __launch_bounds__(kBlock) void k_region_chunks(const uint32_t* members, const int64_t* c_lo,
+                                                          const int64_t* c_hi, const real* g_br, double* part)
+{
+    __shared__ double s_w[kWaves][D];
+    const int t = threadIdx.x;
+    const int64_t lo = c_lo[blockIdx.x], hi = c_hi[blockIdx.x];
+    double v[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) v[k] = 0.0;
+    for (int64_t j = lo + t; j < hi; j += kBlock) {
+        const int64_t p = members[j];
+#pragma unroll
+        for (int k = 0; k < D; ++k) v[k] += (double)g_br[p * D + k];
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    if ((t & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < D; ++k) s_w[t >> 6][k] = v[k];
+    __syncthreads();
+    if (t < D) {
+        double a = 0.0;
+        for (int w2 = 0; w2 < kWaves; ++w2) a += s_w[w2][t];
+        part[(int64_t)blockIdx.x * D + t] = a;
+    }
+}
+
 // region gradients from G_m: g_mag = Br_max b . G, g_zeta = Br_max Br_m (G / r - zeta (zeta . G) / r^3)
 template <typename real, int D>
 __device__ __forceinline__ void region_grad(const real* br_mag, const real* zeta, real br_max, real delta,
@@ -343,6 +378,7 @@ __device__ __forceinline__ void region_grad(const real* br_mag, const real* zeta
     }
 }
 
+// region gradients from the accumulated G_m (atomic path)
 template <typename real, int D>
 __global__ __launch_bounds__(kBlock) void k_region_grads(const double* G, int64_t n_m, const real* br_mag,
                                                          const real* zeta, real br_max, real delta, real* g_mag,
@@ -353,6 +389,29 @@ __global__ __launch_bounds__(kBlock) void k_region_grads(const double* G, int64_
     double g[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) g[k] = G[m * D + k];
+    region_grad<real, D>(br_mag, zeta, br_max, delta, m, g, g_mag, g_zeta);
+}
+
+// region gradients from the chunk partials [m_chunk[m], m_chunk[m + 1]) of each
+// region (chunked path): one wave per region, lanes striding over the
+// partials, a fixed reduction order
+template <typename real, int D>
+__global__ __launch_bounds__(64) void k_region_chunk_grads(const double* part, const int* m_chunk, int64_t n_m,
+                                                           const real* br_mag, const real* zeta, real br_max,
+                                                           real delta, real* g_mag, real* g_zeta)
+{
+    const int64_t m = blockIdx.x;
+    const int lane = threadIdx.x;
+    double g[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) g[k] = 0.0;
+    for (int c = m_chunk[m] + lane; c < m_chunk[m + 1]; c += 64)
+#pragma unroll
+        for (int k = 0; k < D; ++k) g[k] += part[(int64_t)c * D + k];
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+        for (int off = 32; off > 0; off >>= 1) g[k] += __shfl_xor(g[k], off, 64);
+    if (lane != 0) return;
     region_grad<real, D>(br_mag, zeta, br_max, delta, m, g, g_mag, g_zeta);
 }
 
@@ -404,7 +463,10 @@ struct Design final : Base {
     real* mag = nullptr;           // [n_m] and [n_m][D] of the last forward
     real* zeta = nullptr;
     real* u = nullptr;             // [N] scratch of backward
-    double* G = nullptr;           // [n_m][D] region sums
+    double* G = nullptr;           // [n_m][D] region sums, or [n_chunks][D] chunk partials
+    int64_t *c_lo = nullptr, *c_hi = nullptr;   // chunked region sums: member range of each chunk
+    int* m_chunk = nullptr;        // [n_m + 1] first chunk of each region
+    int n_chunks = 0;
     FwdParams<real> fp{};
     bool have_fwd = false;
     std::vector<void*> allocs;
@@ -557,7 +619,35 @@ struct Design final : Base {
             if ((st = dalloc(&reg_sorted, n)) || (st = dalloc(&members, n))) return st;
             FE_HIP(hipMemcpyAsync(reg_sorted, k[0], sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
             FE_HIP(hipMemcpyAsync(members, v[0], sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
-            if ((st = dalloc(&G, (size_t)n_m * D))) return st;
+            if (n / n_m >= kChunkedMinMean) {
+                // few large regions: chunks of at most kChunk members inside each region
+                std::vector<uint32_t> rs((size_t)n);
+                FE_HIP(hipMemcpyAsync(rs.data(), reg_sorted, sizeof(uint32_t) * n, hipMemcpyDeviceToHost, s));
+                FE_HIP(hipStreamSynchronize(s));
+                std::vector<int64_t> lo_h, hi_h;
+                std::vector<int> mc((size_t)n_m + 1, 0);
+                int64_t j = 0;
+                for (int64_t m = 0; m < n_m; ++m) {
+                    mc[m] = (int)lo_h.size();
+                    int64_t e = j;
+                    while (e < n && rs[e] == (uint32_t)m) ++e;
+                    for (int64_t a = j; a < e; a += kChunk) {
+                        lo_h.push_back(a);
+                        hi_h.push_back(std::min<int64_t>(e, a + kChunk));
+                    }
+                    j = e;
+                }
+                mc[n_m] = (int)lo_h.size();
+                n_chunks = (int)lo_h.size();
+                if ((st = dalloc(&c_lo, std::max(1, n_chunks))) || (st = dalloc(&c_hi, std::max(1, n_chunks))) ||
+                    (st = dalloc(&m_chunk, n_m + 1)) || (st = dalloc(&G, (size_t)std::max(1, n_chunks) * D)))
+                    return st;
+                FE_HIP(hipMemcpy(c_lo, lo_h.data(), sizeof(int64_t) * n_chunks, hipMemcpyHostToDevice));
+                FE_HIP(hipMemcpy(c_hi, hi_h.data(), sizeof(int64_t) * n_chunks, hipMemcpyHostToDevice));
+                FE_HIP(hipMemcpy(m_chunk, mc.data(), sizeof(int) * (n_m + 1), hipMemcpyHostToDevice));
+            } else if ((st = dalloc(&G, (size_t)n_m * D))) {
+                return st;
+            }
         }
         if ((st = dalloc(&phit, n)) || (st = dalloc(&u, n)) || (st = dalloc(&mag, n_m)) ||
             (st = dalloc(&zeta, (size_t)n_m * D)))
@@ -626,12 +716,24 @@ struct Design final : Base {
         }
         if (g_mag || g_zeta) {
             if (has_region) {
-                FE_HIP(hipMemsetAsync(G, 0, sizeof(double) * n_m * D, s));
-                hipLaunchKernelGGL((k_region_sums<real, D>), dim3(grid_of(N)), dim3(kBlock), 0, s,
-                                   (const uint32_t*)reg_sorted, (const uint32_t*)members, N, (const real*)g_br, G);
-                hipLaunchKernelGGL((k_region_grads<real, D>), dim3(grid_of(n_m)), dim3(kBlock), 0, s,
-                                   (const double*)G, n_m, (const real*)mag, (const real*)zeta, fp.br_max, fp.delta,
-                                   (real*)g_mag, (real*)g_zeta);
+                if (m_chunk) {
+                    if (n_chunks > 0)
+                        hipLaunchKernelGGL((k_region_chunks<real, D>), dim3(n_chunks), dim3(kBlock), 0, s,
+                                           (const uint32_t*)members, (const int64_t*)c_lo, (const int64_t*)c_hi,
+                                           (const real*)g_br, G);
+                } else {
+                    FE_HIP(hipMemsetAsync(G, 0, sizeof(double) * n_m * D, s));
+                    hipLaunchKernelGGL((k_region_sums<real, D>), dim3(grid_of(N)), dim3(kBlock), 0, s,
+                                       (const uint32_t*)reg_sorted, (const uint32_t*)members, N, (const real*)g_br, G);
+                }
+                if (m_chunk)
+                    hipLaunchKernelGGL((k_region_chunk_grads<real, D>), dim3((unsigned)n_m), dim3(64), 0, s,
+                                       (const double*)G, (const int*)m_chunk, n_m, (const real*)mag,
+                                       (const real*)zeta, fp.br_max, fp.delta, (real*)g_mag, (real*)g_zeta);
+                else
+                    hipLaunchKernelGGL((k_region_grads<real, D>), dim3(grid_of(n_m)), dim3(kBlock), 0, s,
+                                       (const double*)G, n_m, (const real*)mag, (const real*)zeta, fp.br_max,
+                                       fp.delta, (real*)g_mag, (real*)g_zeta);
             } else {
                 hipLaunchKernelGGL((k_particle_grads<real, D>), dim3(grid_of(N)), dim3(kBlock), 0, s,
                                    (const real*)g_br, N, (const real*)mag, (const real*)zeta, fp.br_max, fp.delta,

@@ -120,6 +120,32 @@ def test_empty_region_gets_zero_gradient():
     assert rel_norm(d_mag, g_mag) < 1e-12 and rel_norm(d_zeta, g_zeta) < 1e-12
 
 
+@pytest.mark.parametrize("precision", [8, 4])
+def test_chunked_region_sums_with_an_empty_region(precision):
+    """Few large regions (mean above 2048 members) take the chunked, atomic-free
+    region sums: 40,000 particles in 5 regions of 3 to 19 chunks each, region 2
+    empty. Region gradients need only the per-particle gradient, so the oracle
+    side is cheap."""
+    rng = np.random.default_rng(14)
+    n = 40000
+    x0 = rng.uniform(0.2, 0.8, (n, 2))
+    region = rng.choice([0, 1, 3, 4], size=n, p=[0.1, 0.2, 0.3, 0.4]).astype(np.int32)
+    mag, zeta = rng.uniform(0.2, 1, 5), rng.uniform(-1, 1, (5, 2))
+    gb = rng.standard_normal((n, 2))
+    fe = PD.MpmMagDesign(x0, 0.004, region=region, n_regions=5, precision=precision)
+    try:
+        fe.forward(rng.uniform(0, 1, n), mag, zeta, 8.0, 1.3, 1e-4)
+        _, d_mag, d_zeta = fe.backward(np.zeros(n), gb, want=(False, True, True))
+        torch.cuda.synchronize()
+        d_mag, d_zeta = d_mag.double().cpu().numpy(), d_zeta.double().cpu().numpy()
+    finally:
+        fe.close()
+    g_mag, g_zeta = OD.magnetization_transpose(region, mag, zeta, 1.3, 1e-4, gb)
+    tol = 1e-12 if precision == 8 else 1e-5
+    assert d_mag[2] == 0 and np.all(d_zeta[2] == 0)
+    assert rel_norm(d_mag, g_mag) <= tol and rel_norm(d_zeta, g_zeta) <= tol
+
+
 def test_errors_are_reported():
     c = _case(2, 4, 11)
     bad = c["region"].copy()
