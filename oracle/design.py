@@ -132,3 +132,51 @@ def front_end_backward(x0, phi, radius, beta, region, br_mag, zeta, br_max, delt
     g_phi = density_filter_transpose(x0, g_phit, radius)
     g_mag, g_zeta = magnetization_transpose(region, br_mag, zeta, br_max, delta, g_br)
     return g_phi, g_mag, g_zeta
+
+
+# --------------------------------------------------------------------------
+# Harmonic stimulus (Sec. 3.1.2, Eqs. 29-30)
+# --------------------------------------------------------------------------
+# The rollout's field program holds one row per step when each step is its own
+# segment (seg_steps = 1); row n is the field at the start of step n, t_n = n dt.
+
+def harmonic_frequency(f, f_min, f_max):
+    """fbar = (f_max - f_min) f + f_min (Eq. 29)."""
+    return (f_max - f_min) * np.asarray(f, dtype=np.float64) + f_min
+
+
+def harmonic_program(b_a, f, eta, n_steps, dt, b_max, f_min, f_max, delta):
+    """Rows [n_inst * n_steps][d]: instance k, step n gives
+    B_max B_a[k] sin(2 pi fbar_k t_n) b(eta_k), b = eta / sqrt(|eta|^2 + delta)."""
+    b_a = np.asarray(b_a, dtype=np.float64)
+    eta = np.asarray(eta, dtype=np.float64)
+    t = np.arange(n_steps) * dt
+    fbar = harmonic_frequency(f, f_min, f_max)
+    b = orientation(eta, delta)
+    s = np.sin(2.0 * np.pi * fbar[:, None] * t[None, :])            # [n_inst][T]
+    return (b_max * b_a[:, None, None] * s[:, :, None] * b[:, None, :]).reshape(-1, eta.shape[1])
+
+
+def harmonic_program_transpose(b_a, f, eta, n_steps, dt, b_max, f_min, f_max, delta, g_prog):
+    """Gradients of (B_a, f, eta) per instance from the program gradient
+    g_prog [n_inst * n_steps][d]: with s_n = sin(w t_n), c_n = cos(w t_n),
+    w = 2 pi fbar and q_n = b . G_n,
+      g_Ba  = B_max sum_n s_n q_n
+      g_f   = B_max B_a sum_n c_n 2 pi (f_max - f_min) t_n q_n
+      g_eta = B_max B_a (S / r - eta (eta . S) / r^3),  S = sum_n s_n G_n."""
+    b_a = np.asarray(b_a, dtype=np.float64)
+    eta = np.asarray(eta, dtype=np.float64)
+    n_inst, d = eta.shape
+    G = np.asarray(g_prog, dtype=np.float64).reshape(n_inst, n_steps, d)
+    t = np.arange(n_steps) * dt
+    w = 2.0 * np.pi * harmonic_frequency(f, f_min, f_max)
+    s = np.sin(w[:, None] * t[None, :])
+    c = np.cos(w[:, None] * t[None, :])
+    r = np.sqrt((eta * eta).sum(-1) + delta)
+    b = eta / r[:, None]
+    q = (G * b[:, None, :]).sum(-1)                                    # [n_inst][T]
+    g_ba = b_max * (s * q).sum(1)
+    g_f = b_max * b_a * (c * (2.0 * np.pi * (f_max - f_min)) * t[None, :] * q).sum(1)
+    S = (s[:, :, None] * G).sum(1)                                     # [n_inst][d]
+    g_eta = b_max * b_a[:, None] * (S / r[:, None] - eta * ((eta * S).sum(-1) / r ** 3)[:, None])
+    return g_ba, g_f, g_eta

@@ -154,3 +154,53 @@ def test_front_end_gradient_matches_central_differences(dim):
     g_phi, g_mag, g_z = D.front_end_backward(x0, phi, R, beta, region, mag, zeta, bmax, delta, gd, gb)
     adj = g_phi @ dphi + g_mag @ dmag + (g_z * dz).sum()
     assert abs(fd - adj) <= 1e-7 * abs(adj), (fd, adj)
+
+
+# ---------------------------------------------------------------- harmonic stimulus (Eqs. 29-30)
+
+def test_harmonic_program_shape_zero_start_bound_and_direction():
+    rng = np.random.default_rng(20)
+    b_a, f, eta = rng.uniform(0.2, 1, 2), rng.uniform(0, 1, 2), rng.uniform(-1, 1, (2, 3))
+    P = D.harmonic_program(b_a, f, eta, 400, 1e-3, 2.0, 1.0, 20.0, 0.0).reshape(2, 400, 3)
+    assert np.all(P[:, 0] == 0)                                   # sin(0)
+    mag = np.linalg.norm(P, axis=-1)
+    assert np.all(mag <= 2.0 * b_a[:, None] * (1 + 1e-14))       # |B| <= B_max B_a (delta = 0)
+    assert np.allclose(mag.max(1), 2.0 * b_a, rtol=1e-3)         # reached within the 0.4 s window
+    assert np.allclose(np.cross(P, eta[:, None, :]), 0, atol=1e-14)
+
+
+def test_harmonic_frequency_ends_and_period():
+    """f = 0 gives f_min and f = 1 gives f_max: the program repeats after
+    1 / fbar (here a whole number of steps)."""
+    dt = 1e-3
+    for f, fbar in ((0.0, 5.0), (1.0, 25.0)):
+        P = D.harmonic_program([1.0], [f], [[1.0, 0.0]], 1000, dt, 1.0, 5.0, 25.0, 0.0)
+        period = int(round(1.0 / fbar / dt))
+        assert np.allclose(P[period:], P[:-period], atol=1e-12)
+        # the first crest a quarter period in
+        assert abs(P[period // 4, 0] - 1.0) < 1e-12
+
+
+def test_harmonic_program_is_linear_in_the_magnitude():
+    P1 = D.harmonic_program([0.3], [0.4], [[0.2, -0.7, 0.1]], 50, 2e-3, 1.5, 2.0, 9.0, 1e-3)
+    P2 = D.harmonic_program([0.6], [0.4], [[0.2, -0.7, 0.1]], 50, 2e-3, 1.5, 2.0, 9.0, 1e-3)
+    assert np.allclose(P2, 2 * P1, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_harmonic_transpose_matches_central_differences(dim):
+    rng = np.random.default_rng(30 + dim)
+    n_inst, T, dt = 3, 300, 1e-3
+    b_a, f, eta = rng.uniform(0.2, 1, n_inst), rng.uniform(0, 1, n_inst), rng.uniform(-1, 1, (n_inst, dim))
+    g = rng.standard_normal((n_inst * T, dim))
+    args = (T, dt, 1.7, 2.0, 30.0, 1e-2)
+    dba, dff, de = rng.standard_normal(n_inst), rng.standard_normal(n_inst), rng.standard_normal((n_inst, dim))
+
+    def L(s):
+        return (D.harmonic_program(b_a + s * dba, f + s * dff, eta + s * de, *args) * g).sum()
+
+    e = 1e-6
+    fd = (L(e) - L(-e)) / (2 * e)
+    gba, gf, ge = D.harmonic_program_transpose(b_a, f, eta, *args, g)
+    adj = gba @ dba + gf @ dff + (ge * de).sum()
+    assert abs(fd - adj) <= 1e-7 * abs(adj), (fd, adj)
