@@ -217,7 +217,9 @@ def front_end(wl, reps=20):
     instance: filter radius 1.5 particle spacings, 8 regions by x slab, the
     handle's precision. Times the neighbour-matrix build once, then forward and
     backward calls with events on the stream they run on, and places each on
-    the HBM roofline by its algorithmic bytes:
+    the HBM roofline by its algorithmic bytes (the harmonic stimulus of every
+    instance over the rollout, a few hundred KB, is timed too; launch latency
+    bounds it):
       forward:  matrix (4 B column + weight per entry), row offsets, 1/s, phi,
                 region ids, phit, density and br written: nnz (4 + r) + N (8 + 4r + d r)
       backward: u = g H'/s (read g, phit, 1/s; write u), the matrix again with u
@@ -255,6 +257,14 @@ def front_end(wl, reps=20):
         f_us = ev_time(lambda: fe.forward(phi, mag, zeta, 8.0, 1.0, 1e-6))
         b_us = ev_time(lambda: fe.backward(gd, gb))
         nnz = fe.nnz
+        # harmonic stimulus of every instance over the rollout (one program row per step)
+        ni, T = len(wl.instances), wl.n_steps
+        hb, hf, he = rnd(ni), rnd(ni), rnd(ni, d) * 2 - 1
+        hg = rnd(ni * T, d) - 0.5
+        dt_s = inst.params["dt"]
+        hargs = (T, dt_s, 0.5, 1.0, 50.0, 1e-6)
+        hp_us = ev_time(lambda: PD.harmonic_program(hb, hf, he, *hargs))
+        hb_us = ev_time(lambda: PD.harmonic_backward(hb, hf, he, *hargs, hg))
     finally:
         fe.close()
     fb = nnz * (4 + r) + n * (8 + 4 * r + d * r)
@@ -262,7 +272,9 @@ def front_end(wl, reps=20):
     out = dict(particles=n, nnz=nnz, radius_spacings=1.5, regions=8, build_ms=round(build_ms, 2),
                forward_us=round(f_us, 2), backward_us=round(b_us, 2), bytes_forward=fb, bytes_backward=bb,
                bound="hbm", peak_gbs=HBM_PEAK_GBS,
-               forward_gbs=round(fb / f_us / 1e3, 1), backward_gbs=round(bb / b_us / 1e3, 1))
+               forward_gbs=round(fb / f_us / 1e3, 1), backward_gbs=round(bb / b_us / 1e3, 1),
+               harmonic=dict(instances=ni, steps=T, program_us=round(hp_us, 2), backward_us=round(hb_us, 2),
+                             bound="latency"))
     out["forward_frac"] = round(out["forward_gbs"] / HBM_PEAK_GBS, 4)
     out["backward_frac"] = round(out["backward_gbs"] / HBM_PEAK_GBS, 4)
     return out

@@ -1,5 +1,6 @@
 /*
  * mpm_mag_design.h: the design front end of the magneto-elastic MPM library.
+ * (The harmonic stimulus of Eqs. 29-30 is at the end of this file.)
  *
  * Maps the design variables of Sec. 3.1 to the per-particle inputs of
  * mpm_mag_rollout, and maps the gradients mpm_mag_backward returns back to
@@ -84,6 +85,44 @@ const char* mpm_mag_design_last_error(const mpm_mag_design* h);
 
 /* Release the handle and its device memory. NULL is accepted. */
 void mpm_mag_design_destroy(mpm_mag_design* h);
+
+/*
+ * Harmonic stimulus (Sec. 3.1.2, Eqs. 29-30) as a field program of one row per
+ * step, for instances created with n_segments = n_steps and seg_steps = 1
+ * (non-periodic), whose step n then takes row n, the field at t_n = n dt:
+ *   B(t_n) = B_max B_a sin(2 pi fbar t_n) b,  fbar = (f_max - f_min) f + f_min,
+ *   b = eta / sqrt(|eta|^2 + delta).
+ * Instance k has its own (B_a[k], f[k], eta[k]); all share the descriptor.
+ * Evaluated in double whatever the element type. No handle and no state.
+ */
+typedef struct {
+    int dim;                 /* 2 or 3 */
+    int n_inst;              /* >= 1 */
+    int n_steps;             /* >= 1; n_inst * n_steps <= 2^31 - 1 */
+    double dt;               /* > 0 */
+    double b_max;            /* B_max */
+    double f_min, f_max;     /* frequency range (finite) */
+    double delta;            /* >= 0; |eta|^2 + delta must be > 0 */
+} mpm_mag_harmonic_desc;
+
+/*
+ *   b_a    [n_inst]                    normalized magnitudes
+ *   f      [n_inst]                    normalized frequencies
+ *   eta    [n_inst][dim]               orientation vectors
+ *   b_prog [n_inst * n_steps][dim]     output, overwritten (instance-major)
+ * Returns EINVAL for a bad descriptor, precision or null pointer.
+ */
+int mpm_mag_harmonic_program(const mpm_mag_harmonic_desc* d, int precision, void* stream, const void* b_a,
+                             const void* f, const void* eta, void* b_prog);
+
+/*
+ * Transpose at (b_a, f, eta): from g_b_prog [n_inst * n_steps][dim] (e.g. the
+ * program gradient of mpm_mag_backward) to g_b_a [n_inst], g_f [n_inst] and
+ * g_eta [n_inst][dim] (outputs, overwritten; each may be NULL).
+ */
+int mpm_mag_harmonic_backward(const mpm_mag_harmonic_desc* d, int precision, void* stream, const void* b_a,
+                              const void* f, const void* eta, const void* g_b_prog, void* g_b_a, void* g_f,
+                              void* g_eta);
 
 #ifdef __cplusplus
 }

@@ -1,7 +1,8 @@
 // Design front end (Sec. 3.1, Eqs. 23-28): density filter over a neighbour
 // matrix built once from the initial positions, Heaviside projection,
 // magnetization parametrization with region sharing, and the transpose of
-// their Jacobian. C ABI in mpm_mag_design.h.
+// their Jacobian; and the harmonic stimulus (Sec. 3.1.2, Eqs. 29-30) as a
+// one-row-per-step field program with its transpose. C ABI in mpm_mag_design.h.
 //
 // Layout: the filter's weights form a CSR matrix whose rows follow the
 // caller's particle order (row p: the particles within R of p, ordered by cell,
@@ -429,6 +430,117 @@ __global__ __launch_bounds__(kBlock) void k_particle_grads(const real* g_br, int
     region_grad<real, D>(br_mag, zeta, br_max, delta, p, g, g_mag, g_zeta);
 }
 
+static int grid_of(int64_t n, int per = kBlock) { return (int)((n + per - 1) / per); }
+
+// ------------------------------------------------------ harmonic stimulus
+
+struct Harm {
+    int n_inst, T;
+    double dt, b_max, f_min, f_max, delta;
+};
+
+template <int D, typename real>
+__device__ __forceinline__ double orient(const real* eta, int k, double delta, double b[D], double* r)
+{
+    double r2 = delta;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        b[c] = (double)eta[k * D + c];
+        r2 += b[c] * b[c];
+    }
+    *r = sqrt(r2);
+#pragma unroll
+    for (int c = 0; c < D; ++c) b[c] /= *r;
+    return r2;
+}
+
+// row (k, n) of the program: B_max B_a sin(2 pi fbar t_n) b (Eqs. 29-30)
+template <typename real, int D>
+__global__ __launch_bounds__(kBlock) void k_harmonic(const real* b_a, const real* f, const real* eta, Harm hp,
+                                                     real* prog)
+{
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= (int64_t)hp.n_inst * hp.T) return;
+    const int k = (int)(idx / hp.T), n = (int)(idx % hp.T);
+    double b[D], r;
+    orient<D>(eta, k, hp.delta, b, &r);
+    const double fbar = (hp.f_max - hp.f_min) * (double)f[k] + hp.f_min;
+    const double a = hp.b_max * (double)b_a[k] * sin(2.0 * M_PI * fbar * ((double)n * hp.dt));
+#pragma unroll
+    for (int c = 0; c < D; ++c) prog[idx * D + c] = (real)(a * b[c]);
+}
+
+// one workgroup per instance: sums over the steps of s_n q_n, c_n t_n q_n and
+// s_n G_n (q_n = b . G_n), reduced in a fixed order
+template <typename real, int D>
+__global__ __launch_bounds__(kBlock) void k_harmonic_t(const real* b_a, const real* f, const real* eta, Harm hp,
+                                                       const real* g, real* g_ba, real* g_f, real* g_eta)
+{
+    constexpr int NV = 2 + D;
+    __shared__ double s_w[kWaves][NV];
+    const int k = blockIdx.x, t = threadIdx.x;
+    double b[D], r;
+    orient<D>(eta, k, hp.delta, b, &r);
+    const double w = 2.0 * M_PI * ((hp.f_max - hp.f_min) * (double)f[k] + hp.f_min);
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    for (int n = t; n < hp.T; n += kBlock) {
+        const double tn = (double)n * hp.dt;
+        const double sn = sin(w * tn), cn = cos(w * tn);
+        const real* G = g + ((int64_t)k * hp.T + n) * D;
+        double q = 0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            const double gc = (double)G[c];
+            q += b[c] * gc;
+            acc[2 + c] += sn * gc;
+        }
+        acc[0] += sn * q;
+        acc[1] += cn * tn * q;
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+        for (int off = 32; off > 0; off >>= 1) acc[v] += __shfl_xor(acc[v], off, 64);
+    if ((t & 63) == 0)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) s_w[t >> 6][v] = acc[v];
+    __syncthreads();
+    if (t != 0) return;
+    double tot[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        tot[v] = 0.0;
+        for (int w2 = 0; w2 < kWaves; ++w2) tot[v] += s_w[w2][v];
+    }
+    const double ba = (double)b_a[k];
+    if (g_ba) g_ba[k] = (real)(hp.b_max * tot[0]);
+    if (g_f) g_f[k] = (real)(hp.b_max * ba * 2.0 * M_PI * (hp.f_max - hp.f_min) * tot[1]);
+    if (g_eta) {
+        // J_b^T S with J_b = I / r - eta eta^T / r^3, eta = r b
+        double bs = 0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) bs += b[c] * tot[2 + c];
+#pragma unroll
+        for (int c = 0; c < D; ++c) g_eta[k * D + c] = (real)(hp.b_max * ba * (tot[2 + c] - b[c] * bs) / r);
+    }
+}
+
+template <typename real, int D>
+int harmonic_launch(const mpm_mag_harmonic_desc* d, hipStream_t s, const void* b_a, const void* f, const void* eta,
+                    const void* g, void* out0, void* out1, void* out2, bool backward)
+{
+    Harm hp{d->n_inst, d->n_steps, d->dt, d->b_max, d->f_min, d->f_max, d->delta};
+    if (backward)
+        hipLaunchKernelGGL((k_harmonic_t<real, D>), dim3(d->n_inst), dim3(kBlock), 0, s, (const real*)b_a,
+                           (const real*)f, (const real*)eta, hp, (const real*)g, (real*)out0, (real*)out1,
+                           (real*)out2);
+    else
+        hipLaunchKernelGGL((k_harmonic<real, D>), dim3((unsigned)grid_of((int64_t)d->n_inst * d->n_steps)),
+                           dim3(kBlock), 0, s, (const real*)b_a, (const real*)f, (const real*)eta, hp, (real*)out0);
+    return hipGetLastError() == hipSuccess ? MPM_MAG_OK : MPM_MAG_EHIP;
+}
+
 // ------------------------------------------------------------------- handle
 
 struct Base {
@@ -447,7 +559,6 @@ struct Base {
         if (e_ != hipSuccess) return fail(MPM_MAG_EHIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
     } while (0)
 
-static int grid_of(int64_t n, int per = kBlock) { return (int)((n + per - 1) / per); }
 
 template <typename real, int D>
 struct Design final : Base {
@@ -841,6 +952,44 @@ int64_t mpm_mag_design_nnz(const mpm_mag_design* h) { return h ? h->d->nnz : 0; 
 const char* mpm_mag_design_last_error(const mpm_mag_design* h)
 {
     return h ? h->last.c_str() : g_design_create_error.c_str();
+}
+
+static int harmonic_check(const mpm_mag_harmonic_desc* d, int precision)
+{
+    if (!d || (d->dim != 2 && d->dim != 3) || (precision != 4 && precision != 8) || d->n_inst < 1 ||
+        d->n_steps < 1 || (int64_t)d->n_inst * d->n_steps > 0x7fffffffLL || !(d->dt > 0) || !std::isfinite(d->dt) ||
+        !std::isfinite(d->b_max) || !std::isfinite(d->f_min) || !std::isfinite(d->f_max) || !(d->delta >= 0))
+        return MPM_MAG_EINVAL;
+    return MPM_MAG_OK;
+}
+
+static int harmonic_dispatch(const mpm_mag_harmonic_desc* d, int precision, hipStream_t s, const void* b_a,
+                             const void* f, const void* eta, const void* g, void* o0, void* o1, void* o2, bool bwd)
+{
+    if (precision == 4)
+        return d->dim == 2 ? mpm::fe::harmonic_launch<float, 2>(d, s, b_a, f, eta, g, o0, o1, o2, bwd)
+                           : mpm::fe::harmonic_launch<float, 3>(d, s, b_a, f, eta, g, o0, o1, o2, bwd);
+    return d->dim == 2 ? mpm::fe::harmonic_launch<double, 2>(d, s, b_a, f, eta, g, o0, o1, o2, bwd)
+                       : mpm::fe::harmonic_launch<double, 3>(d, s, b_a, f, eta, g, o0, o1, o2, bwd);
+}
+
+int mpm_mag_harmonic_program(const mpm_mag_harmonic_desc* d, int precision, void* stream, const void* b_a,
+                             const void* f, const void* eta, void* b_prog)
+{
+    const int st = harmonic_check(d, precision);
+    if (st) return st;
+    if (!b_a || !f || !eta || !b_prog) return MPM_MAG_EINVAL;
+    return harmonic_dispatch(d, precision, (hipStream_t)stream, b_a, f, eta, nullptr, b_prog, nullptr, nullptr, false);
+}
+
+int mpm_mag_harmonic_backward(const mpm_mag_harmonic_desc* d, int precision, void* stream, const void* b_a,
+                              const void* f, const void* eta, const void* g_b_prog, void* g_b_a, void* g_f,
+                              void* g_eta)
+{
+    const int st = harmonic_check(d, precision);
+    if (st) return st;
+    if (!b_a || !f || !eta || !g_b_prog) return MPM_MAG_EINVAL;
+    return harmonic_dispatch(d, precision, (hipStream_t)stream, b_a, f, eta, g_b_prog, g_b_a, g_f, g_eta, true);
 }
 
 void mpm_mag_design_destroy(mpm_mag_design* h)

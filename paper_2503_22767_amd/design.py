@@ -8,6 +8,11 @@ library, and there is no CPU fallback.
 `density` and `br` are the `density` and `br` inputs of MpmMag.rollout, so
 DesignFn composed with MpmMagFn gives gradients with respect to the design
 variables of Sec. 3.1 (phi, per-region magnitude and orientation).
+
+    b_prog = HarmonicFn.apply(b_a, f, eta, n_steps, dt, b_max, f_min, f_max, delta)
+
+is the harmonic stimulus (Sec. 3.1.2) as a field program of one row per step,
+for instances made with n_segments = n_steps and seg_steps = 1.
 """
 from __future__ import annotations
 
@@ -19,6 +24,11 @@ import torch
 from .mpm_mag import OK, MpmMagError, _ptr, lib as _mpm_lib
 
 _bound = False
+
+
+class HarmonicDesc(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n_inst", C.c_int), ("n_steps", C.c_int), ("dt", C.c_double),
+                ("b_max", C.c_double), ("f_min", C.c_double), ("f_max", C.c_double), ("delta", C.c_double)]
 
 
 def lib():
@@ -39,6 +49,11 @@ def lib():
         L.mpm_mag_design_last_error.restype = C.c_char_p
         L.mpm_mag_design_destroy.argtypes = [vp]
         L.mpm_mag_design_destroy.restype = None
+        hp = C.POINTER(HarmonicDesc)
+        L.mpm_mag_harmonic_program.argtypes = [hp, C.c_int, vp, vp, vp, vp, vp]
+        L.mpm_mag_harmonic_program.restype = C.c_int
+        L.mpm_mag_harmonic_backward.argtypes = [hp, C.c_int, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.mpm_mag_harmonic_backward.restype = C.c_int
         _bound = True
     return L
 
@@ -151,3 +166,64 @@ class DesignFn(torch.autograd.Function):
             g_br = torch.zeros((fe.N, fe.dim), dtype=fe.dtype, device=fe.device)
         g_phi, g_mag, g_zeta = fe.backward(g_density, g_br, want=(need[1], need[2], need[3]))
         return None, g_phi, g_mag, g_zeta, None, None, None
+
+
+def _harmonic_args(b_a, f, eta, n_steps, dt, b_max, f_min, f_max, delta):
+    eta = torch.as_tensor(eta)
+    dev = eta.device if eta.is_cuda else torch.device("cuda")
+    dtype = eta.dtype if eta.dtype in (torch.float32, torch.float64) else torch.float32
+    conv = lambda t: torch.as_tensor(t, device=dev).to(dtype).contiguous()
+    b_a, f, eta = conv(b_a), conv(f), conv(eta)
+    n_inst, dim = eta.shape
+    if tuple(b_a.shape) != (n_inst,) or tuple(f.shape) != (n_inst,):
+        raise ValueError("b_a and f must be [n_inst], eta [n_inst][dim]")
+    d = HarmonicDesc(int(dim), int(n_inst), int(n_steps), float(dt), float(b_max), float(f_min), float(f_max),
+                     float(delta))
+    prec = 4 if dtype == torch.float32 else 8
+    return d, prec, dev, dtype, b_a, f, eta
+
+
+def harmonic_program(b_a, f, eta, n_steps, dt, b_max, f_min, f_max, delta=1e-6):
+    """Field program [n_inst * n_steps][dim] of the harmonic stimulus (Eqs. 29-30)."""
+    d, prec, dev, dtype, b_a, f, eta = _harmonic_args(b_a, f, eta, n_steps, dt, b_max, f_min, f_max, delta)
+    out = torch.empty((d.n_inst * d.n_steps, d.dim), dtype=dtype, device=dev)
+    with torch.cuda.device(dev):
+        st = lib().mpm_mag_harmonic_program(C.byref(d), prec, C.c_void_p(torch.cuda.current_stream(dev).cuda_stream),
+                                            _ptr(b_a), _ptr(f), _ptr(eta), _ptr(out))
+    if st != OK:
+        raise MpmMagError(st, "mpm_mag_harmonic_program")
+    return out
+
+
+def harmonic_backward(b_a, f, eta, n_steps, dt, b_max, f_min, f_max, delta, g_b_prog, want=(True, True, True)):
+    """Gradients of (b_a, f, eta) from the program gradient g_b_prog."""
+    d, prec, dev, dtype, b_a, f, eta = _harmonic_args(b_a, f, eta, n_steps, dt, b_max, f_min, f_max, delta)
+    g = torch.as_tensor(g_b_prog, device=dev).to(dtype).contiguous()
+    if tuple(g.shape) != (d.n_inst * d.n_steps, d.dim):
+        raise ValueError("g_b_prog must be [n_inst * n_steps][dim]")
+    gb = torch.empty(d.n_inst, dtype=dtype, device=dev) if want[0] else None
+    gf = torch.empty(d.n_inst, dtype=dtype, device=dev) if want[1] else None
+    ge = torch.empty((d.n_inst, d.dim), dtype=dtype, device=dev) if want[2] else None
+    with torch.cuda.device(dev):
+        st = lib().mpm_mag_harmonic_backward(C.byref(d), prec, C.c_void_p(torch.cuda.current_stream(dev).cuda_stream),
+                                             _ptr(b_a), _ptr(f), _ptr(eta), _ptr(g), _ptr(gb), _ptr(gf), _ptr(ge))
+    if st != OK:
+        raise MpmMagError(st, "mpm_mag_harmonic_backward")
+    return gb, gf, ge
+
+
+class HarmonicFn(torch.autograd.Function):
+    """b_prog = HarmonicFn.apply(b_a, f, eta, n_steps, dt, b_max, f_min, f_max, delta)."""
+
+    @staticmethod
+    def forward(ctx, b_a, f, eta, n_steps, dt, b_max, f_min, f_max, delta=1e-6):
+        ctx.args = (n_steps, dt, b_max, f_min, f_max, delta)
+        ctx.save_for_backward(b_a, f, eta)
+        return harmonic_program(b_a, f, eta, n_steps, dt, b_max, f_min, f_max, delta)
+
+    @staticmethod
+    def backward(ctx, g):
+        b_a, f, eta = ctx.saved_tensors
+        need = ctx.needs_input_grad
+        gb, gf, ge = harmonic_backward(b_a, f, eta, *ctx.args, g, want=(need[0], need[1], need[2]))
+        return gb, gf, ge, None, None, None, None, None, None

@@ -254,3 +254,73 @@ def test_chain_through_the_rollout_matches_the_oracle_chain():
     finally:
         fe.close()
         sim.close()
+
+
+# ---------------------------------------------------------------- harmonic stimulus (Eqs. 29-30)
+
+@pytest.mark.parametrize("dim,n_inst", [(2, 1), (3, 3)])
+@pytest.mark.parametrize("precision", [8, 4])
+def test_harmonic_program_matches_oracle(dim, n_inst, precision):
+    rng = np.random.default_rng(40 + dim)
+    T, dt, bmax, fmin, fmax, delta = 4000, 5e-5, 0.8, 2.0, 60.0, 1e-4
+    b_a, f, eta = rng.uniform(0.1, 1, n_inst), rng.uniform(0, 1, n_inst), rng.uniform(-1, 1, (n_inst, dim))
+    g = rng.standard_normal((n_inst * T, dim))
+    dt_ = torch.float32 if precision == 4 else torch.float64
+    cu = lambda a: torch.as_tensor(a, dtype=dt_, device="cuda")
+    prog = PD.harmonic_program(cu(b_a), cu(f), cu(eta), T, dt, bmax, fmin, fmax, delta)
+    gb, gf, ge = PD.harmonic_backward(cu(b_a), cu(f), cu(eta), T, dt, bmax, fmin, fmax, delta, cu(g))
+    torch.cuda.synchronize()
+    # the oracle takes the inputs the device got
+    r = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64) if precision == 4 else a
+    ref = OD.harmonic_program(r(b_a), r(f), r(eta), T, dt, bmax, fmin, fmax, delta)
+    rgb, rgf, rge = OD.harmonic_program_transpose(r(b_a), r(f), r(eta), T, dt, bmax, fmin, fmax, delta, r(g))
+    vt, gt = (1e-13, 1e-12) if precision == 8 else (1e-6, 1e-6)
+    assert np.abs(prog.double().cpu().numpy() - ref).max() <= vt
+    assert rel_norm(gb.double().cpu().numpy(), rgb) <= gt
+    assert rel_norm(gf.double().cpu().numpy(), rgf) <= gt
+    assert rel_norm(ge.double().cpu().numpy(), rge) <= gt
+
+
+def test_harmonic_errors_are_reported():
+    e = torch.ones(1, 2, dtype=torch.float64, device="cuda")
+    o = torch.ones(1, dtype=torch.float64, device="cuda")
+    with pytest.raises(M.MpmMagError, match="invalid argument"):
+        PD.harmonic_program(o, o, e, 10, -1.0, 1.0, 0.0, 1.0, 0.0)   # dt <= 0
+    with pytest.raises(M.MpmMagError, match="invalid argument"):
+        PD.harmonic_program(o, o, e, 0, 1e-3, 1.0, 0.0, 1.0, 0.0)    # no steps
+
+
+def test_harmonic_chain_through_the_rollout_matches_the_oracle_chain():
+    """(B_a, f, eta) -> one-row-per-step program -> rollout -> loss, by torch
+    autograd through HarmonicFn and MpmMagFn, against the oracle's program, its
+    rollout adjoint and the program transpose (FP64)."""
+    import oracle as orc
+    T = 24
+    inst = W.make_tiny(seed=15, dim=3, n_steps=T, loss_kind=W.LOSS_TRAJ_VEL, floor=True, gravity=1.0,
+                       size=(0.3, 0.2, 0.25), n_grid=16, n_segments=T)
+    p = dict(inst.params)
+    assert p["n_segments"] == T and p["seg_steps"] == 1 and not p["periodic"]
+    dt = p["dt"]
+    fmin, fmax = 0.5 / (T * dt), 3.0 / (T * dt)   # half a period to three over the rollout
+    b_a, f, eta = np.array([0.7]), np.array([0.4]), np.array([[0.3, -0.8, 0.5]])
+    args = (T, dt, 0.5, fmin, fmax, 1e-4)
+    prog = OD.harmonic_program(b_a, f, eta, *args)
+    ref = orc.backward(p, inst.x0, inst.density, inst.br, prog, inst.target, inst.mask, ckpt_every=5)
+    rgb, rgf, rge = OD.harmonic_program_transpose(b_a, f, eta, *args, ref["g_b_prog"])
+    sim = M.MpmMag([p], [inst.n], precision=8)
+    try:
+        x0, density, br, _, target, mask = M.instance_tensors([inst], dtype=torch.float64)
+        tb = torch.tensor(b_a, dtype=torch.float64, device="cuda", requires_grad=True)
+        tf = torch.tensor(f, dtype=torch.float64, device="cuda", requires_grad=True)
+        te = torch.tensor(eta, dtype=torch.float64, device="cuda", requires_grad=True)
+        bp = PD.HarmonicFn.apply(tb, tf, te, *args)
+        loss, _ = M.MpmMagFn.apply(sim, x0, density, br, bp, target, mask)
+        loss.sum().backward()
+        torch.cuda.synchronize()
+        errs = dict(loss=abs(loss.item() - ref["loss"]), g_b_a=rel_norm(tb.grad.cpu().numpy(), rgb),
+                    g_f=rel_norm(tf.grad.cpu().numpy(), rgf), g_eta=rel_norm(te.grad.cpu().numpy(), rge))
+        log("harmonic chain fp64", errs)
+        assert errs["loss"] <= 1e-9 * max(1.0, abs(ref["loss"]))
+        assert errs["g_b_a"] <= 1e-9 and errs["g_f"] <= 1e-9 and errs["g_eta"] <= 1e-9
+    finally:
+        sim.close()
