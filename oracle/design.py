@@ -180,3 +180,21 @@ def harmonic_program_transpose(b_a, f, eta, n_steps, dt, b_max, f_min, f_max, de
     S = (s[:, :, None] * G).sum(1)                                     # [n_inst][d]
     g_eta = b_max * b_a[:, None] * (S / r[:, None] - eta * ((eta * S).sum(-1) / r ** 3)[:, None])
     return g_ba, g_f, g_eta
+
+
+# --------------------------------------------------------------------------
+# Optimizer update of the co-design loop (Sec. 3.2)
+# --------------------------------------------------------------------------
+
+def adam_step(p, g, m, v, t, lr, beta1, beta2, eps, lo, hi):
+    """One Adam update (Kingma and Ba, "Adam: A method for stochastic
+    optimization", ICLR 2015, Algorithm 1) at step t >= 1, then the variables
+    mapped back into [lo, hi] (the bounds of Eqs. 34c-d and 35c-d). Returns the
+    new (p, m, v)."""
+    g = np.asarray(g, dtype=np.float64)
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    p = np.asarray(p, dtype=np.float64) - lr * m_hat / (np.sqrt(v_hat) + eps)
+    return np.clip(p, lo, hi), m, v

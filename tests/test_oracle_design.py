@@ -204,3 +204,40 @@ def test_harmonic_transpose_matches_central_differences(dim):
     gba, gf, ge = D.harmonic_program_transpose(b_a, f, eta, *args, g)
     adj = gba @ dba + gf @ dff + (ge * de).sum()
     assert abs(fd - adj) <= 1e-7 * abs(adj), (fd, adj)
+
+
+# ---------------------------------------------------------------- optimizer update (Sec. 3.2)
+
+def test_adam_first_step_moves_each_variable_by_the_learning_rate():
+    """m_hat = g and v_hat = g^2 after one step, so with eps = 0 every variable
+    moves by lr against the sign of its gradient."""
+    g = np.array([3.0, -0.02, 1e-6, -7.5])
+    p, m, v = D.adam_step(np.full(4, 0.5), g, np.zeros(4), np.zeros(4), 1, 0.01, 0.9, 0.999, 0.0, 0.0, 1.0)
+    assert np.allclose(p, 0.5 - 0.01 * np.sign(g), rtol=0, atol=1e-15)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_adam_constant_gradient_steps_lr_each_iteration():
+    p, m, v = np.zeros(3), np.zeros(3), np.zeros(3)
+    g = np.array([2.0, -1.0, 0.5])
+    for t in range(1, 30):
+        p, m, v = D.adam_step(p, g, m, v, t, 1e-3, 0.9, 0.999, 0.0, -1.0, 1.0)
+        assert np.allclose(p, -1e-3 * t * np.sign(g), rtol=1e-12, atol=1e-15)
+
+
+def test_adam_maps_back_into_the_bounds_and_stops_without_gradient():
+    p, m, v = D.adam_step(np.array([0.995, 0.002]), np.array([-1.0, 1.0]), np.zeros(2), np.zeros(2), 1, 0.01,
+                          0.9, 0.999, 1e-8, 0.0, 1.0)
+    assert p[0] == 1.0 and p[1] == 0.0
+    # a zero gradient from the start leaves the variables where they are
+    q, _, _ = D.adam_step(np.array([0.3]), np.array([0.0]), np.zeros(1), np.zeros(1), 1, 0.01, 0.9, 0.999, 1e-8,
+                          0.0, 1.0)
+    assert q[0] == 0.3
+
+
+def test_adam_minimizes_a_separable_quadratic():
+    c = np.array([0.2, -0.4, 0.9])
+    p, m, v = np.zeros(3), np.zeros(3), np.zeros(3)
+    for t in range(1, 2001):
+        p, m, v = D.adam_step(p, 2 * (p - c), m, v, t, 0.01, 0.9, 0.999, 1e-8, -1.0, 1.0)
+    assert np.allclose(p, c, atol=1e-3)
