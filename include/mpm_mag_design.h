@@ -58,23 +58,28 @@ int mpm_mag_design_create(int dim, int64_t n_particles, const void* x0, double r
  *   zeta        [n_m][dim]   magnetization orientation vectors
  *   br_max      Br_max of Eq. 26
  *   delta       delta of Eq. 27, >= 0 (|zeta_m|^2 + delta must be > 0)
- *   density_out [N]          projected density (output, overwritten)
- *   br_out      [N][dim]     remanent flux density (output, overwritten)
+ *   copies      1..4096: the outputs hold this many consecutive copies of the
+ *               design, one per task instance that shares it (Eq. 35)
+ *   density_out [copies][N]      projected density (output, overwritten)
+ *   br_out      [copies][N][dim] remanent flux density (output, overwritten)
  * The handle keeps phit, beta, br_mag, zeta, br_max and delta for backward.
  */
 int mpm_mag_design_forward(mpm_mag_design* h, void* stream, const void* phi, double beta, const void* br_mag,
-                           const void* zeta, double br_max, double delta, void* density_out, void* br_out);
+                           const void* zeta, double br_max, double delta, int copies, void* density_out,
+                           void* br_out);
 
 /*
- * Transpose of the forward map's Jacobian at the last forward call.
- *   g_density [N]        gradient with respect to density (e.g. from mpm_mag_backward)
- *   g_br      [N][dim]   gradient with respect to br
+ * Transpose of the forward map's Jacobian at the last forward call; the
+ * gradients of the copies are summed (Eq. 35's shared design).
+ *   copies    1..4096
+ *   g_density [copies][N]      gradient with respect to density (e.g. from mpm_mag_backward)
+ *   g_br      [copies][N][dim] gradient with respect to br
  *   g_phi     [N]        output, overwritten, or NULL
  *   g_br_mag  [n_m]      output, overwritten, or NULL
  *   g_zeta    [n_m][dim] output, overwritten, or NULL
  * Returns ESTATE before a successful forward call.
  */
-int mpm_mag_design_backward(mpm_mag_design* h, void* stream, const void* g_density, const void* g_br,
+int mpm_mag_design_backward(mpm_mag_design* h, void* stream, int copies, const void* g_density, const void* g_br,
                             void* g_phi, void* g_br_mag, void* g_zeta);
 
 /* Stored entries of the neighbour matrix (pairs within the radius, self included). */
@@ -123,6 +128,19 @@ int mpm_mag_harmonic_program(const mpm_mag_harmonic_desc* d, int precision, void
 int mpm_mag_harmonic_backward(const mpm_mag_harmonic_desc* d, int precision, void* stream, const void* b_a,
                               const void* f, const void* eta, const void* g_b_prog, void* g_b_a, void* g_f,
                               void* g_eta);
+
+/*
+ * Optimizer update of the co-design loop (Sec. 3.2): one Adam step (Kingma and
+ * Ba, 2015) at step >= 1 on n variables, then the variables mapped back into
+ * [lo, hi] (Eqs. 34c-d, 35c-d):
+ *   m = beta1 m + (1 - beta1) g,  v = beta2 v + (1 - beta2) g^2,
+ *   param = clamp(param - lr (m / (1 - beta1^step)) / (sqrt(v / (1 - beta2^step)) + eps), lo, hi)
+ *   param [n] in/out; grad [n]; m, v [n] in/out, zero before the first step.
+ * Element type by precision (4 float, 8 double). Returns EINVAL for bad
+ * hyper-parameters (0 <= beta < 1, eps >= 0, lr >= 0, lo <= hi) or null arrays.
+ */
+int mpm_mag_adam_step(int precision, void* stream, int64_t n, void* param, const void* grad, void* m, void* v,
+                      int step, double lr, double beta1, double beta2, double eps, double lo, double hi);
 
 #ifdef __cplusplus
 }

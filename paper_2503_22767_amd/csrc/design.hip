@@ -30,6 +30,7 @@ constexpr int kMaxCellBits = 24;                 // cell keys of the binning
 constexpr int kBoxBlocks = 1024;                 // blocks of the bounding-box pass
 constexpr int kChunk = 2048;                     // members per workgroup of the chunked region sums
 constexpr int kChunkedMinMean = 2048;            // mean region size from which region sums are chunked
+constexpr int kMaxCopies = 4096;                 // design copies (tasks sharing the design)
 
 enum { kBadNonFinite = 1, kBadRegion = 2 };
 
@@ -250,7 +251,8 @@ template <typename real, int D>
 __global__ __launch_bounds__(kBlock) void k_forward(const uint32_t* row_ptr, const int* col, const real* w,
                                                     const real* inv_s, int64_t n, const real* phi,
                                                     const int32_t* region, const real* br_mag, const real* zeta,
-                                                    FwdParams<real> fp, real* phit, real* density, real* br)
+                                                    FwdParams<real> fp, int copies, real* phit, real* density,
+                                                    real* br)
 {
     const int g = threadIdx.x % kRowLanes;
     const int64_t p0 = (int64_t)blockIdx.x * kRowsPerBlock + threadIdx.x / kRowLanes;
@@ -260,26 +262,39 @@ __global__ __launch_bounds__(kBlock) void k_forward(const uint32_t* row_ptr, con
     if (g == 0) {
         const real pt = acc * inv_s[p];
         phit[p] = pt;
-        density[p] = (fp.t_half + tanh(fp.beta * (pt - real(0.5)))) * fp.inv_2t;
+        const real dp = (fp.t_half + tanh(fp.beta * (pt - real(0.5)))) * fp.inv_2t;
+        for (int c = 0; c < copies; ++c) density[c * n + p] = dp;
     }
     if (g < D) {
         const int64_t m = region ? (int64_t)region[p] : p;
         real z2 = fp.delta;
 #pragma unroll
         for (int k = 0; k < D; ++k) z2 += zeta[m * D + k] * zeta[m * D + k];
-        br[p * D + g] = fp.br_max * br_mag[m] * zeta[m * D + g] / sqrt(z2);
+        const real b = fp.br_max * br_mag[m] * zeta[m * D + g] / sqrt(z2);
+        for (int c = 0; c < copies; ++c) br[(c * n + p) * D + g] = b;
     }
+}
+
+// gradient of particle p summed over the copies of the design (tasks that
+// share it, Eq. 35): component k of [copies][n][D]
+template <typename real, int D>
+__device__ __forceinline__ double copies_sum(const real* g, int64_t n, int copies, int64_t p, int k)
+{
+    double s = 0.0;
+    for (int c = 0; c < copies; ++c) s += (double)g[(c * n + p) * D + k];
+    return s;
 }
 
 // u_p = g_density_p H'(phit_p) / s_p
 template <typename real>
 __global__ __launch_bounds__(kBlock) void k_scale(const real* g_density, const real* phit, const real* inv_s,
-                                                  int64_t n, FwdParams<real> fp, real* u)
+                                                  int64_t n, int copies, FwdParams<real> fp, real* u)
 {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (p >= n) return;
     const real th = tanh(fp.beta * (phit[p] - real(0.5)));
-    u[p] = g_density[p] * fp.beta * (real(1) - th * th) * fp.inv_2t * inv_s[p];
+    const real gd = (real)copies_sum<real, 1>(g_density, n, copies, p, 0);
+    u[p] = gd * fp.beta * (real(1) - th * th) * fp.inv_2t * inv_s[p];
 }
 
 // g_phi = W u (W symmetric)
@@ -299,7 +314,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const uint32_t* row_ptr, const 
 // to the accumulators
 template <typename real, int D>
 __global__ __launch_bounds__(kBlock) void k_region_sums(const uint32_t* reg_sorted, const uint32_t* members,
-                                                        int64_t n, const real* g_br, double* G)
+                                                        int64_t n, int copies, const real* g_br, double* G)
 {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63;
@@ -308,7 +323,7 @@ __global__ __launch_bounds__(kBlock) void k_region_sums(const uint32_t* reg_sort
     double v[D];
     const int64_t p = valid ? (int64_t)members[j] : 0;
 #pragma unroll
-    for (int k = 0; k < D; ++k) v[k] = valid ? (double)g_br[p * D + k] : 0.0;
+    for (int k = 0; k < D; ++k) v[k] = valid ? copies_sum<real, D>(g_br, n, copies, p, k) : 0.0;
     // inclusive scan inside runs of equal r
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -331,7 +346,8 @@ __global__ __launch_bounds__(kBlock) void k_region_sums(const uint32_t* reg_sort
 // its partial, with no atomics.
 template <typename real, int D>
 __global__ __launch_bounds__(kBlock) void k_region_chunks(const uint32_t* members, const int64_t* c_lo,
-                                                          const int64_t* c_hi, const real* g_br, double* part)
+                                                          const int64_t* c_hi, int64_t n, int copies,
+                                                          const real* g_br, double* part)
 {
     __shared__ double s_w[kWaves][D];
     const int t = threadIdx.x;
@@ -342,7 +358,7 @@ __global__ __launch_bounds__(kBlock) void k_region_chunks(const uint32_t* member
     for (int64_t j = lo + t; j < hi; j += kBlock) {
         const int64_t p = members[j];
 #pragma unroll
-        for (int k = 0; k < D; ++k) v[k] += (double)g_br[p * D + k];
+        for (int k = 0; k < D; ++k) v[k] += copies_sum<real, D>(g_br, n, copies, p, k);
     }
 #pragma unroll
     for (int k = 0; k < D; ++k)
@@ -418,15 +434,15 @@ __global__ __launch_bounds__(64) void k_region_chunk_grads(const double* part, c
 
 // every particle its own region: G_p = g_br_p
 template <typename real, int D>
-__global__ __launch_bounds__(kBlock) void k_particle_grads(const real* g_br, int64_t n, const real* br_mag,
-                                                           const real* zeta, real br_max, real delta, real* g_mag,
-                                                           real* g_zeta)
+__global__ __launch_bounds__(kBlock) void k_particle_grads(const real* g_br, int64_t n, int copies,
+                                                           const real* br_mag, const real* zeta, real br_max,
+                                                           real delta, real* g_mag, real* g_zeta)
 {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (p >= n) return;
     double g[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) g[k] = (double)g_br[p * D + k];
+    for (int k = 0; k < D; ++k) g[k] = copies_sum<real, D>(g_br, n, copies, p, k);
     region_grad<real, D>(br_mag, zeta, br_max, delta, p, g, g_mag, g_zeta);
 }
 
@@ -541,14 +557,37 @@ int harmonic_launch(const mpm_mag_harmonic_desc* d, hipStream_t s, const void* b
     return hipGetLastError() == hipSuccess ? MPM_MAG_OK : MPM_MAG_EHIP;
 }
 
+// ------------------------------------------------------- optimizer update
+
+// One Adam step (Kingma and Ba 2015) on n variables, then the bound map:
+// m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+// p = clamp(p - lr (m c1) / (sqrt(v c2) + eps), lo, hi), c1, c2 the bias
+// corrections. 1 - b1 and 1 - b2 come from the host in double: formed in FP32
+// from b2 = 0.999 the difference would be off by 1e-5.
+template <typename real>
+__global__ __launch_bounds__(kBlock) void k_adam(int64_t n, real* p, const real* g, real* m, real* v, real lr,
+                                                 real b1, real b2, real one_b1, real one_b2, real eps, real c1,
+                                                 real c2, real lo, real hi)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const real gi = g[i];
+    const real mi = b1 * m[i] + one_b1 * gi;
+    const real vi = b2 * v[i] + one_b2 * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const real q = p[i] - lr * (mi * c1) / (sqrt(vi * c2) + eps);
+    p[i] = q < lo ? lo : (q > hi ? hi : q);
+}
+
 // ------------------------------------------------------------------- handle
 
 struct Base {
     virtual ~Base() = default;
     virtual int forward(hipStream_t s, const void* phi, double beta, const void* br_mag, const void* zeta,
-                        double br_max, double delta, void* density, void* br) = 0;
-    virtual int backward(hipStream_t s, const void* g_density, const void* g_br, void* g_phi, void* g_mag,
-                         void* g_zeta) = 0;
+                        double br_max, double delta, int copies, void* density, void* br) = 0;
+    virtual int backward(hipStream_t s, int copies, const void* g_density, const void* g_br, void* g_phi,
+                         void* g_mag, void* g_zeta) = 0;
     int64_t nnz = 0;
     std::string err;
 };
@@ -787,11 +826,12 @@ struct Design final : Base {
     }
 
     int forward(hipStream_t s, const void* phi, double beta, const void* br_mag, const void* zeta_in,
-                double br_max, double delta, void* density, void* br) override
+                double br_max, double delta, int copies, void* density, void* br) override
     {
         err.clear();
         have_fwd = false;
         if (!phi || !br_mag || !zeta_in || !density || !br) return fail(MPM_MAG_EINVAL, "null array");
+        if (copies < 1 || copies > kMaxCopies) return fail(MPM_MAG_EINVAL, "copies must be in [1, 4096]");
         if (!(beta > 0) || !std::isfinite(beta)) return fail(MPM_MAG_EINVAL, "beta must be positive");
         if (!(delta >= 0) || !std::isfinite(br_max)) return fail(MPM_MAG_EINVAL, "bad br_max or delta");
         const double th = std::tanh(0.5 * beta);
@@ -804,22 +844,23 @@ struct Design final : Base {
         FE_HIP(hipMemcpyAsync(zeta, zeta_in, sizeof(real) * n_m * D, hipMemcpyDeviceToDevice, s));
         hipLaunchKernelGGL((k_forward<real, D>), dim3(grid_of(N, kRowsPerBlock)), dim3(kBlock), 0, s,
                            (const uint32_t*)row_ptr, (const int*)col, (const real*)w, (const real*)inv_s, N,
-                           (const real*)phi, (const int32_t*)region, (const real*)mag, (const real*)zeta, fp, phit,
-                           (real*)density, (real*)br);
+                           (const real*)phi, (const int32_t*)region, (const real*)mag, (const real*)zeta, fp, copies,
+                           phit, (real*)density, (real*)br);
         FE_HIP(hipGetLastError());
         have_fwd = true;
         return MPM_MAG_OK;
     }
 
-    int backward(hipStream_t s, const void* g_density, const void* g_br, void* g_phi, void* g_mag,
+    int backward(hipStream_t s, int copies, const void* g_density, const void* g_br, void* g_phi, void* g_mag,
                  void* g_zeta) override
     {
         err.clear();
         if (!have_fwd) return fail(MPM_MAG_ESTATE, "backward needs a forward call");
+        if (copies < 1 || copies > kMaxCopies) return fail(MPM_MAG_EINVAL, "copies must be in [1, 4096]");
         if ((g_phi && !g_density) || ((g_mag || g_zeta) && !g_br)) return fail(MPM_MAG_EINVAL, "null gradient input");
         if (g_phi) {
             hipLaunchKernelGGL((k_scale<real>), dim3(grid_of(N)), dim3(kBlock), 0, s, (const real*)g_density,
-                               (const real*)phit, (const real*)inv_s, N, fp, u);
+                               (const real*)phit, (const real*)inv_s, N, copies, fp, u);
             hipLaunchKernelGGL((k_spmv<real>), dim3(grid_of(N, kRowsPerBlock)), dim3(kBlock), 0, s,
                                (const uint32_t*)row_ptr, (const int*)col, (const real*)w, N, (const real*)u,
                                (real*)g_phi);
@@ -831,11 +872,12 @@ struct Design final : Base {
                     if (n_chunks > 0)
                         hipLaunchKernelGGL((k_region_chunks<real, D>), dim3(n_chunks), dim3(kBlock), 0, s,
                                            (const uint32_t*)members, (const int64_t*)c_lo, (const int64_t*)c_hi,
-                                           (const real*)g_br, G);
+                                           N, copies, (const real*)g_br, G);
                 } else {
                     FE_HIP(hipMemsetAsync(G, 0, sizeof(double) * n_m * D, s));
                     hipLaunchKernelGGL((k_region_sums<real, D>), dim3(grid_of(N)), dim3(kBlock), 0, s,
-                                       (const uint32_t*)reg_sorted, (const uint32_t*)members, N, (const real*)g_br, G);
+                                       (const uint32_t*)reg_sorted, (const uint32_t*)members, N, copies,
+                                       (const real*)g_br, G);
                 }
                 if (m_chunk)
                     hipLaunchKernelGGL((k_region_chunk_grads<real, D>), dim3((unsigned)n_m), dim3(64), 0, s,
@@ -847,8 +889,8 @@ struct Design final : Base {
                                        fp.delta, (real*)g_mag, (real*)g_zeta);
             } else {
                 hipLaunchKernelGGL((k_particle_grads<real, D>), dim3(grid_of(N)), dim3(kBlock), 0, s,
-                                   (const real*)g_br, N, (const real*)mag, (const real*)zeta, fp.br_max, fp.delta,
-                                   (real*)g_mag, (real*)g_zeta);
+                                   (const real*)g_br, N, copies, (const real*)mag, (const real*)zeta, fp.br_max,
+                                   fp.delta, (real*)g_mag, (real*)g_zeta);
             }
             FE_HIP(hipGetLastError());
         }
@@ -930,19 +972,21 @@ int mpm_mag_design_create(int dim, int64_t n_particles, const void* x0, double r
 }
 
 int mpm_mag_design_forward(mpm_mag_design* h, void* stream, const void* phi, double beta, const void* br_mag,
-                           const void* zeta, double br_max, double delta, void* density_out, void* br_out)
+                           const void* zeta, double br_max, double delta, int copies, void* density_out,
+                           void* br_out)
 {
     if (!h) return MPM_MAG_EINVAL;
-    const int st = h->d->forward((hipStream_t)stream, phi, beta, br_mag, zeta, br_max, delta, density_out, br_out);
+    const int st =
+        h->d->forward((hipStream_t)stream, phi, beta, br_mag, zeta, br_max, delta, copies, density_out, br_out);
     h->last = st ? h->d->err : std::string();
     return st;
 }
 
-int mpm_mag_design_backward(mpm_mag_design* h, void* stream, const void* g_density, const void* g_br, void* g_phi,
-                            void* g_br_mag, void* g_zeta)
+int mpm_mag_design_backward(mpm_mag_design* h, void* stream, int copies, const void* g_density, const void* g_br,
+                            void* g_phi, void* g_br_mag, void* g_zeta)
 {
     if (!h) return MPM_MAG_EINVAL;
-    const int st = h->d->backward((hipStream_t)stream, g_density, g_br, g_phi, g_br_mag, g_zeta);
+    const int st = h->d->backward((hipStream_t)stream, copies, g_density, g_br, g_phi, g_br_mag, g_zeta);
     h->last = st ? h->d->err : std::string();
     return st;
 }
@@ -990,6 +1034,29 @@ int mpm_mag_harmonic_backward(const mpm_mag_harmonic_desc* d, int precision, voi
     if (st) return st;
     if (!b_a || !f || !eta || !g_b_prog) return MPM_MAG_EINVAL;
     return harmonic_dispatch(d, precision, (hipStream_t)stream, b_a, f, eta, g_b_prog, g_b_a, g_f, g_eta, true);
+}
+
+int mpm_mag_adam_step(int precision, void* stream, int64_t n, void* param, const void* grad, void* m, void* v,
+                      int step, double lr, double beta1, double beta2, double eps, double lo, double hi)
+{
+    if ((precision != 4 && precision != 8) || n < 0 || step < 1 || !(lr >= 0) || !(beta1 >= 0 && beta1 < 1) ||
+        !(beta2 >= 0 && beta2 < 1) || !(eps >= 0) || !(lo <= hi))
+        return MPM_MAG_EINVAL;
+    if (n == 0) return MPM_MAG_OK;
+    if (!param || !grad || !m || !v) return MPM_MAG_EINVAL;
+    const double c1 = 1.0 / (1.0 - std::pow(beta1, step)), c2 = 1.0 / (1.0 - std::pow(beta2, step));
+    hipStream_t s = (hipStream_t)stream;
+    const dim3 grid((unsigned)mpm::fe::grid_of(n));
+    if (precision == 4)
+        hipLaunchKernelGGL(mpm::fe::k_adam<float>, grid, dim3(mpm::kBlock), 0, s, n, (float*)param,
+                           (const float*)grad, (float*)m, (float*)v, (float)lr, (float)beta1, (float)beta2,
+                           (float)(1.0 - beta1), (float)(1.0 - beta2), (float)eps, (float)c1, (float)c2, (float)lo,
+                           (float)hi);
+    else
+        hipLaunchKernelGGL(mpm::fe::k_adam<double>, grid, dim3(mpm::kBlock), 0, s, n, (double*)param,
+                           (const double*)grad, (double*)m, (double*)v, lr, beta1, beta2, 1.0 - beta1, 1.0 - beta2,
+                           eps, c1, c2, lo, hi);
+    return hipGetLastError() == hipSuccess ? MPM_MAG_OK : MPM_MAG_EHIP;
 }
 
 void mpm_mag_design_destroy(mpm_mag_design* h)

@@ -39,9 +39,9 @@ def lib():
         d = C.c_double
         L.mpm_mag_design_create.argtypes = [C.c_int, i64, vp, d, vp, C.c_int, C.c_int, vp, C.POINTER(vp)]
         L.mpm_mag_design_create.restype = C.c_int
-        L.mpm_mag_design_forward.argtypes = [vp, vp, vp, d, vp, vp, d, d, vp, vp]
+        L.mpm_mag_design_forward.argtypes = [vp, vp, vp, d, vp, vp, d, d, C.c_int, vp, vp]
         L.mpm_mag_design_forward.restype = C.c_int
-        L.mpm_mag_design_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.mpm_mag_design_backward.argtypes = [vp, vp, C.c_int, vp, vp, vp, vp, vp]
         L.mpm_mag_design_backward.restype = C.c_int
         L.mpm_mag_design_nnz.argtypes = [vp]
         L.mpm_mag_design_nnz.restype = i64
@@ -107,27 +107,30 @@ class MpmMagDesign:
     def nnz(self) -> int:
         return int(lib().mpm_mag_design_nnz(self._h))
 
-    def forward(self, phi, br_mag, zeta, beta: float, br_max: float = 1.0, delta: float = 1e-6):
+    def forward(self, phi, br_mag, zeta, beta: float, br_max: float = 1.0, delta: float = 1e-6, copies: int = 1):
+        """density [copies * N], br [copies * N][dim]: one copy per task sharing the design."""
         phi = self._arg(phi, (self.N,), "phi")
         br_mag = self._arg(br_mag, (self.n_m,), "br_mag")
         zeta = self._arg(zeta, (self.n_m, self.dim), "zeta")
-        density = torch.empty(self.N, dtype=self.dtype, device=self.device)
-        br = torch.empty((self.N, self.dim), dtype=self.dtype, device=self.device)
+        density = torch.empty(copies * self.N, dtype=self.dtype, device=self.device)
+        br = torch.empty((copies * self.N, self.dim), dtype=self.dtype, device=self.device)
         with torch.cuda.device(self.device):
             st = lib().mpm_mag_design_forward(self._h, self._stream(), _ptr(phi), float(beta), _ptr(br_mag),
-                                              _ptr(zeta), float(br_max), float(delta), _ptr(density), _ptr(br))
+                                              _ptr(zeta), float(br_max), float(delta), int(copies), _ptr(density),
+                                              _ptr(br))
         self._check(st, "mpm_mag_design_forward")
         return density, br
 
-    def backward(self, g_density, g_br, want=(True, True, True)):
-        g_density = self._arg(g_density, (self.N,), "g_density")
-        g_br = self._arg(g_br, (self.N, self.dim), "g_br")
+    def backward(self, g_density, g_br, want=(True, True, True), copies: int = 1):
+        """Gradients of (phi, br_mag, zeta), the copies' gradients summed."""
+        g_density = self._arg(g_density, (copies * self.N,), "g_density")
+        g_br = self._arg(g_br, (copies * self.N, self.dim), "g_br")
         g_phi = torch.empty(self.N, dtype=self.dtype, device=self.device) if want[0] else None
         g_mag = torch.empty(self.n_m, dtype=self.dtype, device=self.device) if want[1] else None
         g_zeta = torch.empty((self.n_m, self.dim), dtype=self.dtype, device=self.device) if want[2] else None
         with torch.cuda.device(self.device):
-            st = lib().mpm_mag_design_backward(self._h, self._stream(), _ptr(g_density), _ptr(g_br), _ptr(g_phi),
-                                               _ptr(g_mag), _ptr(g_zeta))
+            st = lib().mpm_mag_design_backward(self._h, self._stream(), int(copies), _ptr(g_density), _ptr(g_br),
+                                               _ptr(g_phi), _ptr(g_mag), _ptr(g_zeta))
         self._check(st, "mpm_mag_design_backward")
         return g_phi, g_mag, g_zeta
 
@@ -144,28 +147,29 @@ class MpmMagDesign:
 
 
 class DesignFn(torch.autograd.Function):
-    """density, br = DesignFn.apply(fe, phi, br_mag, zeta, beta, br_max, delta).
+    """density, br = DesignFn.apply(fe, phi, br_mag, zeta, beta, br_max, delta, copies).
 
     The backward runs the transpose on the device at the forward's point; it
     relies on the handle's last forward call being this one (as MpmMagFn
     relies on the last recorded rollout)."""
 
     @staticmethod
-    def forward(ctx, fe: MpmMagDesign, phi, br_mag, zeta, beta, br_max=1.0, delta=1e-6):
-        density, br = fe.forward(phi, br_mag, zeta, beta, br_max, delta)
+    def forward(ctx, fe: MpmMagDesign, phi, br_mag, zeta, beta, br_max=1.0, delta=1e-6, copies=1):
+        density, br = fe.forward(phi, br_mag, zeta, beta, br_max, delta, copies)
         ctx.fe = fe
+        ctx.copies = copies
         return density, br
 
     @staticmethod
     def backward(ctx, g_density, g_br):
         need = ctx.needs_input_grad
-        fe = ctx.fe
+        fe, c = ctx.fe, ctx.copies
         if g_density is None:
-            g_density = torch.zeros(fe.N, dtype=fe.dtype, device=fe.device)
+            g_density = torch.zeros(c * fe.N, dtype=fe.dtype, device=fe.device)
         if g_br is None:
-            g_br = torch.zeros((fe.N, fe.dim), dtype=fe.dtype, device=fe.device)
-        g_phi, g_mag, g_zeta = fe.backward(g_density, g_br, want=(need[1], need[2], need[3]))
-        return None, g_phi, g_mag, g_zeta, None, None, None
+            g_br = torch.zeros((c * fe.N, fe.dim), dtype=fe.dtype, device=fe.device)
+        g_phi, g_mag, g_zeta = fe.backward(g_density, g_br, want=(need[1], need[2], need[3]), copies=c)
+        return None, g_phi, g_mag, g_zeta, None, None, None, None
 
 
 def _harmonic_args(b_a, f, eta, n_steps, dt, b_max, f_min, f_max, delta):
