@@ -280,6 +280,46 @@ def front_end(wl, reps=20):
     return out
 
 
+def codesign(wl, iters=2):
+    """Co-design iterations (Sec. 3.2) over the workload's tasks sharing one
+    design: every task driven by its own harmonic stimulus (one program row per
+    step), 8 regions by x slab, filter radius 1.5 spacings. One warm-up
+    iteration (it sizes the checkpoints and the grid store), then `iters` timed
+    ones, host clock around each (an iteration ends by reading its losses)."""
+    from paper_2503_22767_amd import codesign as CD
+    insts = wl.instances
+    x0 = insts[0].x0
+    if not all(np.array_equal(i.x0, x0) for i in insts):
+        return None
+    params = []
+    for i in insts:
+        p = dict(i.params)
+        p.update(n_segments=wl.n_steps, seg_steps=1, periodic=0)
+        params.append(p)
+    n, d = len(x0), insts[0].params["dim"]
+    h = insts[0].params["particle_volume"] ** (1.0 / d)
+    T, dt = wl.n_steps, insts[0].params["dt"]
+    region = np.clip(((x0[:, 0] - x0[:, 0].min()) / np.ptp(x0[:, 0]) * 8).astype(np.int32), 0, 7)
+    cfg = CD.CoDesignConfig(radius=1.5 * h, b_max=0.5, f_min=2.0 / (T * dt), f_max=20.0 / (T * dt), lr=0.01)
+    cd = CD.CoDesign(params, x0, cfg, region=region, n_regions=8,
+                     targets=[i.target if i.target is not None else i.x0 for i in insts],
+                     masks=[i.mask if i.mask is not None else np.ones(n, np.uint8) for i in insts],
+                     precision=wl.precision, seed=3)
+    try:
+        cd.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(iters):
+            cd.step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / iters
+        hist = [float(f"{v:.6g}") for v in cd.history]
+    finally:
+        cd.close()
+    return dict(tasks=len(insts), particles_per_task=n, steps=T, regions=8, timed_iterations=iters,
+                ms_per_iteration=round(ms, 1), loss_history=hist)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -295,6 +335,8 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized device buffer (reference kernel for HBM byte counters)")
     ap.add_argument("--no-front-end", action="store_true", help="skip the design front-end leg")
+    ap.add_argument("--codesign", type=int, default=2, metavar="K",
+                    help="timed co-design iterations after one warm-up (0 skips the leg)")
     ap.add_argument("--front-end-only", action="store_true", help="run only the design front-end leg")
     ap.add_argument("--compare-separate", action="store_true",
                     help="also time one handle per instance (default for the batched workload)")
@@ -375,6 +417,11 @@ def main():
     if not args.no_front_end:
         rec["front_end"] = front_end(wl)
         log(f"[bench] front end {rec['front_end']}")
+    if args.codesign > 0:
+        cd = codesign(wl, args.codesign)
+        if cd is not None:
+            rec["codesign"] = cd
+            log(f"[bench] co-design {cd}")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         cb, insts, grads = cpu_baseline(wl.name, wl)
