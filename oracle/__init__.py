@@ -22,6 +22,15 @@ _LIB = None
 OK, EINVAL, ENOMEM, EDOMAIN, EINVERT, ENONFINITE = 0, 1, 2, 4, 5, 6
 
 
+MAX_OBSTACLES = 4
+OBST_HALFSPACE, OBST_SPHERE, OBST_BOX = 1, 2, 3
+
+
+class Obstacle(C.Structure):
+    _fields_ = [("kind", C.c_int), ("attached", C.c_int), ("a", C.c_double * 3), ("b", C.c_double * 3),
+                ("mu", C.c_double), ("vel", C.c_double * 3)]
+
+
 class Params(C.Structure):
     _fields_ = [
         ("dim", C.c_int), ("n_grid", C.c_int), ("dt", C.c_double), ("n_steps", C.c_int),
@@ -32,12 +41,28 @@ class Params(C.Structure):
         ("particle_volume", C.c_double),
         ("n_segments", C.c_int), ("seg_steps", C.c_int), ("periodic", C.c_int),
         ("loss_kind", C.c_int), ("loss_dir", C.c_double * 3),
+        ("n_obstacles", C.c_int), ("obst", Obstacle * MAX_OBSTACLES),
     ]
 
 
+def _vec3(v):
+    return (C.c_double * 3)(*([float(x) for x in list(v)] + [0.0] * 3)[:3])
+
+
 def params(p: dict) -> Params:
+    """Parameter struct of one instance; p["obstacles"] (optional) is a list of
+    dicts with kind, a, b, mu (default 0), vel (default 0) and attached (default 0)."""
     s = Params()
+    obst = list(p.get("obstacles", []))
+    if len(obst) > MAX_OBSTACLES:
+        raise ValueError("at most 4 obstacles")
+    s.n_obstacles = len(obst)
+    for j, o in enumerate(obst):
+        s.obst[j] = Obstacle(int(o["kind"]), int(o.get("attached", 0)), _vec3(o["a"]), _vec3(o["b"]),
+                             float(o.get("mu", 0.0)), _vec3(o.get("vel", [0.0, 0.0, 0.0])))
     for name, _ in Params._fields_:
+        if name in ("n_obstacles", "obst"):
+            continue
         val = p[name]
         if name in ("gravity", "loss_dir"):
             arr = (C.c_double * 3)(*[float(v) for v in list(val) + [0.0] * (3 - len(val))][:3])
@@ -198,17 +223,18 @@ def p2g(p, x, v, Cm, F, phi, br3, B):
     return m, mom
 
 
-def grid(p, m, mom):
+def grid(p, m, mom, step=0):
+    """Grid update of step `step` (moving obstacles sit at a + v_b step dt)."""
     G = num_nodes(p)
     v = np.zeros((G, 3))
-    lib().orc_grid(C.byref(params(p)), _d(_f64(m, (G,))), _d(_f64(mom, (G, 3))), _d(v))
+    lib().orc_grid(C.byref(params(p)), int(step), _d(_f64(m, (G,))), _d(_f64(mom, (G, 3))), _d(v))
     return v
 
 
-def grid_adj(p, m, mom, vbar):
+def grid_adj(p, m, mom, vbar, step=0):
     G = num_nodes(p)
     pbar = np.zeros((G, 3)); mbar = np.zeros(G)
-    lib().orc_grid_adj(C.byref(params(p)), _d(_f64(m, (G,))), _d(_f64(mom, (G, 3))),
+    lib().orc_grid_adj(C.byref(params(p)), int(step), _d(_f64(m, (G,))), _d(_f64(mom, (G, 3))),
                        _d(_f64(vbar, (G, 3))), _d(pbar), _d(mbar))
     return pbar, mbar
 

@@ -33,6 +33,14 @@
  *     the node moves into the floor (normal +y, static floor). |v_t| = 0 gives 0.
  *     Domain walls (b cells) zero the component pointing out of the domain.
  *     Attached (clamped) nodes x_i <= clamp_xmax get v = 0 (applied last).
+ *   - Obstacles (the solid boundaries of Eq. 18 beyond the floor): analytic
+ *     shapes (half-space, sphere, axis-aligned box) translating with a constant
+ *     velocity v_b, at position a + v_b t_n during step n. A node lies on the
+ *     boundary when the shape's signed distance at the node is <= 0; the normal
+ *     is the distance's gradient. Such a node whose velocity relative to v_b
+ *     points into the shape applies Eq. 18 relative to v_b (no-slip: v = v_b);
+ *     an attached obstacle sets v = v_b whatever the velocity. Obstacles act
+ *     after the floor, in order, before walls and clamp.
  *   - Piecewise-constant field: segment k(n) = n / L (periodic: mod S, else
  *     clamped to S-1), B evaluated at the start of the step.
  *
@@ -51,6 +59,17 @@ enum {
 };
 enum { ORC_LOSS_FINAL_MSE = 0, ORC_LOSS_COM_DISP = 1, ORC_LOSS_TRAJ_VEL = 2, ORC_LOSS_TIP_DISP = 3 };
 
+enum { ORC_MAX_OBST = 4 };
+enum { ORC_OBST_NONE = 0, ORC_OBST_HALFSPACE = 1, ORC_OBST_SPHERE = 2, ORC_OBST_BOX = 3 };
+
+typedef struct {
+    int kind, attached;
+    double a[3];     /* half-space: a point of its plane; sphere, box: centre at t = 0 */
+    double b[3];     /* half-space: outward normal; sphere: b[0] radius; box: half extents */
+    double mu;       /* friction; INFINITY: no-slip */
+    double vel[3];   /* v_b */
+} orc_obstacle;
+
 typedef struct {
     int dim, n_grid;
     double dt;
@@ -65,6 +84,8 @@ typedef struct {
     int n_segments, seg_steps, periodic;
     int loss_kind;
     double loss_dir[3];
+    int n_obstacles;
+    orc_obstacle obst[ORC_MAX_OBST];
 } orc_params;
 
 typedef struct {
@@ -372,8 +393,80 @@ static int floor_contact(const orc_params* P, double u[3])
     return 2;
 }
 
-/* Eqs. 16-18 for one node: returns v; vhat = p/m before forces */
-static void grid_node(const orc_params* P, int g, double m, const double p[3], double v[3])
+/* Signed distance of obstacle O at node position x during step n, and its
+ * outward normal; <= 0 on and inside the solid. */
+static double obstacle_sdf(const orc_params* P, const orc_obstacle* O, int n, const double x[3], double nrm[3])
+{
+    double t = n * P->dt;
+    double y[3];
+    for (int k = 0; k < 3; ++k) y[k] = (k < P->dim) ? x[k] - (O->a[k] + O->vel[k] * t) : 0.0;
+    nrm[0] = nrm[1] = nrm[2] = 0.0;
+    if (O->kind == ORC_OBST_HALFSPACE) {
+        double len = 0.0;
+        for (int k = 0; k < P->dim; ++k) len += O->b[k] * O->b[k];
+        len = sqrt(len);
+        double d = 0.0;
+        for (int k = 0; k < P->dim; ++k) {
+            nrm[k] = O->b[k] / len;
+            d += y[k] * nrm[k];
+        }
+        return d;
+    }
+    if (O->kind == ORC_OBST_SPHERE) {
+        double r = 0.0;
+        for (int k = 0; k < P->dim; ++k) r += y[k] * y[k];
+        r = sqrt(r);
+        if (r > 0.0)
+            for (int k = 0; k < P->dim; ++k) nrm[k] = y[k] / r;
+        else
+            nrm[1] = 1.0;
+        return r - O->b[0];
+    }
+    if (O->kind == ORC_OBST_BOX) {
+        double best = -INFINITY;
+        int kb = 0;
+        for (int k = 0; k < P->dim; ++k) {
+            double q = fabs(y[k]) - O->b[k];
+            if (q > best) { best = q; kb = k; }
+        }
+        nrm[kb] = y[kb] < 0.0 ? -1.0 : 1.0;
+        return best;   /* exact inside (<= 0), a lower bound outside */
+    }
+    return INFINITY;
+}
+
+/* contact of Eq. 18 against a boundary with velocity vb and outward normal
+ * nrm on node velocity u (3 components); returns 0 untouched, 1 set to vb,
+ * 2 sliding */
+static int obstacle_contact(const orc_params* P, const orc_obstacle* O, const double nrm[3], double u[3])
+{
+    double r[3], vn = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        r[k] = (k < P->dim) ? u[k] - O->vel[k] : 0.0;
+        vn += r[k] * nrm[k];
+    }
+    if (O->attached) {
+        for (int k = 0; k < 3; ++k) u[k] = (k < P->dim) ? O->vel[k] : 0.0;
+        return 1;
+    }
+    if (!(vn < 0.0)) return 0;
+    double tv[3], t = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        tv[k] = r[k] - vn * nrm[k];
+        t += tv[k] * tv[k];
+    }
+    t = sqrt(t);
+    double sl = t + O->mu * vn;
+    if (isinf(O->mu) || t == 0.0 || sl <= 0.0) {
+        for (int k = 0; k < 3; ++k) u[k] = (k < P->dim) ? O->vel[k] : 0.0;
+        return 1;
+    }
+    for (int k = 0; k < 3; ++k) u[k] = (k < P->dim) ? O->vel[k] + sl / t * tv[k] : 0.0;
+    return 2;
+}
+
+/* Eqs. 16-18 for one node during step n: returns v; vhat = p/m before forces */
+static void grid_node(const orc_params* P, int g, int n, double m, const double p[3], double v[3])
 {
     if (!(m > 0.0)) { v[0] = v[1] = v[2] = 0.0; return; }
     int ijk[3];
@@ -386,6 +479,11 @@ static void grid_node(const orc_params* P, int g, double m, const double p[3], d
         u[k] = (k < P->dim) ? vh + P->dt * (P->gravity[k] - c * vh) : 0.0;
     }
     if (P->floor_on && ijk[1] * dx <= P->floor_y) floor_contact(P, u);
+    double xi[3] = {ijk[0] * dx, ijk[1] * dx, ijk[2] * dx};
+    for (int j = 0; j < P->n_obstacles; ++j) {
+        double nrm[3];
+        if (obstacle_sdf(P, &P->obst[j], n, xi, nrm) <= 0.0) obstacle_contact(P, &P->obst[j], nrm, u);
+    }
     int b = P->wall_cells;
     for (int k = 0; k < P->dim; ++k) {
         if (ijk[k] < b && u[k] < 0.0) u[k] = 0.0;
@@ -395,10 +493,10 @@ static void grid_node(const orc_params* P, int g, double m, const double p[3], d
     for (int k = 0; k < 3; ++k) v[k] = u[k];
 }
 
-void orc_grid(const orc_params* P, const double* m, const double* p, double* v)
+void orc_grid(const orc_params* P, int n, const double* m, const double* p, double* v)
 {
     int G = n_nodes(P);
-    for (int g = 0; g < G; ++g) grid_node(P, g, m[g], p + 3 * g, v + 3 * g);
+    for (int g = 0; g < G; ++g) grid_node(P, g, n, m[g], p + 3 * g, v + 3 * g);
 }
 
 /* Eqs. 19-22: new particle state from grid velocities v[G][3] */
@@ -448,13 +546,13 @@ int orc_g2p(const orc_params* P, int N, const orc_particle* s, const double* v, 
 }
 
 /* one full step n: P2G, grid update, G2P. Work arrays m[G], p[3G], v[3G]. */
-static int step_forward(const orc_params* P, int N, const orc_particle* s, const double* phi,
+static int step_forward(const orc_params* P, int N, int n, const orc_particle* s, const double* phi,
                         const double* br3, const double B[3], double* m, double* p, double* v,
                         orc_particle* out)
 {
     int e = orc_p2g(P, N, s, phi, br3, B, m, p);
     if (e) return e;
-    orc_grid(P, m, p, v);
+    orc_grid(P, n, m, p, v);
     return orc_g2p(P, N, s, v, out);
 }
 
@@ -554,8 +652,35 @@ static void floor_slide_adj(const orc_params* P, const double u[3], double gbar[
     for (int k = 0; k < 3; ++k) gbar[k] = out[k];
 }
 
-/* transpose of Eqs. 16-18 for one node: vbar -> (pbar, mbar) */
-static void grid_node_adj(const orc_params* P, int g, double m, const double p[3], const double vbar[3],
+/* transpose of the obstacle slide map u -> vb + (1 + mu vn / t) P (u - vb) at
+ * input u (P = I - n n^T, vn = n . (u - vb), t = |P (u - vb)|):
+ * J^T g = (1 + mu vn / t) P g + mu (n / t - vn tv / t^3) (tv . g) */
+static void obstacle_slide_adj(const orc_params* P, const orc_obstacle* O, const double nrm[3], const double u[3],
+                               double g[3])
+{
+    double r[3], vn = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        r[k] = (k < P->dim) ? u[k] - O->vel[k] : 0.0;
+        vn += r[k] * nrm[k];
+    }
+    double tv[3], t = 0.0, ng = 0.0, tg = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        tv[k] = r[k] - vn * nrm[k];
+        t += tv[k] * tv[k];
+        ng += nrm[k] * g[k];
+        tg += tv[k] * g[k];
+    }
+    t = sqrt(t);
+    double out[3];
+    for (int k = 0; k < 3; ++k) {
+        double pg = g[k] - ng * nrm[k];
+        out[k] = (1.0 + O->mu * vn / t) * pg + O->mu * (nrm[k] / t - vn * tv[k] / (t * t * t)) * tg;
+    }
+    for (int k = 0; k < 3; ++k) g[k] = out[k];
+}
+
+/* transpose of Eqs. 16-18 for one node during step n: vbar -> (pbar, mbar) */
+static void grid_node_adj(const orc_params* P, int g, int n, double m, const double p[3], const double vbar[3],
                           double pbar[3], double* mbar)
 {
     pbar[0] = pbar[1] = pbar[2] = 0.0;
@@ -573,13 +698,27 @@ static void grid_node_adj(const orc_params* P, int g, double m, const double p[3
     }
     int floor_branch = 0;
     if (P->floor_on && ijk[1] * dx <= P->floor_y) floor_branch = floor_contact(P, u1);
-    /* reverse order: clamp, walls, floor */
+    /* obstacles in order, keeping each one's input velocity, branch and normal */
+    double xi[3] = {ijk[0] * dx, ijk[1] * dx, ijk[2] * dx};
+    double ob_in[ORC_MAX_OBST][3], ob_n[ORC_MAX_OBST][3];
+    int ob_branch[ORC_MAX_OBST];
+    for (int j = 0; j < P->n_obstacles; ++j) {
+        for (int k = 0; k < 3; ++k) ob_in[j][k] = u1[k];
+        ob_branch[j] = 0;
+        if (obstacle_sdf(P, &P->obst[j], n, xi, ob_n[j]) <= 0.0)
+            ob_branch[j] = obstacle_contact(P, &P->obst[j], ob_n[j], u1);
+    }
+    /* reverse order: clamp, walls, obstacles (last first), floor */
     double gb[3] = {vbar[0], vbar[1], vbar[2]};
     if (P->clamp_xmax >= 0.0 && ijk[0] * dx <= P->clamp_xmax) gb[0] = gb[1] = gb[2] = 0.0;
     int b = P->wall_cells;
     for (int k = 0; k < P->dim; ++k) {
         if (ijk[k] < b && u1[k] < 0.0) gb[k] = 0.0;
         if (ijk[k] >= P->n_grid - b && u1[k] > 0.0) gb[k] = 0.0;
+    }
+    for (int j = P->n_obstacles - 1; j >= 0; --j) {
+        if (ob_branch[j] == 1) gb[0] = gb[1] = gb[2] = 0.0;
+        else if (ob_branch[j] == 2) obstacle_slide_adj(P, &P->obst[j], ob_n[j], ob_in[j], gb);
     }
     if (floor_branch == 1) gb[0] = gb[1] = gb[2] = 0.0;
     else if (floor_branch == 2) floor_slide_adj(P, u0, gb);
@@ -591,11 +730,11 @@ static void grid_node_adj(const orc_params* P, int g, double m, const double p[3
     *mbar = -(vhb[0] * vh[0] + vhb[1] * vh[1] + vhb[2] * vh[2]) / m;
 }
 
-void orc_grid_adj(const orc_params* P, const double* m, const double* p, const double* vbar,
+void orc_grid_adj(const orc_params* P, int n, const double* m, const double* p, const double* vbar,
                   double* pbar, double* mbar)
 {
     int G = n_nodes(P);
-    for (int g = 0; g < G; ++g) grid_node_adj(P, g, m[g], p + 3 * g, vbar + 3 * g, pbar + 3 * g, mbar + g);
+    for (int g = 0; g < G; ++g) grid_node_adj(P, g, n, m[g], p + 3 * g, vbar + 3 * g, pbar + 3 * g, mbar + g);
 }
 
 /*
@@ -807,7 +946,7 @@ int orc_rollout(const orc_params* P, int N, const double* x0, const double* v0, 
     for (int n = 0; n < P->n_steps; ++n) {
         double B[3];
         field_at(P, bprog, n, B);
-        err = step_forward(P, N, s, phi, br3, B, m, p, v, t);
+        err = step_forward(P, N, n, s, phi, br3, B, m, p, v, t);
         if (err) goto done;
         orc_particle* tmp = s; s = t; t = tmp;
         if (P->loss_kind == ORC_LOSS_TRAJ_VEL && N) traj += traj_step(P, N, s, phi, M);
@@ -838,7 +977,7 @@ static int reverse_step(const orc_params* P, int N, int n, const orc_particle* s
     field_at(P, bprog, n, B);
     int e = orc_p2g(P, N, sn, phi, br3, B, m, p);
     if (e) return e;
-    orc_grid(P, m, p, v);
+    orc_grid(P, n, m, p, v);
     if (P->loss_kind == ORC_LOSS_TRAJ_VEL)
         for (int q = 0; q < N; ++q) {
             double mq = particle_mass(P, phi[q]);
@@ -846,7 +985,7 @@ static int reverse_step(const orc_params* P, int N, int n, const orc_particle* s
         }
     e = orc_g2p_adj(P, N, sn, v, adj, vbar, adj0);
     if (e) return e;
-    orc_grid_adj(P, m, p, vbar, pbar, mbar);
+    orc_grid_adj(P, n, m, p, vbar, pbar, mbar);
     double gB[3] = {0, 0, 0};
     e = orc_p2g_adj(P, N, sn, phi, br3, B, pbar, mbar, adj0, gphi, gbr3, gB);
     if (e) return e;
@@ -905,7 +1044,7 @@ int orc_backward(const orc_params* P, int N, const double* x0, const double* phi
         if (n % K == 0) memcpy(ck + (size_t)(n / K) * N, cur, ps);
         double B[3];
         field_at(P, bprog, n, B);
-        err = step_forward(P, N, cur, phi, br3, B, m, p, v, nxt);
+        err = step_forward(P, N, n, cur, phi, br3, B, m, p, v, nxt);
         if (err) goto done;
         orc_particle* tmp = cur; cur = nxt; nxt = tmp;
         if (P->loss_kind == ORC_LOSS_TRAJ_VEL) {
@@ -960,7 +1099,7 @@ int orc_backward(const orc_params* P, int N, const double* x0, const double* phi
         for (int n = s0; n < s1 - 1; ++n) {
             double B[3];
             field_at(P, bprog, n, B);
-            err = step_forward(P, N, seg + (size_t)(n - s0) * N, phi, br3, B, m, p, v,
+            err = step_forward(P, N, n, seg + (size_t)(n - s0) * N, phi, br3, B, m, p, v,
                                seg + (size_t)(n - s0 + 1) * N);
             if (err) goto done;
         }
