@@ -56,6 +56,31 @@ typedef enum {
 } mpm_mag_loss_kind;
 
 /*
+ * A solid boundary of Eq. 18 beyond the floor: an analytic shape translating
+ * with the constant velocity vel (v_b), at position a + vel t_n during step n
+ * (t_n = n dt). A grid node lies on the boundary when the shape's signed
+ * distance at the node is <= 0; the outward normal is the distance's gradient.
+ * Such a node whose velocity relative to v_b points into the shape applies
+ * Eq. 18 relative to v_b (mu = INFINITY: v = v_b); an attached obstacle sets
+ * v = v_b whatever the velocity. Obstacles act after the floor, in order,
+ * before the walls and the clamp.
+ */
+#define MPM_MAG_MAX_OBSTACLES 4
+typedef enum {
+    MPM_MAG_OBSTACLE_HALFSPACE = 1,  /* a: a point of the plane; b: outward normal (any length > 0) */
+    MPM_MAG_OBSTACLE_SPHERE = 2,     /* a: centre at t = 0; b[0]: radius > 0                        */
+    MPM_MAG_OBSTACLE_BOX = 3         /* axis-aligned; a: centre at t = 0; b: half extents > 0       */
+} mpm_mag_obstacle_kind;
+
+typedef struct {
+    int kind;                /* mpm_mag_obstacle_kind                                          */
+    int attached;            /* 1: nodes inside take v_b whatever their velocity              */
+    double a[3], b[3];       /* shape parameters (components beyond dim ignored)              */
+    double mu;               /* Coulomb friction of Eq. 18, >= 0; INFINITY: no-slip            */
+    double vel[3];           /* v_b                                                           */
+} mpm_mag_obstacle;
+
+/*
  * One design instance. The domain is the unit square/cube with n_grid nodes per
  * axis (dx = 1 / n_grid, node i at i dx). Units are the caller's (the
  * workloads use nondimensional E = 1, mu0 = 1).
@@ -84,6 +109,8 @@ typedef struct {
     int loss_kind;           /* mpm_mag_loss_kind                                              */
     double loss_dir[3];      /* e of the displacement / velocity losses                        */
     int ckpt_every;          /* checkpoint spacing K of the recorded rollout (0: auto ~ sqrt(T)) */
+    int n_obstacles;         /* 0..MPM_MAG_MAX_OBSTACLES                                      */
+    mpm_mag_obstacle obstacles[MPM_MAG_MAX_OBSTACLES];
 } mpm_mag_instance_desc;
 
 /*

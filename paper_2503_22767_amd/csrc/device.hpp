@@ -23,6 +23,8 @@ enum LossKind { kFinalMse = 0, kComDisp = 1, kTrajVel = 2, kTipDisp = 3 };
 // per-instance loss accumulators (double)
 enum Acc { kAccMass = 0, kAccS0, kAccS1, kAccSq, kAccCnt, kAccTip, kAccTraj, kAccCount = 8 };
 
+constexpr int kMaxObst = 4;   // obstacles per instance
+
 template <typename real>
 struct InstDev {
     int n_grid, grid_off, n_nodes, n_steps;
@@ -37,6 +39,14 @@ struct InstDev {
     real gdt[3];                         // g dt
     real floor_mu;
     real loss_dir[3];
+    // obstacles: solid boundaries of Eq. 18 beyond the floor, at a + vel t
+    int n_obst;
+    int obst_kind[kMaxObst];             // 1 half-space, 2 sphere, 3 axis-aligned box
+    int obst_mode[kMaxObst];             // 0 sliding (Coulomb), 1 no-slip, 2 attached
+    real obst_a[kMaxObst][3];            // point of the plane / centre at t = 0
+    real obst_b[kMaxObst][3];            // unit outward normal / radius in [0] / half extents
+    real obst_vel[kMaxObst][3];          // v_b
+    real obst_mu[kMaxObst];
 };
 
 struct ChunkDev {

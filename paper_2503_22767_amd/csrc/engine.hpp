@@ -153,6 +153,34 @@ public:
                 I.loss_dir[c] = (real)d.loss_dir[c];
             }
             I.floor_mu = I.floor_noslip ? (real)0 : (real)d.floor_mu;
+            if (d.n_obstacles < 0 || d.n_obstacles > kMaxObst) return fail(MPM_MAG_EINVAL, "n_obstacles must be in [0, 4]");
+            I.n_obst = d.n_obstacles;
+            for (int j = 0; j < d.n_obstacles; ++j) {
+                const mpm_mag_obstacle& o = d.obstacles[j];
+                if (o.kind < MPM_MAG_OBSTACLE_HALFSPACE || o.kind > MPM_MAG_OBSTACLE_BOX)
+                    return fail(MPM_MAG_EINVAL, "unknown obstacle kind");
+                if (!(o.mu >= 0)) return fail(MPM_MAG_EINVAL, "obstacle friction must be >= 0");
+                double len = 0;
+                for (int k = 0; k < D; ++k) len += o.b[k] * o.b[k];
+                len = std::sqrt(len);
+                bool ok = std::isfinite(len);
+                if (o.kind == MPM_MAG_OBSTACLE_HALFSPACE) ok = ok && len > 0;
+                if (o.kind == MPM_MAG_OBSTACLE_SPHERE) ok = ok && o.b[0] > 0;
+                if (o.kind == MPM_MAG_OBSTACLE_BOX)
+                    for (int k = 0; k < D; ++k) ok = ok && o.b[k] > 0;
+                for (int k = 0; k < D; ++k) ok = ok && std::isfinite(o.a[k]) && std::isfinite(o.vel[k]);
+                if (!ok) return fail(MPM_MAG_EINVAL, "bad obstacle shape");
+                I.obst_kind[j] = o.kind;
+                I.obst_mode[j] = o.attached ? 2 : (std::isinf(o.mu) ? 1 : 0);
+                I.obst_mu[j] = std::isinf(o.mu) ? (real)0 : (real)o.mu;
+                for (int k = 0; k < 3; ++k) {
+                    // the half-space's normal is stored unit length (divided in double)
+                    const double bk = (o.kind == MPM_MAG_OBSTACLE_HALFSPACE) ? (k < D ? o.b[k] / len : 0.0) : o.b[k];
+                    I.obst_a[j][k] = (real)o.a[k];
+                    I.obst_b[j][k] = (real)bk;
+                    I.obst_vel[j][k] = (real)o.vel[k];
+                }
+            }
             inst_h_.push_back(I);
             {
                 // grid-store sizing before the first recorded rollout: coarse
@@ -624,7 +652,7 @@ private:
         const int nc = chains_[q].nc;
         const int s0 = c * K_, s1 = std::min(T_, s0 + K_), j = n - s0;
         int r = launch(K_GRID_ADJ, cs, grid_blocks_of(q), kGridBlock, k_grid_adj<real, D>, a, (const real*)gm_slot(j),
-                       gpm_, lst(n));
+                       gpm_, lst(n), n);
         if (r) return r;
         if (n > s0 && fuse_adj_)
             return launch(K_ADJ_FUSED, cs, nc, kBlock, k_adj_fused<real, D>, a, (const real*)gpm_,

@@ -1123,13 +1123,139 @@ __device__ __forceinline__ void node_ijk(const InstDev<real>& I, int local, int 
     }
 }
 
-// Velocity of one node with mass m > 0 and momentum p. Returns the floor branch
-// (0 untouched, 1 zeroed, 2 sliding) and the intermediates the transpose needs:
-// vh = p/m, u0 after damping and gravity, u1 after the floor, v final.
+// Signed distance of obstacle j at node position xi at time t (the shape sits
+// at a + vel t) and its outward normal; <= 0 on and inside the solid. The box's
+// distance is exact inside, a lower bound outside.
+template <typename real, int D>
+__device__ __forceinline__ real obstacle_sdf(const InstDev<real>& I, int j, const real xi[D], real t, real nrm[D])
+{
+    real y[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        y[k] = xi[k] - (I.obst_a[j][k] + I.obst_vel[j][k] * t);
+        nrm[k] = real(0);
+    }
+    const int kind = I.obst_kind[j];
+    if (kind == 1) {
+        real d = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            nrm[k] = I.obst_b[j][k];
+            d += y[k] * nrm[k];
+        }
+        return d;
+    }
+    if (kind == 2) {
+        real r2 = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) r2 += y[k] * y[k];
+        const real r = sqrt(r2);
+        if (r > real(0)) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) nrm[k] = y[k] / r;
+        } else {
+            nrm[1] = real(1);
+        }
+        return r - I.obst_b[j][0];
+    }
+    real best = -INFINITY;
+    int kb = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const real q = fabs(y[k]) - I.obst_b[j][k];
+        if (q > best) {
+            best = q;
+            kb = k;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+        if (k == kb) nrm[k] = y[k] < real(0) ? real(-1) : real(1);
+    return best;
+}
+
+// Eq. 18 against obstacle j (normal nrm) on node velocity u: 0 untouched,
+// 1 set to v_b (no-slip, attached, no tangential motion or friction exceeding
+// it), 2 sliding
+template <typename real, int D>
+__device__ __forceinline__ int obstacle_contact(const InstDev<real>& I, int j, const real nrm[D], real u[D])
+{
+    const int mode = I.obst_mode[j];
+    if (mode == 2) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) u[k] = I.obst_vel[j][k];
+        return 1;
+    }
+    real r[D], vn = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        r[k] = u[k] - I.obst_vel[j][k];
+        vn += r[k] * nrm[k];
+    }
+    if (!(vn < real(0))) return 0;
+    real tv[D], t2 = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        tv[k] = r[k] - vn * nrm[k];
+        t2 += tv[k] * tv[k];
+    }
+    const real t = sqrt(t2);
+    const real sl = t + I.obst_mu[j] * vn;
+    if (mode == 1 || t == real(0) || sl <= real(0)) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) u[k] = I.obst_vel[j][k];
+        return 1;
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) u[k] = I.obst_vel[j][k] + sl / t * tv[k];
+    return 2;
+}
+
+// What the grid transpose needs of each obstacle: its input velocity, normal
+// and branch.
+template <typename real, int D>
+struct ObstTrace {
+    real in[kMaxObst][D], nrm[kMaxObst][D];
+    int br[kMaxObst];
+};
+
+// Transpose of the sliding map u -> v_b + (1 + mu vn / t) P (u - v_b) at input u:
+// g <- (1 + mu vn / t) P g + mu (n / t - vn tv / t^3) (tv . g)
+template <typename real, int D>
+__device__ __forceinline__ void obstacle_slide_adj(const InstDev<real>& I, int j, const real nrm[D], const real u[D],
+                                                   real g[D])
+{
+    real r[D], vn = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        r[k] = u[k] - I.obst_vel[j][k];
+        vn += r[k] * nrm[k];
+    }
+    real tv[D], t2 = 0, ng = 0, tg = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        tv[k] = r[k] - vn * nrm[k];
+        t2 += tv[k] * tv[k];
+        ng += nrm[k] * g[k];
+        tg += tv[k] * g[k];
+    }
+    const real t = sqrt(t2), mu = I.obst_mu[j];
+    real o[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+        o[k] = (real(1) + mu * vn / t) * (g[k] - ng * nrm[k]) + mu * (nrm[k] / t - vn * tv[k] / (t2 * t)) * tg;
+#pragma unroll
+    for (int k = 0; k < D; ++k) g[k] = o[k];
+}
+
+// Velocity of one node with mass m > 0 and momentum p at time t. Returns the
+// floor branch (0 untouched, 1 zeroed, 2 sliding) and the intermediates the
+// transpose needs: vh = p/m, u0 after damping and gravity, u1 after the floor,
+// v final; tr (if given) records the obstacles.
 template <typename real, int D>
 __device__ __forceinline__ int node_velocity(const InstDev<real>& I, const int ijk[D], real m, const real p[D],
                                              real vh[D], real u0[D], real u1[D], real v[D], int wallz[D],
-                                             bool& clamped)
+                                             bool& clamped, real t, ObstTrace<real, D>* tr)
 {
     const real rm = real(1) / m;
 #pragma unroll
@@ -1161,8 +1287,27 @@ __device__ __forceinline__ int node_velocity(const InstDev<real>& I, const int i
         }
     }
 #pragma unroll
+    for (int k = 0; k < D; ++k) v[k] = u1[k];
+    if (I.n_obst > 0) {
+        real xi[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) xi[k] = (real)ijk[k] * I.dx;
+        for (int j = 0; j < I.n_obst; ++j) {
+            real nrm[D];
+            int ob = 0;
+            if (tr)
+#pragma unroll
+                for (int k = 0; k < D; ++k) tr->in[j][k] = v[k];
+            if (obstacle_sdf<real, D>(I, j, xi, t, nrm) <= real(0)) ob = obstacle_contact<real, D>(I, j, nrm, v);
+            if (tr) {
+                tr->br[j] = ob;
+#pragma unroll
+                for (int k = 0; k < D; ++k) tr->nrm[j][k] = nrm[k];
+            }
+        }
+    }
+#pragma unroll
     for (int k = 0; k < D; ++k) {
-        v[k] = u1[k];
         wallz[k] = 0;
         if (ijk[k] < I.wall_cells && v[k] < real(0)) wallz[k] = 1;
         if (ijk[k] >= I.n_grid - I.wall_cells && v[k] > real(0)) wallz[k] = 1;
@@ -1209,7 +1354,8 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Args<real> a, real* gv_out,
             real vh[D], u0[D], u1[D];
             int wz[D];
             bool cl;
-            node_velocity<real, D>(I, ijk, node[3], node, vh, u0, u1, v, wz, cl);
+            node_velocity<real, D>(I, ijk, node[3], node, vh, u0, u1, v, wz, cl, (real)gs.step * I.dt,
+                                   (ObstTrace<real, D>*)nullptr);
         } else {
 #pragma unroll
             for (int k = 0; k < D; ++k) v[k] = real(0);
@@ -1830,7 +1976,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p_adj(Args<real> a, const real* __
 
 template <typename real, int D>
 __global__ __launch_bounds__(kGridBlock) void k_grid_adj(Args<real> a, const real* __restrict__ gmd_in,
-                                                         real* __restrict__ gpm_out, int list)
+                                                         real* __restrict__ gpm_out, int list, int step)
 {
   const int n_act = a.active[list];
   for (int ai = blockIdx.x; ai < n_act; ai += gridDim.x) {
@@ -1848,12 +1994,22 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_adj(Args<real> a, const rea
             real vh[D], u0[D], u1[D], v[D], gb[D];
             int wz[D];
             bool cl;
-            int br = node_velocity<real, D>(I, ijk, node[3], node, vh, u0, u1, v, wz, cl);
+            ObstTrace<real, D> tr;
+            int br = node_velocity<real, D>(I, ijk, node[3], node, vh, u0, u1, v, wz, cl, (real)step * I.dt,
+                                            I.n_obst > 0 ? &tr : (ObstTrace<real, D>*)nullptr);
 #pragma unroll
             for (int k = 0; k < D; ++k) gb[k] = cl ? real(0) : vb[k];
 #pragma unroll
             for (int k = 0; k < D; ++k)
                 if (wz[k]) gb[k] = real(0);
+            for (int j = I.n_obst - 1; j >= 0; --j) {
+                if (tr.br[j] == 1) {
+#pragma unroll
+                    for (int k = 0; k < D; ++k) gb[k] = real(0);
+                } else if (tr.br[j] == 2) {
+                    obstacle_slide_adj<real, D>(I, j, tr.nrm[j], tr.in[j], gb);
+                }
+            }
             if (br == 1) {
 #pragma unroll
                 for (int k = 0; k < D; ++k) gb[k] = real(0);

@@ -29,6 +29,16 @@ LIB_PATH = os.environ.get("MPM_MAG_LIB") or os.path.join(HERE, "libmpm_mag.so")
 OK, EINVAL, ENOMEM, EHIP, EDOMAIN, EINVERT, ENONFINITE, ESTATE = range(8)
 
 
+MAX_OBSTACLES = 4
+OBSTACLE_HALFSPACE, OBSTACLE_SPHERE, OBSTACLE_BOX = 1, 2, 3
+
+
+class ObstacleDesc(C.Structure):
+    """Mirror of mpm_mag_obstacle."""
+    _fields_ = [("kind", C.c_int), ("attached", C.c_int), ("a", C.c_double * 3), ("b", C.c_double * 3),
+                ("mu", C.c_double), ("vel", C.c_double * 3)]
+
+
 class InstanceDesc(C.Structure):
     """Mirror of mpm_mag_instance_desc."""
     _fields_ = [
@@ -39,14 +49,27 @@ class InstanceDesc(C.Structure):
         ("floor_on", C.c_int), ("floor_y", C.c_double), ("floor_mu", C.c_double),
         ("particle_volume", C.c_double), ("n_segments", C.c_int), ("seg_steps", C.c_int),
         ("periodic", C.c_int), ("loss_kind", C.c_int), ("loss_dir", C.c_double * 3),
-        ("ckpt_every", C.c_int),
+        ("ckpt_every", C.c_int), ("n_obstacles", C.c_int), ("obstacles", ObstacleDesc * MAX_OBSTACLES),
     ]
 
 
+def _vec3(v):
+    return (C.c_double * 3)(*([float(x) for x in list(v)] + [0.0] * 3)[:3])
+
+
 def desc_from_params(p: dict) -> InstanceDesc:
+    """p["obstacles"] (optional): a list of dicts with kind, a, b, mu (default 0),
+    vel (default 0) and attached (default 0)."""
     d = InstanceDesc()
+    obst = list(p.get("obstacles", []))
+    if len(obst) > MAX_OBSTACLES:
+        raise ValueError(f"at most {MAX_OBSTACLES} obstacles")
+    d.n_obstacles = len(obst)
+    for j, o in enumerate(obst):
+        d.obstacles[j] = ObstacleDesc(int(o["kind"]), int(o.get("attached", 0)), _vec3(o["a"]), _vec3(o["b"]),
+                                      float(o.get("mu", 0.0)), _vec3(o.get("vel", [0.0, 0.0, 0.0])))
     for name, _ in InstanceDesc._fields_:
-        if name not in p:
+        if name not in p or name in ("n_obstacles", "obstacles"):
             continue
         val = p[name]
         if name in ("gravity", "loss_dir"):
