@@ -84,12 +84,12 @@ ALU_PEAK_PACKED_TFLOPS = {4: 157.3, 8: 78.6}
 # device-to-device copy of 1 GiB (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0). Valid
 # only for the kernel sources they were taken on (hash of csrc/).
 TRAFFIC = {
-    # (530261.2 KiB fetched x 2.0 + 257401.5 KiB written) x 1024, mean of 5 launches
-    "p2g_g2p_adj": 1349554112,
-    # (142456.4 x 2.0 + 221027.1) x 1024, mean of 21 launches (plain and recorded steps)
-    "g2p_p2g": 518082450,
+    # (530052.2 KiB fetched x 2.0 + 257436.5 KiB written) x 1024, mean of 5 launches
+    "p2g_g2p_adj": 1349161958,
+    # (142494.3 x 2.0 + 221017.0) x 1024, mean of 21 launches (plain and recorded steps)
+    "g2p_p2g": 518149798,
 }
-TRAFFIC_SRC_HASH = "43ee8857a986a845"
+TRAFFIC_SRC_HASH = "8833088ce70095e0"
 
 
 def csrc_hash():
@@ -280,6 +280,42 @@ def front_end(wl, reps=20):
     return out
 
 
+def obstacles(wl):
+    """A plain forward of the workload, one stream, kernel timing on, with two
+    obstacles added to every instance (a sphere whose top is one cell below
+    the front of the body and a tilted half-space moving towards it) and
+    without: the grid update's time per launch, and the forward's."""
+    import dataclasses
+    out = {}
+    for label in ("without", "with"):
+        insts = []
+        for i in wl.instances:
+            p = dict(i.params)
+            if label == "with":
+                lo, hi = i.x0.min(0), i.x0.max(0)
+                d = p["dim"]
+                z = lambda v: list(v) + [0.0] * (3 - len(v))
+                mid = (lo + hi) / 2
+                p["obstacles"] = [
+                    dict(kind=M.OBSTACLE_SPHERE, a=z([hi[0] - 0.05, lo[1] - 0.1 - 1.0 / p["n_grid"]] + list(mid[2:d])),
+                         b=[0.1, 0, 0], mu=0.5),
+                    dict(kind=M.OBSTACLE_HALFSPACE, a=z([hi[0] + 0.1, 0.0] + [0.0] * (d - 2)),
+                         b=z([-1.0, 0.3] + [0.0] * (d - 2)), mu=0.3, vel=z([-0.2] + [0.0] * (d - 1)))]
+            insts.append(dataclasses.replace(i, params=p))
+        w2 = dataclasses.replace(wl, instances=insts)
+        sim, tens, dtype = make_sim(w2, {"streams": 1, "kernel_timing": 1})
+        try:
+            dloss = torch.ones(len(insts), dtype=dtype, device="cuda")
+            sim.kernel_stats(reset=True)
+            t = timed(lambda: run_step(sim, tens, dloss, record=False, backward=False), 1)
+            st = sim.kernel_stats()["grid_update"]
+        finally:
+            sim.close()
+        out[label] = dict(grid_update_us=round(st["ms"] / st["launches"] * 1e3, 2), fwd_ms=round(t * 1e3, 1))
+    out["obstacles_per_instance"] = 2
+    return out
+
+
 def codesign(wl, iters=2):
     """Co-design iterations (Sec. 3.2) over the workload's tasks sharing one
     design: every task driven by its own harmonic stimulus (one program row per
@@ -335,6 +371,7 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized device buffer (reference kernel for HBM byte counters)")
     ap.add_argument("--no-front-end", action="store_true", help="skip the design front-end leg")
+    ap.add_argument("--no-obstacles", action="store_true", help="skip the obstacle leg")
     ap.add_argument("--codesign", type=int, default=2, metavar="K",
                     help="timed co-design iterations after one warm-up (0 skips the leg)")
     ap.add_argument("--front-end-only", action="store_true", help="run only the design front-end leg")
@@ -417,6 +454,9 @@ def main():
     if not args.no_front_end:
         rec["front_end"] = front_end(wl)
         log(f"[bench] front end {rec['front_end']}")
+    if not args.no_obstacles:
+        rec["obstacles"] = obstacles(wl)
+        log(f"[bench] obstacles {rec['obstacles']}")
     if args.codesign > 0:
         cd = codesign(wl, args.codesign)
         if cd is not None:
