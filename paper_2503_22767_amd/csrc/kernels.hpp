@@ -819,6 +819,26 @@ __device__ __forceinline__ void store_particle(real* st, int64_t S, int64_t i, c
         }
 }
 
+// the same with non-temporal stores, for states written long before they are
+// read (the segment stash: a quadruped step's state is 330 MB)
+template <typename real, int D>
+__device__ __forceinline__ void stream_particle(real* st, int64_t S, int64_t i, const Particle<real, D>& q)
+{
+    using Cp = Comp<D>;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        __builtin_nontemporal_store(q.x[k], &st[(Cp::X + k) * S + i]);
+        __builtin_nontemporal_store(q.v[k], &st[(Cp::V + k) * S + i]);
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            __builtin_nontemporal_store(q.C[a][b], &st[(Cp::C + a * D + b) * S + i]);
+            __builtin_nontemporal_store(q.F[a][b], &st[(Cp::F + a * D + b) * S + i]);
+        }
+}
+
 // --------------------------------------------------------------------------
 // per-particle stress and affine momentum matrix (Eqs. 7, 15, 31-33)
 // --------------------------------------------------------------------------
@@ -1539,11 +1559,14 @@ __device__ __forceinline__ void traj_accumulate(const Args<real>& a, const InstD
     if (threadIdx.x == 0) unsafeAtomicAdd(&a.acc[inst * kAccCount + kAccTraj], v1[0]);
 }
 
-// G2P of one step (no scatter follows). slot_order: lanes take their own slots
-// rather than the lane order, which serves only the scatter of the forward
-// kernels (the recompute of a stored segment).
+// G2P of one step (no scatter follows): the recompute of a stored segment,
+// and the forward's last step. slot_order: lanes take their own slots rather
+// than the lane order, which serves only the scatter of the forward kernels.
+// The new state is streamed out with non-temporal stores (a stashed state is
+// read back only after the rest of its segment), and the kernel is bound to
+// 6 waves per SIMD: it waits on memory more than it computes.
 template <typename real, int D>
-__global__ __launch_bounds__(kBlock) void k_g2p(Args<real> a, const real* __restrict__ gv_in, const real* sin,
+__global__ __launch_bounds__(kBlock, 6) void k_g2p(Args<real> a, const real* __restrict__ gv_in, const real* sin,
                                                 real* sout, int step, int traj_on, int list_done, int slot_order)
 {
     const ChunkDev ch = a.chunks[a.chunk_base + blockIdx.x];
@@ -1586,7 +1609,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(Args<real> a, const real* __rest
                                           4 * n * n, F, u, org, q, x1);
         }
         if (err) atomicOr(a.err, err);
-        store_particle<real, D>(sout, a.nalloc, i, q);
+        stream_particle<real, D>(sout, a.nalloc, i, q);
     }
     if (traj_on && I.loss_kind == kTrajVel) traj_accumulate<real, D>(a, I, ch.inst, active, i, q);
 }
