@@ -84,12 +84,12 @@ ALU_PEAK_PACKED_TFLOPS = {4: 157.3, 8: 78.6}
 # device-to-device copy of 1 GiB (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0). Valid
 # only for the kernel sources they were taken on (hash of csrc/).
 TRAFFIC = {
-    # (530052.2 KiB fetched x 2.0 + 257436.5 KiB written) x 1024, mean of 5 launches
-    "p2g_g2p_adj": 1349161958,
-    # (142494.3 x 2.0 + 221017.0) x 1024, mean of 21 launches (plain and recorded steps)
-    "g2p_p2g": 518149798,
+    # (530171.2 KiB fetched x 2.0 + 257459.5 KiB written) x 1024, mean of 5 launches
+    "p2g_g2p_adj": 1349429056,
+    # (142458.8 x 2.0 + 221016.6) x 1024, mean of 21 launches (plain and recorded steps)
+    "g2p_p2g": 518076532,
 }
-TRAFFIC_SRC_HASH = "8833088ce70095e0"
+TRAFFIC_SRC_HASH = "cdc8ded1c45972cf"
 
 
 def csrc_hash():
