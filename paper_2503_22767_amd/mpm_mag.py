@@ -18,6 +18,7 @@ from __future__ import annotations
 import ctypes as C
 import math
 import os
+import sys
 from typing import Optional, Sequence
 
 import torch
@@ -165,6 +166,11 @@ class MpmMag:
         if st != OK:
             raise MpmMagError(st, "mpm_mag_create", lib().mpm_mag_last_error(None).decode())
         self._h = h
+        # MPM_MAG_KERNEL_TIMING=1: time every launch with events and print the
+        # per-kernel table to stderr when the handle is closed
+        self._print_timing = os.environ.get("MPM_MAG_KERNEL_TIMING", "0") not in ("", "0")
+        if self._print_timing:
+            self.set_option("kernel_timing", 1)
 
     # -- helpers --------------------------------------------------------------
     def _check(self, st: int, where: str):
@@ -229,8 +235,23 @@ class MpmMag:
     def device_bytes(self) -> int:
         return int(lib().mpm_mag_device_bytes(self._h))
 
+    def print_kernel_stats(self, file=None):
+        """Per-kernel launches, time and rates since the last reset."""
+        file = file or sys.stderr
+        print(f"{'kernel':14s} {'launches':>9s} {'total ms':>10s} {'avg us':>9s} {'GB/s':>8s} {'TFLOP/s':>8s}", file=file)
+        for k, v in self.kernel_stats().items():
+            if not v["launches"]:
+                continue
+            avg = v["ms"] / v["launches"] * 1e3
+            gbs = v["bytes"] / v["launches"] / (avg * 1e3) if avg > 0 and v["bytes"] else 0.0
+            tfl = v["flops"] / v["launches"] / (avg * 1e6) if avg > 0 and v["flops"] else 0.0
+            print(f"{k:14s} {v['launches']:9d} {v['ms']:10.3f} {avg:9.2f} {gbs:8.1f} {tfl:8.2f}", file=file)
+
     def close(self):
         if getattr(self, "_h", None):
+            if getattr(self, "_print_timing", False):
+                torch.cuda.synchronize(self.device)
+                self.print_kernel_stats()
             lib().mpm_mag_destroy(self._h)
             self._h = None
 

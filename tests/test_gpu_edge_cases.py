@@ -137,3 +137,24 @@ def test_chunk_spanning_distant_blobs_matches_oracle(dim):
     compare(got, ref, pos_tol=1e-10, grad_tol=1e-9, loss_tol=1e-9, label=f"two blobs d{dim} fp64")
     got = gpu_run([inst], precision=4)
     compare(got, ref, pos_tol=1e-4, grad_tol=1e-3, label=f"two blobs d{dim} fp32")
+
+
+def test_kernel_timing_env_var_prints_the_table(monkeypatch, capfd):
+    """MPM_MAG_KERNEL_TIMING=1 times every launch and prints the per-kernel
+    table when the handle closes."""
+    import torch
+    from paper_2503_22767_amd import mpm_mag as M
+    monkeypatch.setenv("MPM_MAG_KERNEL_TIMING", "1")
+    inst = W.make_tiny(seed=3, dim=2, n_steps=6, loss_kind=W.LOSS_COM_DISP, floor=True, gravity=1.0,
+                       size=(0.4, 0.2, 0.2), n_grid=16)
+    sim = M.MpmMag([inst.params], [inst.n], precision=8)
+    x0, density, br, b_prog, target, mask = M.instance_tensors([inst], dtype=torch.float64)
+    sim.rollout(x0, density, br, b_prog, target, mask, record=True)
+    sim.backward(torch.ones(1, dtype=torch.float64, device="cuda"))
+    sim.close()
+    err = capfd.readouterr().err
+    rows = {line.split()[0]: line.split() for line in err.splitlines() if line.strip()}
+    assert "kernel" in rows and "grid_update" in rows and "p2g_g2p_adj" in rows
+    # 6 forward steps; the reverse sweep restores the stored grids instead
+    assert int(rows["grid_update"][1]) == 6 and float(rows["grid_update"][3]) > 0.0
+    assert int(rows["grid_restore"][1]) == 6
