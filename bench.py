@@ -84,12 +84,12 @@ ALU_PEAK_PACKED_TFLOPS = {4: 157.3, 8: 78.6}
 # device-to-device copy of 1 GiB (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0). Valid
 # only for the kernel sources they were taken on (hash of csrc/).
 TRAFFIC = {
-    # (530171.2 KiB fetched x 2.0 + 257459.5 KiB written) x 1024, mean of 5 launches
-    "p2g_g2p_adj": 1349429056,
-    # (142458.8 x 2.0 + 221016.6) x 1024, mean of 21 launches (plain and recorded steps)
-    "g2p_p2g": 518076532,
+    # (530191.8 KiB fetched x 2.0 + 257392.7 KiB written) x 1024, mean of 5 launches
+    "p2g_g2p_adj": 1349402970,
+    # (142463.8 x 2.0 + 221024.0) x 1024, mean of 21 launches (plain and recorded steps)
+    "g2p_p2g": 518094421,
 }
-TRAFFIC_SRC_HASH = "cdc8ded1c45972cf"
+TRAFFIC_SRC_HASH = "8b6ea7d6fe571759"
 
 
 def csrc_hash():

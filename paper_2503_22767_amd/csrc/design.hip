@@ -355,10 +355,13 @@ __global__ __launch_bounds__(kBlock) void k_region_chunks(const uint32_t* member
     double v[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) v[k] = 0.0;
-    for (int64_t j = lo + t; j < hi; j += kBlock) {
-        const int64_t p = members[j];
+    for (int c = 0; c < copies; ++c) {   // copies outermost: the inner loop stays a plain gather
+        const real* gc = g_br + (int64_t)c * n * D;
+        for (int64_t j = lo + t; j < hi; j += kBlock) {
+            const int64_t p = members[j];
 #pragma unroll
-        for (int k = 0; k < D; ++k) v[k] += copies_sum<real, D>(g_br, n, copies, p, k);
+            for (int k = 0; k < D; ++k) v[k] += (double)gc[p * D + k];
+        }
     }
 #pragma unroll
     for (int k = 0; k < D; ++k)
