@@ -84,12 +84,12 @@ ALU_PEAK_PACKED_TFLOPS = {4: 157.3, 8: 78.6}
 # device-to-device copy of 1 GiB (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0). Valid
 # only for the kernel sources they were taken on (hash of csrc/).
 TRAFFIC = {
-    # (530191.8 KiB fetched x 2.0 + 257392.7 KiB written) x 1024, mean of 5 launches
-    "p2g_g2p_adj": 1349402970,
-    # (142463.8 x 2.0 + 221024.0) x 1024, mean of 21 launches (plain and recorded steps)
-    "g2p_p2g": 518094421,
+    # (530125.3 KiB fetched x 2.0 + 257404.1 KiB written) x 1024, mean of 5 launches
+    "p2g_g2p_adj": 1349278477,
+    # (142459.7 x 2.0 + 221014.2) x 1024, mean of 21 launches (plain and recorded steps)
+    "g2p_p2g": 518075970,
 }
-TRAFFIC_SRC_HASH = "8b6ea7d6fe571759"
+TRAFFIC_SRC_HASH = "e131a676d3fb40af"
 
 
 def csrc_hash():

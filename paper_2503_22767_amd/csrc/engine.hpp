@@ -293,6 +293,13 @@ public:
             ++plan_gen_;   // baked into captured launches
             return MPM_MAG_OK;
         }
+        if (k == "grid_threads") {
+            if (value != 0 && (value < Coarse<D>::cap || value > kGridBlock || value % 64))
+                return fail(MPM_MAG_EINVAL, "grid_threads must be 0 or a multiple of 64 in [256, 512]");
+            grid_threads_ = (int)value;
+            ++plan_gen_;   // baked into captured launches
+            return MPM_MAG_OK;
+        }
         if (k == "grid_store") {
             if (value < -1 || value > ((int64_t)1 << 30)) return fail(MPM_MAG_EINVAL, "grid_store must be -1, 0 or MiB");
             gs_budget_mib_ = value;   // applied at the next recorded rollout
@@ -526,6 +533,13 @@ private:
         return a;
     }
 
+    // Threads per workgroup of the grid update and its transpose. On one
+    // stream the larger workgroup gathers a coarse block's boxes in fewer
+    // rounds; when instance groups overlap on several streams, one-wave-per-SIMD
+    // workgroups fit beside the particle kernels' blocks sooner (measured: 3%
+    // more steps per second on three streams, 25% slower grid kernels alone).
+    int grid_threads() const { return grid_threads_ > 0 ? grid_threads_ : (n_chains() > 1 ? 256 : kGridBlock); }
+
     int grid_blocks_of(int q) const { return (int)std::min<int64_t>(chains_[q].ncb, grid_wgs_); }
 
     // copy of the chain's particle state (all components) from src to dst
@@ -558,7 +572,7 @@ private:
             r = launch(K_P2G, cs, nc, kBlock, k_p2g<real, D>, a, (const real*)st_, n, lf(n));
             if (r) return r;
         }
-        r = launch(K_GRID, cs, grid_blocks_of(q), kGridBlock, k_grid<real, D>, a, gv_, (real*)nullptr, lf(n),
+        r = launch(K_GRID, cs, grid_blocks_of(q), grid_threads(), k_grid<real, D>, a, gv_, (real*)nullptr, lf(n),
                    store_of(q, n, record));
         if (r) return r;
         if (n + 1 < T_ && fuse_fwd_) {
@@ -599,7 +613,7 @@ private:
             r = launch(K_P2G, cs, nc, kBlock, k_p2g<real, D>, a, (const real*)seg_state(c, j), n, lf(n));
             if (r) return r;
         }
-        r = launch(K_GRID, cs, grid_blocks_of(q), kGridBlock, k_grid<real, D>, a, gv_slot(j), gm_slot(j), lf(n),
+        r = launch(K_GRID, cs, grid_blocks_of(q), grid_threads(), k_grid<real, D>, a, gv_slot(j), gm_slot(j), lf(n),
                    store_of(q, n, false));
         if (r) return r;
         if (n + 1 >= s1) return MPM_MAG_OK;
@@ -651,7 +665,7 @@ private:
         Args<real> a = args_of(q);
         const int nc = chains_[q].nc;
         const int s0 = c * K_, s1 = std::min(T_, s0 + K_), j = n - s0;
-        int r = launch(K_GRID_ADJ, cs, grid_blocks_of(q), kGridBlock, k_grid_adj<real, D>, a, (const real*)gm_slot(j),
+        int r = launch(K_GRID_ADJ, cs, grid_blocks_of(q), grid_threads(), k_grid_adj<real, D>, a, (const real*)gm_slot(j),
                        gpm_, lst(n), n);
         if (r) return r;
         if (n > s0 && fuse_adj_)
@@ -1271,7 +1285,7 @@ private:
     bool recorded_ = false, has_target_ = false;
     // options
     bool graph_ = false, timing_ = false, use_lds_ = true;
-    int box_cap_ = kBoxCap, grid_wgs_ = 2048;
+    int box_cap_ = kBoxCap, grid_wgs_ = 2048, grid_threads_ = 0;
     bool fuse_adj_ = true, fuse_fwd_ = true, lane_sort_ = true;
     std::vector<hipEvent_t> events_;
     size_t ev_used_ = 0;

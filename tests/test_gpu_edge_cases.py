@@ -62,6 +62,18 @@ def _status_of(fn):
     return M.OK
 
 
+def test_grid_threads_option_is_validated():
+    inst = _block(3, 4, floor=False)
+    sim = M.MpmMag([inst.params], [len(inst.x0)], precision=4)
+    try:
+        for bad in (128, 300, 576, -1):
+            assert _status_of(lambda: sim.set_option("grid_threads", bad)) == M.EINVAL, bad
+        for good in (0, 256, 384, 512):
+            sim.set_option("grid_threads", good)
+    finally:
+        sim.close()
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_particle_outside_the_grid_reports_edomain(dim):
     inst = _block(dim, 4, floor=False)
