@@ -336,6 +336,7 @@ public:
         MPM_HIP(hipMemsetAsync(acc_, 0, sizeof(double) * kAccCount * n_inst_, s));
         MPM_HIP(hipMemsetAsync(gm_, 0, sizeof(real) * 4 * G_, s));
         MPM_HIP(hipMemsetAsync(reg_count_, 0, sizeof(int) * n_cb_, s));
+        MPM_HIP(hipMemsetAsync(fb_used_, 0, sizeof(int) * n_cb_, s));
         MPM_HIP(hipMemsetAsync(active_, 0, sizeof(int) * 4 * kMaxChains, s));
         MPM_HIP(hipMemcpyAsync(bprog_, b_prog, sizeof(real) * S_tot_ * D, hipMemcpyDeviceToDevice, s));
         int st = sort_and_gather(s, (const real*)x0, (const real*)density, (const real*)br, (const real*)target, mask);
@@ -729,6 +730,7 @@ private:
         a.box = box_;
         a.reg_count = reg_count_;
         a.reg_list = reg_list_;
+        a.fb_used = fb_used_;
         a.cb_inst = cb_inst_d_;
         a.active = active_;
         a.active_list = active_list_;
@@ -1142,6 +1144,7 @@ private:
         st |= dalloc(&box_, (size_t)n_chunks_ * kWaves * 2);
         st |= dalloc(&reg_count_, (size_t)n_cb_);
         st |= dalloc(&reg_list_, (size_t)n_cb_ * Coarse<D>::cap);
+        st |= dalloc(&fb_used_, (size_t)n_cb_);
         st |= dalloc(&cb_inst_d_, (size_t)n_cb_);
         st |= dalloc(&active_, 4 * kMaxChains);
         st |= dalloc(&active_list_, (size_t)4 * kMaxChains * n_cb_);
@@ -1169,6 +1172,7 @@ private:
                           hipMemcpyHostToDevice));
         MPM_HIP(hipMemcpy(cb_inst_d_, cb_inst_h_.data(), sizeof(int) * cb_inst_h_.size(), hipMemcpyHostToDevice));
         MPM_HIP(hipMemset(reg_count_, 0, sizeof(int) * n_cb_));
+        MPM_HIP(hipMemset(fb_used_, 0, sizeof(int) * n_cb_));
         MPM_HIP(hipMemset(active_, 0, sizeof(int) * 4 * kMaxChains));
         MPM_HIP(hipMemset(gm_, 0, sizeof(real) * 4 * G_));
         MPM_HIP(hipMemset(gv_, 0, sizeof(real) * 4 * G_));
@@ -1246,6 +1250,7 @@ private:
     int4* box_ = nullptr;
     int* reg_count_ = nullptr;
     int* reg_list_ = nullptr;
+    int* fb_used_ = nullptr;
     int* cb_inst_d_ = nullptr;
     int* active_ = nullptr;
     int* active_list_ = nullptr;

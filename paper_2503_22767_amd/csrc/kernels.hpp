@@ -86,6 +86,7 @@ struct Args {
     int4* box;           // [n_chunks][2]: lo (xyz), ext (xyz); ext = 0 when the box was not staged
     int* reg_count;      // [n_coarse] boxes registered with each coarse block this phase
     int* reg_list;       // [n_coarse][cap] chunk ids
+    int* fb_used;        // [n_coarse] nonzero when the dense fallback accumulator holds values of the block
     const int* cb_inst;  // [n_coarse] instance of each coarse block
     int* active;         // [4]: coarse blocks activated per scatter list (P2G: 0, 3; G2P transpose: 1, 2)
     int* active_list;    // [4][n_coarse]
@@ -184,6 +185,7 @@ __device__ __forceinline__ void register_box(const Args<real>& a, const InstDev<
         int cb = I.cb_off + (b0[0] + jj[0]) + I.nb * ((b0[1] + jj[1]) + (D == 3 ? I.nb * (b0[2] + jj[2]) : 0));
         int slot = atomicAdd(&a.reg_count[cb], 1);
         if (slot == 0) a.active_list[phase * a.n_coarse + atomicAdd(&a.active[phase], 1)] = cb;
+        if (!staged || slot >= CB::cap) a.fb_used[cb] = 1;   // values of this block go to fb
         if (slot < CB::cap) {
             a.reg_list[cb * CB::cap + slot] = id;
         } else if (staged) {
@@ -520,6 +522,7 @@ __device__ __forceinline__ void gather_coarse(const Args<real>& a, const InstDev
     __syncthreads();   // the previous coarse block of this workgroup is done with the shared arrays
     const int cnt_raw = a.reg_count[b];
     if (cnt_raw == 0) return;
+    const bool fb_any = a.fb_used[b] != 0;   // otherwise fb is zero over the block
     const int cnt = min(cnt_raw, CB::cap);
     const int lb = b - I.cb_off;
     const int bc[3] = {lb % I.nb, D == 3 ? (lb / I.nb) % I.nb : lb / I.nb, D == 3 ? lb / (I.nb * I.nb) : 0};
@@ -618,14 +621,20 @@ __device__ __forceinline__ void gather_coarse(const Args<real>& a, const InstDev
         const int64_t g = (int64_t)I.grid_off + local;
         real acc[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            acc[q] = fb[4 * g + q] + (real)s_acc[q][ln];
-            fb[4 * g + q] = real(0);
-        }
+        for (int q = 0; q < 4; ++q) acc[q] = (real)s_acc[q][ln];
+        if (fb_any)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                acc[q] += fb[4 * g + q];
+                fb[4 * g + q] = real(0);
+            }
         node_fn(g, g3, ln, acc);
     }
     __syncthreads();
-    if (t == 0) a.reg_count[b] = 0;
+    if (t == 0) {
+        a.reg_count[b] = 0;
+        if (fb_any) a.fb_used[b] = 0;
+    }
 }
 
 // Box of grid nodes covering the active particles' stencils, copied from a

@@ -170,3 +170,38 @@ def test_kernel_timing_env_var_prints_the_table(monkeypatch, capfd):
     # 6 forward steps; the reverse sweep restores the stored grids instead
     assert int(rows["grid_update"][1]) == 6 and float(rows["grid_update"][3]) > 0.0
     assert int(rows["grid_restore"][1]) == 6
+
+
+def _crowded_coarse_block(n_steps=4, seed=12):
+    """75,625 particles (25 per cell and axis) inside one 16 x 16 coarse block of
+    a 32-node 2D grid: 296 chunk boxes register with that block, more than its
+    list of 256 holds, so the last ones add their staged values to the dense
+    fallback accumulator, in the forward scatter and in the transposed one."""
+    rng = np.random.default_rng(seed)
+    n_grid = 32
+    dx = 1.0 / n_grid
+    h = dx / 25
+    x0 = W.box_particles([18.2 * dx, 18.2 * dx], [11 * dx, 11 * dx], h)
+    n = x0.shape[0]
+    p = W.default_params(2, n_grid, 1e-3, n_steps, h)
+    p["loss_kind"] = W.LOSS_FINAL_MSE
+    density = rng.uniform(0.3, 1.0, size=n)
+    br = W._unit_vectors(rng, n, 2)
+    b_prog = rng.uniform(-0.3, 0.3, size=(1, 2))
+    target = x0 + rng.uniform(-0.01, 0.01, size=x0.shape)
+    return W.Instance(p, x0, density, br, b_prog, target, None)
+
+
+def test_coarse_block_list_overflow_matches_oracle():
+    inst = _crowded_coarse_block()
+    base = np.floor(inst.x0 / (1.0 / 32) - 0.5).astype(int)
+    # every stencil (base .. base + 2) lies in coarse block (1, 1): nodes 16 .. 31
+    assert base.min() >= 16 and base.max() + 2 <= 31
+    n_chunks = (inst.n + 255) // 256
+    log("crowded coarse block", inst.n, "particles", n_chunks, "chunk boxes")
+    assert n_chunks > 256
+    ref = oracle_run([inst])
+    got = gpu_run([inst], precision=8)
+    compare(got, ref, pos_tol=1e-10, grad_tol=1e-9, loss_tol=1e-9, label="crowded block fp64")
+    got = gpu_run([inst], precision=4)
+    compare(got, ref, pos_tol=1e-4, grad_tol=1e-3, label="crowded block fp32")
