@@ -179,8 +179,8 @@ const char* mpm_mag_last_error(const mpm_mag* h);
  *                   larger boxes are staged per wave or fall back to global atomics
  *   "grid_wgs"      workgroups of the grid kernels, 16..2^20 (default 2048)
  *   "grid_threads"  threads per workgroup of the grid update and its transpose, a
- *                   multiple of 64 in 256..512; 0 (default): 256 when instance groups
- *                   run on several streams, 512 on one
+ *                   multiple of 64 in 256..1024; 0 (default): 256 when instance groups
+ *                   run on several streams, 1024 on one
  *   "streams"       instance groups advanced on separate streams, 0..8 (0: min(3, instances));
  *                   consecutive instances form a group; 1 runs everything on the call's stream
  *   "fuse_fwd"      1: G2P of step n and P2G of step n+1 in one kernel (default), 0: separate

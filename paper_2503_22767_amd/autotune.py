@@ -45,7 +45,7 @@ SPACE: Dict[str, List[int]] = dict(
     fuse_fwd=[1, 0],
     fuse_adj=[1, 0],
     streams=[0, 1, 2, 4],
-    grid_threads=[0, 256, 512],
+    grid_threads=[0, 256, 512, 1024],
 )
 CACHE_ENV = "MPM_MAG_TUNE_CACHE"
 

@@ -12,6 +12,7 @@ namespace mpm {
 constexpr int kBlock = 256;       // threads per particle block = particles per chunk
 constexpr int kWaves = kBlock / 64;
 constexpr int kGridBlock = 512;   // threads of the grid kernels (and grid padding unit)
+constexpr int kGridThreadsMax = 1024;   // largest workgroup of the grid update and its transpose
 
 // device error word bits
 constexpr int kErrDomain = 1;

@@ -554,7 +554,7 @@ __device__ __forceinline__ void gather_coarse(const Args<real>& a, const InstDev
     __syncthreads();
     // inclusive scan of s_off[1..cnt] (cnt <= blockDim.x): wave scans, then wave totals
     {
-        __shared__ int s_wsum[kGridBlock / 64];
+        __shared__ int s_wsum[kGridThreadsMax / 64];
         const int lane = t & 63, wv = t >> 6;
         int v = (t < cnt) ? s_off[t + 1] : 0;
 #pragma unroll
@@ -1357,7 +1357,7 @@ __device__ __forceinline__ int node_velocity(const InstDev<real>& I, const int i
 // The FP32 build is held to 64 VGPRs (8 waves per SIMD): the gather is a
 // chain of dependent loads, so more coarse blocks in flight pay off.
 template <typename real, int D>
-__global__ __launch_bounds__(kGridBlock) __attribute__((amdgpu_waves_per_eu(sizeof(real) == 4 ? 8 : 1))) void k_grid(Args<real> a, real* gv_out, real* gmd_out, int list,
+__global__ __launch_bounds__(kGridThreadsMax) __attribute__((amdgpu_waves_per_eu(sizeof(real) == 4 ? 8 : 1))) void k_grid(Args<real> a, real* gv_out, real* gmd_out, int list,
                                                      GridStore<real> gs)
 {
   const int n_act = a.active[list];
@@ -2009,7 +2009,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p_adj(Args<real> a, const real* __
 // --------------------------------------------------------------------------
 
 template <typename real, int D>
-__global__ __launch_bounds__(kGridBlock) __attribute__((amdgpu_waves_per_eu(sizeof(real) == 4 ? 8 : 1))) void k_grid_adj(Args<real> a, const real* __restrict__ gmd_in,
+__global__ __launch_bounds__(kGridThreadsMax) __attribute__((amdgpu_waves_per_eu(sizeof(real) == 4 ? 8 : 1))) void k_grid_adj(Args<real> a, const real* __restrict__ gmd_in,
                                                          real* __restrict__ gpm_out, int list, int step)
 {
   const int n_act = a.active[list];

@@ -66,9 +66,9 @@ def test_grid_threads_option_is_validated():
     inst = _block(3, 4, floor=False)
     sim = M.MpmMag([inst.params], [len(inst.x0)], precision=4)
     try:
-        for bad in (128, 300, 576, -1):
+        for bad in (128, 300, 1088, -1):
             assert _status_of(lambda: sim.set_option("grid_threads", bad)) == M.EINVAL, bad
-        for good in (0, 256, 384, 512):
+        for good in (0, 256, 384, 512, 1024):
             sim.set_option("grid_threads", good)
     finally:
         sim.close()
