@@ -147,6 +147,15 @@ def bspline(f: float):
     return w, dw
 
 
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (n <= 0: the OpenMP default)."""
+    lib().orc_set_threads(C.c_int(int(n)))
+
+
+def get_threads() -> int:
+    return int(lib().orc_get_threads())
+
+
 def segment(p: dict, n: int) -> int:
     return lib().orc_segment(C.byref(params(p)), C.c_int(n))
 

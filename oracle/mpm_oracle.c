@@ -44,14 +44,21 @@
  *   - Piecewise-constant field: segment k(n) = n / L (periodic: mod S, else
  *     clamped to S-1), B evaluated at the start of the step.
  *
- * Arithmetic: IEEE double, serial loops in a fixed order, no fast-math.
- * Particle data is stored with three components and 3x3 matrices in 2D too
- * (z parts zero, F33 = 1).
+ * Arithmetic: IEEE double, no fast-math. Particle and node loops run on the
+ * host's cores with OpenMP; a scatter to the grid adds into one private grid
+ * per thread, and the private grids are summed node by node in thread order
+ * (see "host parallelism" below). Built without OpenMP the loops run serially
+ * in particle order. Particle data is stored with three components and 3x3
+ * matrices in 2D too (z parts zero, F33 = 1).
  */
+#include <limits.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 enum {
     ORC_OK = 0, ORC_EINVAL = 1, ORC_ENOMEM = 2,
@@ -143,6 +150,124 @@ static double ddot9(const double A[9], const double B[9])
     double s = 0.0;
     for (int k = 0; k < 9; ++k) s += A[k] * B[k];
     return s;
+}
+
+/* ------------------------------------------------------------------------- */
+/* host parallelism                                                          */
+/* ------------------------------------------------------------------------- */
+
+static int max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+static int thread_id(void)
+{
+#ifdef _OPENMP
+    return omp_get_thread_num();
+#else
+    return 0;
+#endif
+}
+
+/* Threads of the oracle's parallel loops; n <= 0 restores the OpenMP default
+ * (all host cores unless OMP_NUM_THREADS says otherwise). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    static int initial = 0;
+    if (!initial) initial = omp_get_max_threads();
+    omp_set_num_threads(n > 0 ? n : initial);
+#else
+    (void)n;
+#endif
+}
+
+int orc_get_threads(void) { return max_threads(); }
+
+/*
+ * Private scatter grids. A particle loop that adds into grid nodes gives each
+ * thread a contiguous block of particles (static schedule) and its own copy of
+ * the grid, 4 values per node. The copies are then summed node by node in
+ * thread order 0, 1, 2, ...: a run repeats exactly, and the result differs
+ * from the serial particle-order sum only in the order of the additions. A
+ * copy holds zeros outside the range of node indices [lo, hi] its thread
+ * touched; the sum skips it there, and the range is cleared afterwards.
+ */
+typedef struct {
+    int nt, G;
+    double* buf;   /* [nt][G][4] */
+    int* lo;       /* [nt] */
+    int* hi;       /* [nt] */
+} orc_scatter;
+
+static int scatter_alloc(orc_scatter* ws, int G)
+{
+    ws->nt = max_threads();
+    ws->G = G;
+    ws->buf = calloc((size_t)ws->nt * (size_t)(G > 0 ? G : 1) * 4, sizeof(double));
+    ws->lo = malloc(sizeof(int) * ws->nt);
+    ws->hi = malloc(sizeof(int) * ws->nt);
+    if (!ws->buf || !ws->lo || !ws->hi) {
+        free(ws->buf); free(ws->lo); free(ws->hi);
+        ws->buf = NULL; ws->lo = ws->hi = NULL;
+        return ORC_ENOMEM;
+    }
+    return 0;
+}
+
+static void scatter_free(orc_scatter* ws)
+{
+    free(ws->buf); free(ws->lo); free(ws->hi);
+    ws->buf = NULL; ws->lo = ws->hi = NULL;
+}
+
+/* no node touched yet */
+static void scatter_begin(orc_scatter* ws)
+{
+    for (int t = 0; t < ws->nt; ++t) {
+        ws->lo[t] = ws->G;
+        ws->hi[t] = -1;
+    }
+}
+
+static double* scatter_copy(const orc_scatter* ws, int t) { return ws->buf + (size_t)t * ws->G * 4; }
+
+/* sum of the private copies at node g, in thread order */
+static void scatter_node(const orc_scatter* ws, int g, double acc[4])
+{
+    acc[0] = acc[1] = acc[2] = acc[3] = 0.0;
+    for (int t = 0; t < ws->nt; ++t) {
+        if (g < ws->lo[t] || g > ws->hi[t]) continue;
+        const double* c = scatter_copy(ws, t) + (size_t)g * 4;
+        for (int k = 0; k < 4; ++k) acc[k] += c[k];
+    }
+}
+
+/* zero what each thread touched, so every copy is zero again */
+static void scatter_clear(orc_scatter* ws)
+{
+    for (int t = 0; t < ws->nt; ++t)
+        if (ws->hi[t] >= ws->lo[t])
+            memset(scatter_copy(ws, t) + (size_t)ws->lo[t] * 4, 0,
+                   sizeof(double) * 4 * (size_t)(ws->hi[t] - ws->lo[t] + 1));
+}
+
+/* Error of a parallel particle loop. The serial loop stops at the first
+ * particle whose stencil cannot be formed, and otherwise reports the first
+ * particle whose new state is flagged; keys index * 8 + code keep that order
+ * under a minimum. */
+#define ERR_KEY(q, code) ((long long)(q) * 8 + (long long)(code))
+#define ERR_NONE LLONG_MAX
+static int err_code(long long first_in, long long first_out)
+{
+    if (first_in != ERR_NONE) return (int)(first_in % 8);
+    if (first_out != ERR_NONE) return (int)(first_out % 8);
+    return 0;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -333,38 +458,72 @@ static double particle_mass(const orc_params* P, double phi) { return phi * P->r
 /* forward pieces                                                            */
 /* ------------------------------------------------------------------------- */
 
-/* Eqs. 14-15: grid mass m[G] and momentum p[G][3] */
-int orc_p2g(const orc_params* P, int N, const orc_particle* s, const double* phi, const double* br3,
-            const double B[3], double* m, double* p)
+/* Eqs. 14-15: grid mass m[G] and momentum p[G][3], through the private
+ * scatter grids ws (copy slot 0: mass, slots 1-3: momentum) */
+static int p2g_into(const orc_params* P, int N, const orc_particle* s, const double* phi, const double* br3,
+                    const double B[3], double* m, double* p, orc_scatter* ws)
 {
     int G = n_nodes(P);
     double dx = 1.0 / P->n_grid;
     double kappa = 4.0 * P->dt / (dx * dx);
-    memset(m, 0, sizeof(double) * G);
-    memset(p, 0, sizeof(double) * 3 * G);
-    for (int q = 0; q < N; ++q) {
-        orc_stencil S;
-        int e = make_stencil(P, s[q].x, &S);
-        if (e) return e;
-        double Pt[9], Pe[9], Pm[9], PFt[9], Ft[9], A[9];
-        particle_stress(P, s[q].F, phi[q], br3 + 3 * q, B, Pt, Pe, Pm);
-        transpose3(s[q].F, Ft);
-        matmul3(Pt, Ft, PFt);
-        double mp = particle_mass(P, phi[q]);
-        double V = P->particle_volume;
-        for (int k = 0; k < 9; ++k) A[k] = mp * s[q].C[k] - kappa * V * PFt[k];
-        FOR_STENCIL(P, a0, a1, a2) {
-            orc_node nd;
-            stencil_node(P, &S, a0, a1, a2, &nd);
-            m[nd.idx] += nd.w * mp;
-            for (int i = 0; i < 3; ++i) {
-                double Ad = 0.0;
-                for (int j = 0; j < 3; ++j) Ad += A[3 * i + j] * nd.dpos[j];
-                p[3 * nd.idx + i] += nd.w * (mp * s[q].v[i] + Ad);
+    long long first_err = ERR_NONE;
+    scatter_begin(ws);
+#pragma omp parallel num_threads(ws->nt) reduction(min : first_err)
+    {
+        const int t = thread_id();
+        double* mine = scatter_copy(ws, t);
+        int lo = G, hi = -1;
+#pragma omp for schedule(static)
+        for (int q = 0; q < N; ++q) {
+            orc_stencil S;
+            int e = make_stencil(P, s[q].x, &S);
+            if (e) {
+                if (ERR_KEY(q, e) < first_err) first_err = ERR_KEY(q, e);
+                continue;
+            }
+            double Pt[9], Pe[9], Pm[9], PFt[9], Ft[9], A[9];
+            particle_stress(P, s[q].F, phi[q], br3 + 3 * q, B, Pt, Pe, Pm);
+            transpose3(s[q].F, Ft);
+            matmul3(Pt, Ft, PFt);
+            double mp = particle_mass(P, phi[q]);
+            double V = P->particle_volume;
+            for (int k = 0; k < 9; ++k) A[k] = mp * s[q].C[k] - kappa * V * PFt[k];
+            FOR_STENCIL(P, a0, a1, a2) {
+                orc_node nd;
+                stencil_node(P, &S, a0, a1, a2, &nd);
+                double* c = mine + (size_t)nd.idx * 4;
+                c[0] += nd.w * mp;
+                for (int i = 0; i < 3; ++i) {
+                    double Ad = 0.0;
+                    for (int j = 0; j < 3; ++j) Ad += A[3 * i + j] * nd.dpos[j];
+                    c[1 + i] += nd.w * (mp * s[q].v[i] + Ad);
+                }
+                if (nd.idx < lo) lo = nd.idx;
+                if (nd.idx > hi) hi = nd.idx;
             }
         }
+        ws->lo[t] = lo;
+        ws->hi[t] = hi;
     }
-    return 0;
+#pragma omp parallel for schedule(static) num_threads(ws->nt)
+    for (int g = 0; g < G; ++g) {
+        double acc[4];
+        scatter_node(ws, g, acc);
+        m[g] = acc[0];
+        for (int i = 0; i < 3; ++i) p[3 * g + i] = acc[1 + i];
+    }
+    scatter_clear(ws);
+    return err_code(first_err, ERR_NONE);
+}
+
+int orc_p2g(const orc_params* P, int N, const orc_particle* s, const double* phi, const double* br3,
+            const double B[3], double* m, double* p)
+{
+    orc_scatter ws;
+    if (scatter_alloc(&ws, n_nodes(P))) return ORC_ENOMEM;
+    int e = p2g_into(P, N, s, phi, br3, B, m, p, &ws);
+    scatter_free(&ws);
+    return e;
 }
 
 static void node_coords(const orc_params* P, int g, int ijk[3])
@@ -496,6 +655,7 @@ static void grid_node(const orc_params* P, int g, int n, double m, const double 
 void orc_grid(const orc_params* P, int n, const double* m, const double* p, double* v)
 {
     int G = n_nodes(P);
+#pragma omp parallel for schedule(static)
     for (int g = 0; g < G; ++g) grid_node(P, g, n, m[g], p + 3 * g, v + 3 * g);
 }
 
@@ -504,11 +664,15 @@ int orc_g2p(const orc_params* P, int N, const orc_particle* s, const double* v, 
 {
     double dx = 1.0 / P->n_grid;
     double lam = 4.0 / (dx * dx);
-    int err = 0;
+    long long first_in = ERR_NONE, first_out = ERR_NONE;
+#pragma omp parallel for schedule(static) reduction(min : first_in, first_out)
     for (int q = 0; q < N; ++q) {
         orc_stencil S;
         int e = make_stencil(P, s[q].x, &S);
-        if (e) return e;
+        if (e) {
+            if (ERR_KEY(q, e) < first_in) first_in = ERR_KEY(q, e);
+            continue;
+        }
         double vn[3] = {0, 0, 0}, Bm[9] = {0};
         FOR_STENCIL(P, a0, a1, a2) {
             orc_node nd;
@@ -531,6 +695,7 @@ int orc_g2p(const orc_params* P, int N, const orc_particle* s, const double* v, 
         matmul3(IdC, s[q].F, r.F);
         out[q] = r;
         /* error flags on the new state */
+        int err = 0;
         for (int k = 0; k < 9 && !err; ++k)
             if (!isfinite(r.F[k]) || !isfinite(r.C[k])) err = ORC_ENONFINITE;
         for (int k = 0; k < 3 && !err; ++k)
@@ -541,16 +706,17 @@ int orc_g2p(const orc_params* P, int N, const orc_particle* s, const double* v, 
             int e2 = make_stencil(P, r.x, &S2);
             if (e2) err = e2;
         }
+        if (err && ERR_KEY(q, err) < first_out) first_out = ERR_KEY(q, err);
     }
-    return err;
+    return err_code(first_in, first_out);
 }
 
 /* one full step n: P2G, grid update, G2P. Work arrays m[G], p[3G], v[3G]. */
 static int step_forward(const orc_params* P, int N, int n, const orc_particle* s, const double* phi,
                         const double* br3, const double B[3], double* m, double* p, double* v,
-                        orc_particle* out)
+                        orc_particle* out, orc_scatter* ws)
 {
-    int e = orc_p2g(P, N, s, phi, br3, B, m, p);
+    int e = p2g_into(P, N, s, phi, br3, B, m, p, ws);
     if (e) return e;
     orc_grid(P, n, m, p, v);
     return orc_g2p(P, N, s, v, out);
@@ -566,73 +732,105 @@ static int step_forward(const orc_params* P, int N, int n, const orc_particle* s
  * (overwritten) and the G2P share of the adjoint of state n: xb0, Fb0
  * (overwritten; the P2G transpose adds its share later).
  */
-int orc_g2p_adj(const orc_params* P, int N, const orc_particle* s, const double* v,
-                const orc_particle* adj1, double* vbar, orc_particle* adj0)
+static int g2p_adj_into(const orc_params* P, int N, const orc_particle* s, const double* v,
+                        const orc_particle* adj1, double* vbar, orc_particle* adj0, orc_scatter* ws)
 {
     int G = n_nodes(P);
     double dx = 1.0 / P->n_grid;
     double lam = 4.0 / (dx * dx);
     double dt = P->dt;
-    memset(vbar, 0, sizeof(double) * 3 * G);
-    for (int q = 0; q < N; ++q) {
-        orc_stencil S;
-        int e = make_stencil(P, s[q].x, &S);
-        if (e) return e;
-        /* recompute the new affine matrix C' */
-        double Bm[9] = {0};
-        FOR_STENCIL(P, a0, a1, a2) {
-            orc_node nd;
-            stencil_node(P, &S, a0, a1, a2, &nd);
-            const double* vi = v + 3 * nd.idx;
+    long long first_err = ERR_NONE;
+    scatter_begin(ws);
+#pragma omp parallel num_threads(ws->nt) reduction(min : first_err)
+    {
+        const int t = thread_id();
+        double* mine = scatter_copy(ws, t);
+        int lo = G, hi = -1;
+#pragma omp for schedule(static)
+        for (int q = 0; q < N; ++q) {
+            orc_stencil S;
+            int e = make_stencil(P, s[q].x, &S);
+            if (e) {
+                if (ERR_KEY(q, e) < first_err) first_err = ERR_KEY(q, e);
+                continue;
+            }
+            /* recompute the new affine matrix C' */
+            double Bm[9] = {0};
+            FOR_STENCIL(P, a0, a1, a2) {
+                orc_node nd;
+                stencil_node(P, &S, a0, a1, a2, &nd);
+                const double* vi = v + 3 * nd.idx;
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) Bm[3 * i + j] += nd.w * vi[i] * nd.dpos[j];
+            }
+            double Cn[9], IdC[9], IdCt[9], Ft[9], FbFt[9];
+            for (int k = 0; k < 9; ++k) Cn[k] = lam * Bm[k];
             for (int i = 0; i < 3; ++i)
-                for (int j = 0; j < 3; ++j) Bm[3 * i + j] += nd.w * vi[i] * nd.dpos[j];
-        }
-        double Cn[9], IdC[9], IdCt[9], Ft[9], FbFt[9];
-        for (int k = 0; k < 9; ++k) Cn[k] = lam * Bm[k];
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) IdC[3 * i + j] = (i == j ? 1.0 : 0.0) + dt * Cn[3 * i + j];
-        const orc_particle* a1p = &adj1[q];
-        orc_particle* a0p = &adj0[q];
-        /* F' = (I + dt C') F */
-        transpose3(IdC, IdCt);
-        matmul3(IdCt, a1p->F, a0p->F);
-        transpose3(s[q].F, Ft);
-        matmul3(a1p->F, Ft, FbFt);
-        double Cbt[9], vbt[3];
-        for (int k = 0; k < 9; ++k) Cbt[k] = a1p->C[k] + dt * FbFt[k];
-        /* x' = x + dt v' */
-        for (int i = 0; i < 3; ++i) {
-            vbt[i] = a1p->v[i] + dt * a1p->x[i];
-            a0p->x[i] = a1p->x[i];
-            a0p->v[i] = 0.0;
-        }
-        for (int k = 0; k < 9; ++k) a0p->C[k] = 0.0;
-        /* v' = sum w v_i ; C' = lam sum w v_i dpos^T */
-        FOR_STENCIL(P, a0, a1, a2) {
-            orc_node nd;
-            stencil_node(P, &S, a0, a1, a2, &nd);
-            const double* vi = v + 3 * nd.idx;
-            double u[3];
+                for (int j = 0; j < 3; ++j) IdC[3 * i + j] = (i == j ? 1.0 : 0.0) + dt * Cn[3 * i + j];
+            const orc_particle* a1p = &adj1[q];
+            orc_particle* a0p = &adj0[q];
+            /* F' = (I + dt C') F */
+            transpose3(IdC, IdCt);
+            matmul3(IdCt, a1p->F, a0p->F);
+            transpose3(s[q].F, Ft);
+            matmul3(a1p->F, Ft, FbFt);
+            double Cbt[9], vbt[3];
+            for (int k = 0; k < 9; ++k) Cbt[k] = a1p->C[k] + dt * FbFt[k];
+            /* x' = x + dt v' */
             for (int i = 0; i < 3; ++i) {
-                double Cd = 0.0;
-                for (int j = 0; j < 3; ++j) Cd += Cbt[3 * i + j] * nd.dpos[j];
-                u[i] = vbt[i] + lam * Cd;
-                vbar[3 * nd.idx + i] += nd.w * u[i];
+                vbt[i] = a1p->v[i] + dt * a1p->x[i];
+                a0p->x[i] = a1p->x[i];
+                a0p->v[i] = 0.0;
             }
-            double vu = vi[0] * u[0] + vi[1] * u[1] + vi[2] * u[2];
-            for (int k = 0; k < 3; ++k) {
-                double CtV = 0.0;
-                for (int i = 0; i < 3; ++i) CtV += Cbt[3 * i + k] * vi[i];
-                a0p->x[k] += vu * nd.gw[k] - lam * nd.w * CtV;
+            for (int k = 0; k < 9; ++k) a0p->C[k] = 0.0;
+            /* v' = sum w v_i ; C' = lam sum w v_i dpos^T */
+            FOR_STENCIL(P, a0, a1, a2) {
+                orc_node nd;
+                stencil_node(P, &S, a0, a1, a2, &nd);
+                const double* vi = v + 3 * nd.idx;
+                double u[3];
+                for (int i = 0; i < 3; ++i) {
+                    double Cd = 0.0;
+                    for (int j = 0; j < 3; ++j) Cd += Cbt[3 * i + j] * nd.dpos[j];
+                    u[i] = vbt[i] + lam * Cd;
+                    mine[(size_t)nd.idx * 4 + i] += nd.w * u[i];
+                }
+                if (nd.idx < lo) lo = nd.idx;
+                if (nd.idx > hi) hi = nd.idx;
+                double vu = vi[0] * u[0] + vi[1] * u[1] + vi[2] * u[2];
+                for (int k = 0; k < 3; ++k) {
+                    double CtV = 0.0;
+                    for (int i = 0; i < 3; ++i) CtV += Cbt[3 * i + k] * vi[i];
+                    a0p->x[k] += vu * nd.gw[k] - lam * nd.w * CtV;
+                }
+            }
+            if (P->dim == 2) {
+                a0p->x[2] = 0.0;
+                for (int k = 0; k < 9; ++k)
+                    if (k / 3 == 2 || k % 3 == 2) a0p->F[k] = 0.0;
             }
         }
-        if (P->dim == 2) {
-            a0p->x[2] = 0.0;
-            for (int k = 0; k < 9; ++k)
-                if (k / 3 == 2 || k % 3 == 2) a0p->F[k] = 0.0;
-        }
+        ws->lo[t] = lo;
+        ws->hi[t] = hi;
     }
-    return 0;
+#pragma omp parallel for schedule(static) num_threads(ws->nt)
+    for (int g = 0; g < G; ++g) {
+        double acc[4];
+        scatter_node(ws, g, acc);
+        for (int i = 0; i < 3; ++i) vbar[3 * g + i] = acc[i];
+    }
+    scatter_clear(ws);
+    return err_code(first_err, ERR_NONE);
+}
+
+int orc_g2p_adj(const orc_params* P, int N, const orc_particle* s, const double* v,
+                const orc_particle* adj1, double* vbar, orc_particle* adj0)
+{
+    orc_scatter ws;
+    if (scatter_alloc(&ws, n_nodes(P))) return ORC_ENOMEM;
+    int e = g2p_adj_into(P, N, s, v, adj1, vbar, adj0, &ws);
+    scatter_free(&ws);
+    return e;
 }
 
 /* transpose of the floor slide map at input u (vn < 0, |v_t| > 0, slide branch) */
@@ -734,6 +932,7 @@ void orc_grid_adj(const orc_params* P, int n, const double* m, const double* p, 
                   double* pbar, double* mbar)
 {
     int G = n_nodes(P);
+#pragma omp parallel for schedule(static)
     for (int g = 0; g < G; ++g) grid_node_adj(P, g, n, m[g], p + 3 * g, vbar + 3 * g, pbar + 3 * g, mbar + g);
 }
 
@@ -751,82 +950,99 @@ int orc_p2g_adj(const orc_params* P, int N, const orc_particle* s, const double*
     double V = P->particle_volume;
     double G, K;
     orc_moduli(P->E, P->nu, &G, &K);
-    for (int q = 0; q < N; ++q) {
-        orc_stencil S;
-        int e = make_stencil(P, s[q].x, &S);
-        if (e) return e;
-        double Pt[9], Pe[9], Pm[9], PFt[9], Ft[9], A[9];
-        particle_stress(P, s[q].F, phi[q], br3 + 3 * q, B, Pt, Pe, Pm);
-        transpose3(s[q].F, Ft);
-        matmul3(Pt, Ft, PFt);
-        double mp = particle_mass(P, phi[q]);
-        for (int k = 0; k < 9; ++k) A[k] = mp * s[q].C[k] - kappa * V * PFt[k];
-        double mb = 0.0, vb[3] = {0, 0, 0}, Ab[9] = {0}, xb[3] = {0, 0, 0};
-        FOR_STENCIL(P, a0, a1, a2) {
-            orc_node nd;
-            stencil_node(P, &S, a0, a1, a2, &nd);
-            const double* pb = pbar + 3 * nd.idx;
-            double mbi = mbar[nd.idx];
-            double Ad[3], Atp[3];
-            for (int i = 0; i < 3; ++i) {
-                Ad[i] = 0.0;
-                Atp[i] = 0.0;
-                for (int j = 0; j < 3; ++j) {
-                    Ad[i] += A[3 * i + j] * nd.dpos[j];
-                    Atp[i] += A[3 * j + i] * pb[j];
+    /* the field gradient sums over all particles: one partial sum per thread
+     * (its contiguous block of particles, in order), added in thread order */
+    const int nt = max_threads();
+    double* gB_part = calloc((size_t)nt * 3, sizeof(double));
+    if (!gB_part) return ORC_ENOMEM;
+    long long first_err = ERR_NONE;
+#pragma omp parallel num_threads(nt) reduction(min : first_err)
+    {
+        double* gB_t = gB_part + 3 * thread_id();
+#pragma omp for schedule(static)
+        for (int q = 0; q < N; ++q) {
+            orc_stencil S;
+            int e = make_stencil(P, s[q].x, &S);
+            if (e) {
+                if (ERR_KEY(q, e) < first_err) first_err = ERR_KEY(q, e);
+                continue;
+            }
+            double Pt[9], Pe[9], Pm[9], PFt[9], Ft[9], A[9];
+            particle_stress(P, s[q].F, phi[q], br3 + 3 * q, B, Pt, Pe, Pm);
+            transpose3(s[q].F, Ft);
+            matmul3(Pt, Ft, PFt);
+            double mp = particle_mass(P, phi[q]);
+            for (int k = 0; k < 9; ++k) A[k] = mp * s[q].C[k] - kappa * V * PFt[k];
+            double mb = 0.0, vb[3] = {0, 0, 0}, Ab[9] = {0}, xb[3] = {0, 0, 0};
+            FOR_STENCIL(P, a0, a1, a2) {
+                orc_node nd;
+                stencil_node(P, &S, a0, a1, a2, &nd);
+                const double* pb = pbar + 3 * nd.idx;
+                double mbi = mbar[nd.idx];
+                double Ad[3], Atp[3];
+                for (int i = 0; i < 3; ++i) {
+                    Ad[i] = 0.0;
+                    Atp[i] = 0.0;
+                    for (int j = 0; j < 3; ++j) {
+                        Ad[i] += A[3 * i + j] * nd.dpos[j];
+                        Atp[i] += A[3 * j + i] * pb[j];
+                    }
                 }
+                double pv = pb[0] * s[q].v[0] + pb[1] * s[q].v[1] + pb[2] * s[q].v[2];
+                double pmom = 0.0;
+                for (int i = 0; i < 3; ++i) pmom += pb[i] * (mp * s[q].v[i] + Ad[i]);
+                mb += nd.w * (mbi + pv);
+                for (int i = 0; i < 3; ++i) {
+                    vb[i] += nd.w * mp * pb[i];
+                    for (int j = 0; j < 3; ++j) Ab[3 * i + j] += nd.w * pb[i] * nd.dpos[j];
+                }
+                for (int k = 0; k < 3; ++k)
+                    xb[k] += (mbi * mp + pmom) * nd.gw[k] - nd.w * Atp[k];
             }
-            double pv = pb[0] * s[q].v[0] + pb[1] * s[q].v[1] + pb[2] * s[q].v[2];
-            double pmom = 0.0;
-            for (int i = 0; i < 3; ++i) pmom += pb[i] * (mp * s[q].v[i] + Ad[i]);
-            mb += nd.w * (mbi + pv);
-            for (int i = 0; i < 3; ++i) {
-                vb[i] += nd.w * mp * pb[i];
-                for (int j = 0; j < 3; ++j) Ab[3 * i + j] += nd.w * pb[i] * nd.dpos[j];
+            /* A = m C - kappa V P F^T */
+            mb += ddot9(Ab, s[q].C);
+            double Pb[9], AbF[9], Abt[9], AbtP[9], dP[9];
+            matmul3(Ab, s[q].F, AbF);
+            for (int k = 0; k < 9; ++k) Pb[k] = -kappa * V * AbF[k];
+            transpose3(Ab, Abt);
+            matmul3(Abt, Pt, AbtP);
+            if (P->dim == 2)
+                for (int k = 0; k < 9; ++k)
+                    if (k / 3 == 2 || k % 3 == 2) Pb[k] = 0.0;
+            orc_stress_elastic_dir(s[q].F, G, K, Pb, dP);
+            double se = simp_e(P, phi[q]), sm = simp_m(P, phi[q]);
+            orc_particle* a = &adj[q];
+            for (int k = 0; k < 9; ++k) {
+                a->C[k] = mp * Ab[k];
+                a->F[k] += -kappa * V * AbtP[k] + se * dP[k];
             }
-            for (int k = 0; k < 3; ++k)
-                xb[k] += (mbi * mp + pmom) * nd.gw[k] - nd.w * Atp[k];
-        }
-        /* A = m C - kappa V P F^T */
-        mb += ddot9(Ab, s[q].C);
-        double Pb[9], AbF[9], Abt[9], AbtP[9], dP[9];
-        matmul3(Ab, s[q].F, AbF);
-        for (int k = 0; k < 9; ++k) Pb[k] = -kappa * V * AbF[k];
-        transpose3(Ab, Abt);
-        matmul3(Abt, Pt, AbtP);
-        if (P->dim == 2)
-            for (int k = 0; k < 9; ++k)
-                if (k / 3 == 2 || k % 3 == 2) Pb[k] = 0.0;
-        orc_stress_elastic_dir(s[q].F, G, K, Pb, dP);
-        double se = simp_e(P, phi[q]), sm = simp_m(P, phi[q]);
-        orc_particle* a = &adj[q];
-        for (int k = 0; k < 9; ++k) {
-            a->C[k] = mp * Ab[k];
-            a->F[k] += -kappa * V * AbtP[k] + se * dP[k];
-        }
-        for (int k = 0; k < 3; ++k) {
-            a->v[k] = vb[k];
-            a->x[k] += xb[k];
-        }
-        if (P->dim == 2) {
-            a->x[2] = a->v[2] = 0.0;
-            for (int k = 0; k < 9; ++k)
-                if (k / 3 == 2 || k % 3 == 2) { a->F[k] = 0.0; a->C[k] = 0.0; }
-        }
-        /* P = s_e(phi) P_e + s_m(phi) P_m ; m = phi rho V */
-        gphi[q] += P->rho * V * mb + simp_e_d(P, phi[q]) * ddot9(Pb, Pe) + simp_m_d(P, phi[q]) * ddot9(Pb, Pm);
-        /* P_m = -(1/mu0) B (x) Br */
-        for (int j = 0; j < 3; ++j) {
-            double PtB = 0.0, PBr = 0.0;
-            for (int i = 0; i < 3; ++i) {
-                PtB += Pb[3 * i + j] * B[i];
-                PBr += Pb[3 * j + i] * br3[3 * q + i];
+            for (int k = 0; k < 3; ++k) {
+                a->v[k] = vb[k];
+                a->x[k] += xb[k];
             }
-            gbr3[3 * q + j] += -sm / P->mu0 * PtB;
-            gB[j] += -sm / P->mu0 * PBr;
+            if (P->dim == 2) {
+                a->x[2] = a->v[2] = 0.0;
+                for (int k = 0; k < 9; ++k)
+                    if (k / 3 == 2 || k % 3 == 2) { a->F[k] = 0.0; a->C[k] = 0.0; }
+            }
+            /* P = s_e(phi) P_e + s_m(phi) P_m ; m = phi rho V */
+            gphi[q] += P->rho * V * mb + simp_e_d(P, phi[q]) * ddot9(Pb, Pe) + simp_m_d(P, phi[q]) * ddot9(Pb, Pm);
+            /* P_m = -(1/mu0) B (x) Br */
+            for (int j = 0; j < 3; ++j) {
+                double PtB = 0.0, PBr = 0.0;
+                for (int i = 0; i < 3; ++i) {
+                    PtB += Pb[3 * i + j] * B[i];
+                    PBr += Pb[3 * j + i] * br3[3 * q + i];
+                }
+                gbr3[3 * q + j] += -sm / P->mu0 * PtB;
+                gB_t[j] += -sm / P->mu0 * PBr;
+            }
         }
     }
-    return 0;
+    for (int t = 0; t < nt; ++t)
+        for (int j = 0; j < 3; ++j) gB[j] += gB_part[3 * t + j];
+    free(gB_part);
+    return err_code(first_err, ERR_NONE);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -934,8 +1150,9 @@ int orc_rollout(const orc_params* P, int N, const double* x0, const double* v0, 
     double* m = malloc(sizeof(double) * G);
     double* p = malloc(sizeof(double) * 3 * G);
     double* v = malloc(sizeof(double) * 3 * G);
-    int err = 0;
-    if (!s || !t || !br3 || !m || !p || !v) { err = ORC_ENOMEM; goto done; }
+    orc_scatter ws;
+    int err = scatter_alloc(&ws, G);
+    if (!s || !t || !br3 || !m || !p || !v || err) { err = ORC_ENOMEM; goto done; }
     init_state(P, N, x0, v0, s);
     expand3(P, N, br, br3);
     double M = total_mass(P, N, phi);
@@ -946,7 +1163,7 @@ int orc_rollout(const orc_params* P, int N, const double* x0, const double* v0, 
     for (int n = 0; n < P->n_steps; ++n) {
         double B[3];
         field_at(P, bprog, n, B);
-        err = step_forward(P, N, n, s, phi, br3, B, m, p, v, t);
+        err = step_forward(P, N, n, s, phi, br3, B, m, p, v, t, &ws);
         if (err) goto done;
         orc_particle* tmp = s; s = t; t = tmp;
         if (P->loss_kind == ORC_LOSS_TRAJ_VEL && N) traj += traj_step(P, N, s, phi, M);
@@ -963,6 +1180,7 @@ int orc_rollout(const orc_params* P, int N, const double* x0, const double* v0, 
     if (loss_out) *loss_out = N ? loss_value(P, N, s, x0, phi, target, mask, traj) : 0.0;
 done:
     free(s); free(t); free(br3); free(m); free(p); free(v);
+    scatter_free(&ws);
     return err;
 }
 
@@ -971,11 +1189,12 @@ done:
 static int reverse_step(const orc_params* P, int N, int n, const orc_particle* sn, const double* phi,
                         const double* br3, const double* bprog, double* m, double* p, double* v,
                         double* vbar, double* pbar, double* mbar, orc_particle* adj, orc_particle* adj0,
-                        double* gphi, double* gbr3, double* gprog, double traj_seed, double M)
+                        double* gphi, double* gbr3, double* gprog, double traj_seed, double M,
+                        orc_scatter* ws)
 {
     double B[3];
     field_at(P, bprog, n, B);
-    int e = orc_p2g(P, N, sn, phi, br3, B, m, p);
+    int e = p2g_into(P, N, sn, phi, br3, B, m, p, ws);
     if (e) return e;
     orc_grid(P, n, m, p, v);
     if (P->loss_kind == ORC_LOSS_TRAJ_VEL)
@@ -983,7 +1202,7 @@ static int reverse_step(const orc_params* P, int N, int n, const orc_particle* s
             double mq = particle_mass(P, phi[q]);
             for (int k = 0; k < P->dim; ++k) adj[q].v[k] += traj_seed * (-P->dt * mq * P->loss_dir[k] / M);
         }
-    e = orc_g2p_adj(P, N, sn, v, adj, vbar, adj0);
+    e = g2p_adj_into(P, N, sn, v, adj, vbar, adj0, ws);
     if (e) return e;
     orc_grid_adj(P, n, m, p, vbar, pbar, mbar);
     double gB[3] = {0, 0, 0};
@@ -1025,8 +1244,9 @@ int orc_backward(const orc_params* P, int N, const double* x0, const double* phi
     double* vbar = malloc(sizeof(double) * 3 * G);
     double* pbar = malloc(sizeof(double) * 3 * G);
     double* mbar = malloc(sizeof(double) * G);
-    int err = 0;
-    if (!ck || !seg || !adj || !adj0 || !br3 || !gbr3 || !vsum || !m || !p || !v || !vbar || !pbar || !mbar) {
+    orc_scatter ws;
+    int err = scatter_alloc(&ws, G);
+    if (!ck || !seg || !adj || !adj0 || !br3 || !gbr3 || !vsum || !m || !p || !v || !vbar || !pbar || !mbar || err) {
         err = ORC_ENOMEM;
         goto done;
     }
@@ -1044,7 +1264,7 @@ int orc_backward(const orc_params* P, int N, const double* x0, const double* phi
         if (n % K == 0) memcpy(ck + (size_t)(n / K) * N, cur, ps);
         double B[3];
         field_at(P, bprog, n, B);
-        err = step_forward(P, N, n, cur, phi, br3, B, m, p, v, nxt);
+        err = step_forward(P, N, n, cur, phi, br3, B, m, p, v, nxt, &ws);
         if (err) goto done;
         orc_particle* tmp = cur; cur = nxt; nxt = tmp;
         if (P->loss_kind == ORC_LOSS_TRAJ_VEL) {
@@ -1100,12 +1320,12 @@ int orc_backward(const orc_params* P, int N, const double* x0, const double* phi
             double B[3];
             field_at(P, bprog, n, B);
             err = step_forward(P, N, n, seg + (size_t)(n - s0) * N, phi, br3, B, m, p, v,
-                               seg + (size_t)(n - s0 + 1) * N);
+                               seg + (size_t)(n - s0 + 1) * N, &ws);
             if (err) goto done;
         }
         for (int n = s1 - 1; n >= s0; --n) {
             err = reverse_step(P, N, n, seg + (size_t)(n - s0) * N, phi, br3, bprog, m, p, v, vbar, pbar,
-                               mbar, adj, adj0, gphi, gbr3, gprog, dloss, M);
+                               mbar, adj, adj0, gphi, gbr3, gprog, dloss, M, &ws);
             if (err) goto done;
         }
     }
@@ -1114,6 +1334,7 @@ int orc_backward(const orc_params* P, int N, const double* x0, const double* phi
 done:
     free(ck); free(seg); free(adj); free(adj0); free(br3); free(gbr3); free(vsum);
     free(m); free(p); free(v); free(vbar); free(pbar); free(mbar);
+    scatter_free(&ws);
     return err;
 }
 
