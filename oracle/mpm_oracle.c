@@ -1099,16 +1099,17 @@ static double loss_value(const orc_params* P, int N, const orc_particle* sT, con
         }
         return cnt ? -s / cnt : 0.0;
     }
-    double M = 0.0, s1 = 0.0, s0 = 0.0;
+    /* Eq. 40 sums the mass-averaged velocity over the steps, i.e. the centre
+     * of mass's displacement: summed here from each particle's displacement
+     * x(T) - x(0), not as a difference of two centres of mass (which would
+     * cancel nearly all digits of a small displacement) */
+    double M = 0.0, s = 0.0;
     for (int q = 0; q < N; ++q) {
         double mq = particle_mass(P, phi[q]);
         M += mq;
-        for (int k = 0; k < d; ++k) {
-            s1 += mq * e[k] * sT[q].x[k];
-            s0 += mq * e[k] * x0[q * d + k];
-        }
+        for (int k = 0; k < d; ++k) s += mq * e[k] * (sT[q].x[k] - x0[q * d + k]);
     }
-    if (P->loss_kind == ORC_LOSS_COM_DISP) return -(s1 - s0) / M;
+    if (P->loss_kind == ORC_LOSS_COM_DISP) return -s / M;
     /* trajectory loss: -dt sum_n e . (sum_p m_p v_p(t_{n+1})) / M, accumulated */
     return traj_acc;
 }
