@@ -8,6 +8,7 @@ components and 3x3 matrices even in 2D (z parts zero, F33 = 1).
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import math
 import os
@@ -154,6 +155,31 @@ def set_threads(n: int) -> None:
 
 def get_threads() -> int:
     return int(lib().orc_get_threads())
+
+
+@contextlib.contextmanager
+def branch_trace(p: dict, replay=None, record: bool = False):
+    """Replay and/or record the grid operation's per-node decisions (has mass,
+    floor branch, wall zeroing, obstacle branches) for the rollouts and
+    gradients run inside the block; tables are uint16 [n_steps, n_nodes] in the
+    packing mpm_oracle.c documents. Yields the record table (or None)."""
+    G = num_nodes(p)
+    T = int(p["n_steps"])
+    rep = None if replay is None else np.ascontiguousarray(np.asarray(replay, dtype=np.uint16).reshape(T, G))
+    rec = np.zeros((T, G), dtype=np.uint16) if record else None
+    u16 = lambda a: a.ctypes.data_as(C.c_void_p) if a is not None else None
+    lib().orc_set_branch_trace(u16(rep), u16(rec), C.c_int64(G))
+    try:
+        yield rec
+    finally:
+        lib().orc_set_branch_trace(None, None, C.c_int64(0))
+
+
+def branch_mass_mismatches() -> int:
+    """Replayed "has mass" decisions at nodes where the oracle's mass is zero
+    (since the last branch_trace began)."""
+    lib().orc_branch_mass_mismatches.restype = C.c_longlong
+    return int(lib().orc_branch_mass_mismatches())
 
 
 def segment(p: dict, n: int) -> int:

@@ -535,21 +535,29 @@ static void node_coords(const orc_params* P, int g, int ijk[3])
 }
 
 /* floor contact (Eq. 18) on one node velocity u; returns the branch taken:
- * 0 untouched, 1 set to zero (no-slip, |v_t| = 0 or friction exceeds slip), 2 sliding */
-static int floor_contact(const orc_params* P, double u[3])
+ * 0 untouched, 1 set to zero (no-slip, |v_t| = 0 or friction exceeds slip), 2 sliding.
+ * force >= 0 applies that branch instead of deciding it (branch replay); a
+ * forced slide keeps the slide map v_t (1 - mu |v_n| / |v_t|), v_n -> 0. */
+static int floor_contact(const orc_params* P, double u[3], int force)
 {
     double vn = u[1];
-    if (!(vn < 0.0)) return 0;
-    if (isinf(P->floor_mu)) { u[0] = u[1] = u[2] = 0.0; return 1; }
     double vt[3] = {u[0], 0.0, u[2]};
     double t = sqrt(vt[0] * vt[0] + vt[2] * vt[2]);
-    if (t == 0.0) { u[0] = u[1] = u[2] = 0.0; return 1; }
     double s = t - P->floor_mu * (-vn);
-    if (s <= 0.0) { u[0] = u[1] = u[2] = 0.0; return 1; }
-    u[0] = s / t * vt[0];
-    u[1] = 0.0;
-    u[2] = s / t * vt[2];
-    return 2;
+    int br = force;
+    if (br < 0) {
+        if (!(vn < 0.0)) br = 0;
+        else if (isinf(P->floor_mu) || t == 0.0 || s <= 0.0) br = 1;
+        else br = 2;
+    }
+    if (br == 1 || (br == 2 && (isinf(P->floor_mu) || t == 0.0))) {
+        u[0] = u[1] = u[2] = 0.0;
+    } else if (br == 2) {
+        u[0] = s / t * vt[0];
+        u[1] = 0.0;
+        u[2] = s / t * vt[2];
+    }
+    return br;
 }
 
 /* Signed distance of obstacle O at node position x during step n, and its
@@ -595,20 +603,16 @@ static double obstacle_sdf(const orc_params* P, const orc_obstacle* O, int n, co
 }
 
 /* contact of Eq. 18 against a boundary with velocity vb and outward normal
- * nrm on node velocity u (3 components); returns 0 untouched, 1 set to vb,
- * 2 sliding */
-static int obstacle_contact(const orc_params* P, const orc_obstacle* O, const double nrm[3], double u[3])
+ * nrm on node velocity u (3 components) of a node on the boundary; returns 0
+ * untouched, 1 set to vb, 2 sliding. force >= 0 applies that branch instead
+ * of deciding it (branch replay). */
+static int obstacle_contact(const orc_params* P, const orc_obstacle* O, const double nrm[3], double u[3], int force)
 {
     double r[3], vn = 0.0;
     for (int k = 0; k < 3; ++k) {
         r[k] = (k < P->dim) ? u[k] - O->vel[k] : 0.0;
         vn += r[k] * nrm[k];
     }
-    if (O->attached) {
-        for (int k = 0; k < 3; ++k) u[k] = (k < P->dim) ? O->vel[k] : 0.0;
-        return 1;
-    }
-    if (!(vn < 0.0)) return 0;
     double tv[3], t = 0.0;
     for (int k = 0; k < 3; ++k) {
         tv[k] = r[k] - vn * nrm[k];
@@ -616,40 +620,130 @@ static int obstacle_contact(const orc_params* P, const orc_obstacle* O, const do
     }
     t = sqrt(t);
     double sl = t + O->mu * vn;
-    if (isinf(O->mu) || t == 0.0 || sl <= 0.0) {
-        for (int k = 0; k < 3; ++k) u[k] = (k < P->dim) ? O->vel[k] : 0.0;
-        return 1;
+    int br = force;
+    if (br < 0) {
+        if (O->attached) br = 1;
+        else if (!(vn < 0.0)) br = 0;
+        else if (isinf(O->mu) || t == 0.0 || sl <= 0.0) br = 1;
+        else br = 2;
     }
-    for (int k = 0; k < 3; ++k) u[k] = (k < P->dim) ? O->vel[k] + sl / t * tv[k] : 0.0;
-    return 2;
+    if (br == 1 || (br == 2 && (isinf(O->mu) || t == 0.0))) {
+        for (int k = 0; k < 3; ++k) u[k] = (k < P->dim) ? O->vel[k] : 0.0;
+    } else if (br == 2) {
+        for (int k = 0; k < 3; ++k) u[k] = (k < P->dim) ? O->vel[k] + sl / t * tv[k] : 0.0;
+    }
+    return br;
 }
 
-/* Eqs. 16-18 for one node during step n: returns v; vhat = p/m before forces */
-static void grid_node(const orc_params* P, int g, int n, double m, const double p[3], double v[3])
+/* ------------------------------------------------------------------------- */
+/* branch decisions of the grid operation                                    */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * The grid operation decides, per node and step, whether the node has mass
+ * (Eq. 16 applies only then), which branch of Eq. 18 the floor and each
+ * obstacle take, and which velocity components the domain walls zero. These
+ * integer decisions are taken from floating-point velocities, so a run in
+ * another precision can decide a near-tie the other way; the adjoint then
+ * follows the other branch (the Jacobian of the branch the forward took). For
+ * comparing such a run's arithmetic with the oracle's, the decisions can be
+ * replayed: with a replay table set, every node takes its decisions from the
+ * table instead of deciding them, in the forward steps and in the transpose
+ * alike. A record table receives the decisions taken. Tables hold one code per
+ * step and node, [n_steps][n_nodes] (nodes x fastest), packed as
+ *   bit 0      the node has mass
+ *   bits 1-2   floor branch (0 untouched, 1 zero, 2 slide)
+ *   bits 3-5   the walls zero the x, y, z component
+ *   bits 6+2j  obstacle j's branch (0 untouched, 1 v_b, 2 slide)
+ * Test instrumentation: the tables are process-wide, set with
+ * orc_set_branch_trace and cleared with NULL.
+ */
+static const uint16_t* g_replay;
+static uint16_t* g_record;
+static int64_t g_trace_nodes;
+static long long g_mass_mismatch;   /* replayed "has mass" where the oracle's mass is 0 */
+
+void orc_set_branch_trace(const uint16_t* replay, uint16_t* record, int64_t n_nodes)
 {
-    if (!(m > 0.0)) { v[0] = v[1] = v[2] = 0.0; return; }
+    g_replay = replay;
+    g_record = record;
+    g_trace_nodes = n_nodes;
+    g_mass_mismatch = 0;
+}
+
+long long orc_branch_mass_mismatches(void) { return g_mass_mismatch; }
+
+/* Eqs. 16-18 on one node in step n with every decision kept for the
+ * transpose. Returns 0 (and v = 0) for a node without mass. */
+typedef struct {
+    double vh[3], u0[3];                  /* p/m; after damping and gravity (Eq. 17) */
+    int floor_br;
+    double ob_in[ORC_MAX_OBST][3], ob_n[ORC_MAX_OBST][3];
+    int ob_br[ORC_MAX_OBST];
+    int wall[3], clamped;
+    double v[3];                          /* the node velocity */
+} orc_node_bc;
+
+static int node_bc(const orc_params* P, int g, int n, double m, const double p[3], orc_node_bc* s)
+{
+    memset(s, 0, sizeof *s);
+    const int64_t slot = (int64_t)n * g_trace_nodes + g;
+    const int code = g_replay ? (int)g_replay[slot] : -1;
+    int has_mass = m > 0.0;
+    if (code >= 0) {
+        if ((code & 1) && !has_mass) {
+#pragma omp atomic
+            ++g_mass_mismatch;
+        }
+        has_mass = has_mass && (code & 1);
+    }
+    if (!has_mass) {
+        if (g_record) g_record[slot] = 0;
+        return 0;
+    }
     int ijk[3];
     node_coords(P, g, ijk);
     double dx = 1.0 / P->n_grid;
     double c = P->damping;
     double u[3];
     for (int k = 0; k < 3; ++k) {
-        double vh = p[k] / m;
-        u[k] = (k < P->dim) ? vh + P->dt * (P->gravity[k] - c * vh) : 0.0;
+        s->vh[k] = p[k] / m;
+        s->u0[k] = (k < P->dim) ? s->vh[k] + P->dt * (P->gravity[k] - c * s->vh[k]) : 0.0;
+        u[k] = s->u0[k];
     }
-    if (P->floor_on && ijk[1] * dx <= P->floor_y) floor_contact(P, u);
+    if (P->floor_on && ijk[1] * dx <= P->floor_y)
+        s->floor_br = floor_contact(P, u, code >= 0 ? (code >> 1) & 3 : -1);
     double xi[3] = {ijk[0] * dx, ijk[1] * dx, ijk[2] * dx};
     for (int j = 0; j < P->n_obstacles; ++j) {
-        double nrm[3];
-        if (obstacle_sdf(P, &P->obst[j], n, xi, nrm) <= 0.0) obstacle_contact(P, &P->obst[j], nrm, u);
+        for (int k = 0; k < 3; ++k) s->ob_in[j][k] = u[k];
+        const int on = obstacle_sdf(P, &P->obst[j], n, xi, s->ob_n[j]) <= 0.0;
+        const int force = code >= 0 ? (code >> (6 + 2 * j)) & 3 : (on ? -1 : 0);
+        s->ob_br[j] = obstacle_contact(P, &P->obst[j], s->ob_n[j], u, force);
     }
     int b = P->wall_cells;
     for (int k = 0; k < P->dim; ++k) {
-        if (ijk[k] < b && u[k] < 0.0) u[k] = 0.0;
-        if (ijk[k] >= P->n_grid - b && u[k] > 0.0) u[k] = 0.0;
+        s->wall[k] = code >= 0 ? (code >> (3 + k)) & 1
+                               : ((ijk[k] < b && u[k] < 0.0) || (ijk[k] >= P->n_grid - b && u[k] > 0.0));
+        if (s->wall[k]) u[k] = 0.0;
     }
-    if (P->clamp_xmax >= 0.0 && ijk[0] * dx <= P->clamp_xmax) u[0] = u[1] = u[2] = 0.0;
-    for (int k = 0; k < 3; ++k) v[k] = u[k];
+    s->clamped = P->clamp_xmax >= 0.0 && ijk[0] * dx <= P->clamp_xmax;
+    if (s->clamped) u[0] = u[1] = u[2] = 0.0;
+    for (int k = 0; k < 3; ++k) s->v[k] = u[k];
+    if (g_record) {
+        int out = 1 | (s->floor_br << 1);
+        for (int k = 0; k < 3; ++k) out |= s->wall[k] << (3 + k);
+        for (int j = 0; j < P->n_obstacles; ++j) out |= s->ob_br[j] << (6 + 2 * j);
+        g_record[slot] = (uint16_t)out;
+    }
+    return 1;
+}
+
+/* Eqs. 16-18 for one node during step n: returns v */
+static void grid_node(const orc_params* P, int g, int n, double m, const double p[3], double v[3])
+{
+    orc_node_bc s;
+    node_bc(P, g, n, m, p, &s);
+    for (int k = 0; k < 3; ++k) v[k] = s.v[k];
 }
 
 void orc_grid(const orc_params* P, int n, const double* m, const double* p, double* v)
@@ -883,49 +977,25 @@ static void grid_node_adj(const orc_params* P, int g, int n, double m, const dou
 {
     pbar[0] = pbar[1] = pbar[2] = 0.0;
     *mbar = 0.0;
-    if (!(m > 0.0)) return;
-    int ijk[3];
-    node_coords(P, g, ijk);
-    double dx = 1.0 / P->n_grid;
-    double c = P->damping;
-    double vh[3], u0[3], u1[3];
-    for (int k = 0; k < 3; ++k) {
-        vh[k] = p[k] / m;
-        u0[k] = (k < P->dim) ? vh[k] + P->dt * (P->gravity[k] - c * vh[k]) : 0.0;
-        u1[k] = u0[k];
-    }
-    int floor_branch = 0;
-    if (P->floor_on && ijk[1] * dx <= P->floor_y) floor_branch = floor_contact(P, u1);
-    /* obstacles in order, keeping each one's input velocity, branch and normal */
-    double xi[3] = {ijk[0] * dx, ijk[1] * dx, ijk[2] * dx};
-    double ob_in[ORC_MAX_OBST][3], ob_n[ORC_MAX_OBST][3];
-    int ob_branch[ORC_MAX_OBST];
-    for (int j = 0; j < P->n_obstacles; ++j) {
-        for (int k = 0; k < 3; ++k) ob_in[j][k] = u1[k];
-        ob_branch[j] = 0;
-        if (obstacle_sdf(P, &P->obst[j], n, xi, ob_n[j]) <= 0.0)
-            ob_branch[j] = obstacle_contact(P, &P->obst[j], ob_n[j], u1);
-    }
+    orc_node_bc s;
+    if (!node_bc(P, g, n, m, p, &s)) return;
     /* reverse order: clamp, walls, obstacles (last first), floor */
     double gb[3] = {vbar[0], vbar[1], vbar[2]};
-    if (P->clamp_xmax >= 0.0 && ijk[0] * dx <= P->clamp_xmax) gb[0] = gb[1] = gb[2] = 0.0;
-    int b = P->wall_cells;
-    for (int k = 0; k < P->dim; ++k) {
-        if (ijk[k] < b && u1[k] < 0.0) gb[k] = 0.0;
-        if (ijk[k] >= P->n_grid - b && u1[k] > 0.0) gb[k] = 0.0;
-    }
+    if (s.clamped) gb[0] = gb[1] = gb[2] = 0.0;
+    for (int k = 0; k < P->dim; ++k)
+        if (s.wall[k]) gb[k] = 0.0;
     for (int j = P->n_obstacles - 1; j >= 0; --j) {
-        if (ob_branch[j] == 1) gb[0] = gb[1] = gb[2] = 0.0;
-        else if (ob_branch[j] == 2) obstacle_slide_adj(P, &P->obst[j], ob_n[j], ob_in[j], gb);
+        if (s.ob_br[j] == 1) gb[0] = gb[1] = gb[2] = 0.0;
+        else if (s.ob_br[j] == 2) obstacle_slide_adj(P, &P->obst[j], s.ob_n[j], s.ob_in[j], gb);
     }
-    if (floor_branch == 1) gb[0] = gb[1] = gb[2] = 0.0;
-    else if (floor_branch == 2) floor_slide_adj(P, u0, gb);
+    if (s.floor_br == 1) gb[0] = gb[1] = gb[2] = 0.0;
+    else if (s.floor_br == 2) floor_slide_adj(P, s.u0, gb);
     if (P->dim == 2) gb[2] = 0.0;
-    double s = 1.0 - c * P->dt;
+    double sc = 1.0 - P->damping * P->dt;
     double vhb[3];
-    for (int k = 0; k < 3; ++k) vhb[k] = s * gb[k];
+    for (int k = 0; k < 3; ++k) vhb[k] = sc * gb[k];
     for (int k = 0; k < 3; ++k) pbar[k] = vhb[k] / m;
-    *mbar = -(vhb[0] * vh[0] + vhb[1] * vh[1] + vhb[2] * vh[2]) / m;
+    *mbar = -(vhb[0] * s.vh[0] + vhb[1] * s.vh[1] + vhb[2] * s.vh[2]) / m;
 }
 
 void orc_grid_adj(const orc_params* P, int n, const double* m, const double* p, const double* vbar,
