@@ -137,25 +137,32 @@ int mpm_mag_create(const mpm_mag_instance_desc* descs, int n_inst, const int64_t
  *   loss_out    [n_inst]  loss of each instance (output, overwritten), or NULL
  *   record      0: plain forward; 1: also keep step checkpoints for backward
  * Inputs are copied; the caller may free them after the call. Returns EDOMAIN,
- * EINVERT or ENONFINITE when the corresponding condition occurred at any step.
+ * EINVERT or ENONFINITE when the corresponding condition occurred: the earliest
+ * one by step (a failure can cause others later, e.g. an inverted F gives a
+ * non-finite stress one step on), and within a step a non-finite value before
+ * det F <= 0 before a stencil outside the grid; mpm_mag_last_error names the
+ * step. Non-finite inputs are ENONFINITE at step 0.
  */
 int mpm_mag_rollout(mpm_mag* h, void* stream, const void* x0, const void* density, const void* br,
                     const void* b_prog, const void* loss_target, const uint8_t* loss_mask,
                     void* x_final, void* loss_out, int record);
 
 /*
- * Reverse-mode gradient of sum_k dloss[k] * loss_k over the last record=1
- * rollout (Sec. 2.3; Eq. 35 when instances share a design): the hand-derived
- * transpose of every step, replayed segment by segment from the checkpoints.
+ * Reverse-mode gradient of sum_k dloss[k] * loss_k + sum_p dx_final_p . x_p(T)
+ * over the last record=1 rollout (Sec. 2.3; Eq. 35 when instances share a
+ * design): the hand-derived transpose of every step, replayed segment by
+ * segment from the checkpoints. The second term lets a caller's own function
+ * g of the final positions (Eq. 34) be differentiated through the rollout.
  *   dloss     [n_inst]      upstream gradient of each instance's loss
+ *   dx_final  [N][dim]      upstream gradient of the final positions, or NULL (zero)
  *   g_density [N]           d/d density   (output, overwritten), or NULL
  *   g_br      [N][dim]      d/d br        (output, overwritten), or NULL
  *   g_b_prog  [S_tot][dim]  d/d b_prog    (output, overwritten), or NULL
- * Gradients are in the caller's particle order. Returns ESTATE without a
- * recorded rollout.
+ * dx_final and the gradients are in the caller's particle order. Returns
+ * ESTATE without a recorded rollout.
  */
-int mpm_mag_backward(mpm_mag* h, void* stream, const void* dloss, void* g_density, void* g_br,
-                     void* g_b_prog);
+int mpm_mag_backward(mpm_mag* h, void* stream, const void* dloss, const void* dx_final, void* g_density,
+                     void* g_br, void* g_b_prog);
 
 /* Release every device buffer and the handle. NULL is accepted. */
 void mpm_mag_destroy(mpm_mag* h);
@@ -225,6 +232,28 @@ int mpm_mag_kernel_flops(mpm_mag* h, int kernel, double* flops);
 
 /* Device bytes currently held by the handle (state, grids, checkpoints). */
 int64_t mpm_mag_device_bytes(const mpm_mag* h);
+
+/*
+ * Branch trace (instrumentation for parity checks). The grid operation of
+ * Eqs. 16-18 takes integer decisions from floating-point node velocities:
+ * whether the node has mass, which branch of Eq. 18 the floor and each
+ * obstacle take, and which velocity components the domain walls zero. A
+ * reference computed in another precision may decide a near-tie the other
+ * way; to compare the arithmetic on equal branches it can replay these.
+ * With a trace set, every forward step of the following rollouts writes one
+ * code per grid node to trace[n * T_nodes + node_off_k + node], where T_nodes =
+ * mpm_mag_trace_nodes(h) (the sum of the instances' n_grid^dim), node_off_k the
+ * sum over the instances before k, and node = i + n_grid (j + n_grid l). Codes:
+ *   bit 0      the node has mass
+ *   bits 1-2   floor branch: 0 untouched, 1 velocity zeroed, 2 sliding
+ *   bits 3-5   the walls zero the x, y, z component
+ *   bits 6+2j  obstacle j: 0 untouched, 1 set to v_b, 2 sliding
+ * Nodes outside the step's active blocks read 0. The rollout clears the trace
+ * first. trace: a caller-owned DEVICE buffer of at least n_steps * T_nodes
+ * uint16 (EINVAL if smaller), kept until the trace is reset with NULL.
+ */
+int mpm_mag_set_branch_trace(mpm_mag* h, uint16_t* trace, int64_t elems);
+int64_t mpm_mag_trace_nodes(const mpm_mag* h);
 
 #ifdef __cplusplus
 }

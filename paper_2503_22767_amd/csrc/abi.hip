@@ -74,11 +74,12 @@ int mpm_mag_rollout(mpm_mag* h, void* stream, const void* x0, const void* densit
     }
 }
 
-int mpm_mag_backward(mpm_mag* h, void* stream, const void* dloss, void* g_density, void* g_br, void* g_b_prog)
+int mpm_mag_backward(mpm_mag* h, void* stream, const void* dloss, const void* dx_final, void* g_density,
+                     void* g_br, void* g_b_prog)
 {
     if (!h) return MPM_MAG_EINVAL;
     try {
-        return record(h, h->eng->backward((hipStream_t)stream, dloss, g_density, g_br, g_b_prog));
+        return record(h, h->eng->backward((hipStream_t)stream, dloss, dx_final, g_density, g_br, g_b_prog));
     } catch (...) {
         h->last = "unexpected host exception";
         return MPM_MAG_ENOMEM;
@@ -136,5 +137,13 @@ int mpm_mag_kernel_stats(mpm_mag* h, int kernel, int64_t* launches, double* tota
 }
 
 int64_t mpm_mag_device_bytes(const mpm_mag* h) { return h ? h->eng->device_bytes() : 0; }
+
+int mpm_mag_set_branch_trace(mpm_mag* h, uint16_t* trace, int64_t elems)
+{
+    if (!h) return MPM_MAG_EINVAL;
+    return record(h, h->eng->set_trace(trace, elems));
+}
+
+int64_t mpm_mag_trace_nodes(const mpm_mag* h) { return h ? h->eng->trace_nodes() : 0; }
 
 }  // extern "C"

@@ -19,6 +19,20 @@ constexpr int kErrDomain = 1;
 constexpr int kErrInvert = 2;
 constexpr int kErrNonFinite = 4;
 
+// The error word of a call keeps its earliest failure, as the key
+// (2 n + phase) * 4 + rank: phase 0 is step n's input (the stencils of the
+// state it starts from), phase 1 its G2P output (the new state); rank 0 a
+// non-finite value, 1 det F <= 0, 2 a stencil outside the grid. A key of all
+// ones means no failure. (After a first failure later steps can fail as its
+// consequence, e.g. an inverted F gives a non-finite stress one step later; the
+// earliest one is the cause reported.)
+constexpr unsigned long long kNoError = ~0ull;
+__device__ __forceinline__ void report_error(unsigned long long* word, int step, int phase, int flags)
+{
+    const unsigned long long rank = (flags & kErrNonFinite) ? 0ull : ((flags & kErrInvert) ? 1ull : 2ull);
+    atomicMin(word, ((unsigned long long)(2 * step + phase) << 2) | rank);
+}
+
 enum LossKind { kFinalMse = 0, kComDisp = 1, kTrajVel = 2, kTipDisp = 3 };
 
 // per-instance loss accumulators (double)
@@ -32,7 +46,8 @@ struct InstDev {
     int seg_off, n_seg, seg_steps, periodic;
     int floor_on, wall_cells, loss_kind, clamp_on;
     int floor_noslip, floor_jmax, clamp_imax, chunk_off;
-    int n_particles, cb_off, nb, pad_;   // first coarse block, coarse blocks per axis
+    int n_particles, cb_off, nb;         // first coarse block, coarse blocks per axis
+    int trace_off;                       // first node of the instance in a branch trace step
     real dx, inv_dx, dt, kappa_vol;      // kappa_vol = 4 dt / dx^2 * V
     real lam;                            // 4 / dx^2
     real G, K, mass_p;                   // mass_p = rho V (m = phi mass_p)

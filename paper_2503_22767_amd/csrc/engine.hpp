@@ -43,9 +43,12 @@ public:
     virtual ~EngineBase() = default;
     virtual int rollout(hipStream_t s, const void* x0, const void* density, const void* br, const void* b_prog,
                         const void* target, const uint8_t* mask, void* x_final, void* loss_out, int record) = 0;
-    virtual int backward(hipStream_t s, const void* dloss, void* g_density, void* g_br, void* g_b_prog) = 0;
+    virtual int backward(hipStream_t s, const void* dloss, const void* dx_final, void* g_density, void* g_br,
+                         void* g_b_prog) = 0;
     virtual int set_option(const char* key, int64_t value) = 0;
     virtual int64_t device_bytes() const = 0;
+    virtual int set_trace(uint16_t* trace, int64_t elems) = 0;
+    virtual int64_t trace_nodes() const = 0;
     int kernel_stats(int k, int64_t* launches, double* ms, double* bytes)
     {
         if (k == -1) {
@@ -133,6 +136,8 @@ public:
             I.n_particles = (int)np[k];
             I.nb = (d.n_grid + Coarse<D>::edge - 1) / Coarse<D>::edge;
             I.cb_off = (int)n_cb_;
+            I.trace_off = (int)trace_nodes_;
+            trace_nodes_ += I.n_nodes;
             const int ncb = D == 2 ? I.nb * I.nb : I.nb * I.nb * I.nb;
             for (int b = 0; b < ncb; ++b) cb_inst_h_.push_back(k);
             n_cb_ += ncb;
@@ -315,6 +320,18 @@ public:
 
     int64_t device_bytes() const override { return bytes_; }
 
+    // Branch trace: the forward steps of the following rollouts write every
+    // node's grid-update decisions to trace[n][node] (see mpm_mag.h).
+    int set_trace(uint16_t* trace, int64_t elems) override
+    {
+        if (trace && elems < (int64_t)std::max(1, T_) * trace_nodes_)
+            return fail(MPM_MAG_EINVAL, "branch trace smaller than n_steps x trace nodes");
+        trace_ = trace;
+        ++plan_gen_;   // the pointer is baked into captured launches
+        return MPM_MAG_OK;
+    }
+    int64_t trace_nodes() const override { return trace_nodes_; }
+
     // --------------------------------------------------------------- rollout
     int rollout(hipStream_t s, const void* x0, const void* density, const void* br, const void* b_prog,
                 const void* target, const uint8_t* mask, void* x_final, void* loss_out, int record) override
@@ -332,13 +349,14 @@ public:
             st = ensure_store();
             if (st) return st;
         }
-        MPM_HIP(hipMemsetAsync(err_d_, 0, sizeof(int), s));
+        MPM_HIP(hipMemsetAsync(err_d_, 0xff, sizeof(*err_d_), s));   // kNoError
         MPM_HIP(hipMemsetAsync(acc_, 0, sizeof(double) * kAccCount * n_inst_, s));
         MPM_HIP(hipMemsetAsync(gm_, 0, sizeof(real) * 4 * G_, s));
         MPM_HIP(hipMemsetAsync(reg_count_, 0, sizeof(int) * n_cb_, s));
         MPM_HIP(hipMemsetAsync(fb_used_, 0, sizeof(int) * n_cb_, s));
         MPM_HIP(hipMemsetAsync(active_, 0, sizeof(int) * 4 * kMaxChains, s));
         MPM_HIP(hipMemcpyAsync(bprog_, b_prog, sizeof(real) * S_tot_ * D, hipMemcpyDeviceToDevice, s));
+        if (trace_) MPM_HIP(hipMemsetAsync(trace_, 0, sizeof(uint16_t) * (size_t)T_ * trace_nodes_, s));
         int st = sort_and_gather(s, (const real*)x0, (const real*)density, (const real*)br, (const real*)target, mask);
         if (st) return st;
         auto steps = [&](hipStream_t cs) -> int {
@@ -387,18 +405,20 @@ public:
     }
 
     // -------------------------------------------------------------- backward
-    int backward(hipStream_t s, const void* dloss, void* g_density, void* g_br, void* g_b_prog) override
+    int backward(hipStream_t s, const void* dloss, const void* dx_final, void* g_density, void* g_br,
+                 void* g_b_prog) override
     {
         err.clear();
         if (!recorded_) return fail(MPM_MAG_ESTATE, "backward needs a successful record=1 rollout");
         if (!dloss) return fail(MPM_MAG_EINVAL, "dloss is required");
-        MPM_HIP(hipMemsetAsync(err_d_, 0, sizeof(int), s));
+        MPM_HIP(hipMemsetAsync(err_d_, 0xff, sizeof(*err_d_), s));   // kNoError
         MPM_HIP(hipMemsetAsync(gB_, 0, sizeof(double) * S_tot_ * D, s));
         MPM_HIP(hipMemcpyAsync(dloss_, dloss, sizeof(real) * n_inst_, hipMemcpyDeviceToDevice, s));
         MPM_HIP(hipMemsetAsync(active_, 0, sizeof(int) * 4 * kMaxChains, s));
         Args<real> a = args();
         int st = launch(K_SEED, s, n_chunks_, kBlock, k_seed<real, D>, a, (const real*)st_, adj_,
-                        (const real*)x0s_, (const real*)tgt_, (const uint8_t*)mask_, (const real*)dloss_);
+                        (const real*)x0s_, (const real*)tgt_, (const uint8_t*)mask_, (const real*)dloss_,
+                        (const int*)id_, (const real*)dx_final);
         if (st) return st;
         auto sweep = [&](hipStream_t cs) -> int {
             int r = fork(cs);
@@ -588,6 +608,7 @@ private:
     int fwd_step(int q, hipStream_t cs, int n, bool record)
     {
         Args<real> a = args_of(q);
+        a.trace = trace_;
         const int nc = chains_[q].nc;
         int r;
         if (n % lane_every() == 0) {
@@ -769,6 +790,8 @@ private:
         a.box_cap = box_cap_;
         a.chunk_base = 0;
         a.lperm = lperm_;
+        a.trace = nullptr;
+        a.trace_nodes = trace_nodes_;
         return a;
     }
 
@@ -975,7 +998,7 @@ private:
 
     int finish(hipStream_t s)
     {
-        MPM_HIP(hipMemcpyAsync(err_h_, err_d_, sizeof(int), hipMemcpyDeviceToHost, s));
+        MPM_HIP(hipMemcpyAsync(err_h_, err_d_, sizeof(*err_d_), hipMemcpyDeviceToHost, s));
         MPM_HIP(hipStreamSynchronize(s));
         if (timing_) {
             for (auto& p : pending_) {
@@ -986,10 +1009,15 @@ private:
         }
         pending_.clear();
         ev_used_ = 0;
-        int e = *err_h_;
-        if (e & kErrNonFinite) return fail(MPM_MAG_ENONFINITE, "non-finite particle state");
-        if (e & kErrInvert) return fail(MPM_MAG_EINVERT, "det F <= 0");
-        if (e & kErrDomain) return fail(MPM_MAG_EDOMAIN, "a particle stencil left the grid");
+        const unsigned long long e = *err_h_;
+        if (e != kNoError) {
+            // the earliest failure (report_error)
+            const int step = (int)((e >> 2) / 2), rank = (int)(e & 3);
+            const std::string at = " (first at step " + std::to_string(step) + ")";
+            if (rank == 0) return fail(MPM_MAG_ENONFINITE, "non-finite particle state" + at);
+            if (rank == 1) return fail(MPM_MAG_EINVERT, "det F <= 0" + at);
+            return fail(MPM_MAG_EDOMAIN, "a particle stencil left the grid" + at);
+        }
         return MPM_MAG_OK;
     }
 
@@ -1209,7 +1237,7 @@ private:
         }
         st |= dalloc(&hist_, (size_t)256 * sort_blocks_);
         if (st) return fail(MPM_MAG_ENOMEM, "device allocation failed");
-        if (hipHostMalloc((void**)&err_h_, sizeof(int)) != hipSuccess) return fail(MPM_MAG_ENOMEM, "pinned error word");
+        if (hipHostMalloc((void**)&err_h_, sizeof(*err_h_)) != hipSuccess) return fail(MPM_MAG_ENOMEM, "pinned error word");
         MPM_HIP(hipMemcpy(inst_d_, inst_h_.data(), sizeof(InstDev<real>) * inst_h_.size(), hipMemcpyHostToDevice));
         MPM_HIP(hipMemcpy(chunks_d_, chunks_h_.data(), sizeof(ChunkDev) * chunks_h_.size(), hipMemcpyHostToDevice));
         MPM_HIP(hipMemcpy(gblock_d_, gblock_h_.data(), sizeof(int) * gblock_h_.size(), hipMemcpyHostToDevice));
@@ -1323,10 +1351,12 @@ private:
     size_t gstash_bytes_ = 0;
     std::vector<int> cb_inst_h_;
     int64_t n_cb_ = 0;
+    int64_t trace_nodes_ = 0;       // sum of the instances' node counts
+    uint16_t* trace_ = nullptr;     // caller's branch trace, or nullptr
     double *gB_ = nullptr, *acc_ = nullptr, *loss_val_ = nullptr;
     real* dloss_ = nullptr;   // copy of the upstream loss gradient (stable address for graphs)
-    int* err_d_ = nullptr;
-    int* err_h_ = nullptr;
+    unsigned long long* err_d_ = nullptr;   // earliest failure of the call (report_error)
+    unsigned long long* err_h_ = nullptr;
     uint32_t* keys_[2] = {nullptr, nullptr};
     uint32_t* vals_[2] = {nullptr, nullptr};
     uint32_t* hist_ = nullptr;

@@ -74,7 +74,7 @@ struct Args {
     real* gm;            // [4 G] momentum / mass
     real* gv;            // [4 G] velocity after the grid operation
     real* gbar;          // [4 G] adjoint grid values
-    int* err;            // device error word
+    unsigned long long* err;   // device error word (earliest failure; report_error)
     double* acc;         // [n_inst][kAccCount]
     double* loss_val;    // [n_inst]
     double* gB;          // [S_tot][D] field-program gradient
@@ -95,6 +95,8 @@ struct Args {
     int chunk_base;      // first chunk of the launch (launches may cover a range of instances)
     int box_cap;         // largest block staging box (nodes, <= kBoxCap)
     const uint8_t* lperm;  // [nalloc]: lane t of chunk c works on slot c * kBlock + lperm[c * kBlock + t]
+    uint16_t* trace;       // [n_steps][trace_nodes] branch decisions of the grid update, or nullptr
+    int64_t trace_nodes;   // nodes of all instances (sum of n_grid^D)
 };
 
 // Grid store: the recorded forward keeps each step's active coarse blocks
@@ -972,7 +974,7 @@ __device__ __forceinline__ void p2g_scatter(const Args<real>& a, const InstDev<r
     chunk_origin(a.corig, a.chunk_base + blockIdx.x, org);
     Stencil<real, D> Sx;
     int err = make_stencil<real, D>(q.x, org, I.inv_dx, I.n_grid, Sx);
-    if (active && err) atomicOr(a.err, err);
+    if (active && err) report_error(a.err, step, 0, err);
     P2GTerms<real, D> T;
     p2g_terms<real, D>(I, q, phi, br, B, T);
     real mv[D];
@@ -1284,7 +1286,7 @@ __device__ __forceinline__ void obstacle_slide_adj(const InstDev<real>& I, int j
 template <typename real, int D>
 __device__ __forceinline__ int node_velocity(const InstDev<real>& I, const int ijk[D], real m, const real p[D],
                                              real vh[D], real u0[D], real u1[D], real v[D], int wallz[D],
-                                             bool& clamped, real t, ObstTrace<real, D>* tr)
+                                             bool& clamped, real t, ObstTrace<real, D>* tr, int* ocode = nullptr)
 {
     const real rm = real(1) / m;
 #pragma unroll
@@ -1328,6 +1330,7 @@ __device__ __forceinline__ int node_velocity(const InstDev<real>& I, const int i
 #pragma unroll
                 for (int k = 0; k < D; ++k) tr->in[j][k] = v[k];
             if (obstacle_sdf<real, D>(I, j, xi, t, nrm) <= real(0)) ob = obstacle_contact<real, D>(I, j, nrm, v);
+            if (ocode) *ocode |= ob << (6 + 2 * j);
             if (tr) {
                 tr->br[j] = ob;
 #pragma unroll
@@ -1380,6 +1383,7 @@ void k_grid(Args<real> a, real* gv_out, real* gmd_out, int list, GridStore<real>
     if (keep && threadIdx.x == 0) gs.blk[sbase + ai] = b;
     gather_coarse<real, D>(a, I, b, a.gm, [&](int64_t g, const int g3[3], int ln, const real node[4]) {
         real v[D];
+        int code = 0;   // branch decisions (the layout of mpm_mag_set_branch_trace)
         if (node[3] > real(0)) {
             int ijk[D];
 #pragma unroll
@@ -1387,12 +1391,17 @@ void k_grid(Args<real> a, real* gv_out, real* gmd_out, int list, GridStore<real>
             real vh[D], u0[D], u1[D];
             int wz[D];
             bool cl;
-            node_velocity<real, D>(I, ijk, node[3], node, vh, u0, u1, v, wz, cl, (real)gs.step * I.dt,
-                                   (ObstTrace<real, D>*)nullptr);
+            const int br = node_velocity<real, D>(I, ijk, node[3], node, vh, u0, u1, v, wz, cl,
+                                                  (real)gs.step * I.dt, (ObstTrace<real, D>*)nullptr,
+                                                  a.trace ? &code : (int*)nullptr);
+            code |= 1 | (br << 1);
+#pragma unroll
+            for (int k = 0; k < D; ++k) code |= wz[k] << (3 + k);
         } else {
 #pragma unroll
             for (int k = 0; k < D; ++k) v[k] = real(0);
         }
+        if (a.trace) a.trace[(int64_t)gs.step * a.trace_nodes + I.trace_off + (g - I.grid_off)] = (uint16_t)code;
 #pragma unroll
         for (int k = 0; k < D; ++k) gv_out[4 * g + k] = v[k];
         if (gmd_out)
@@ -1621,7 +1630,7 @@ __global__ __launch_bounds__(kBlock, 6) void k_g2p(Args<real> a, const real* __r
             err = g2p_from_nodes<real, D>(a, I, i, Sx, gv + 4 * node_index<real, D>(Sx.base, kZero3, n), 4 * n,
                                           4 * n * n, F, u, org, q, x1);
         }
-        if (err) atomicOr(a.err, err);
+        if (err) report_error(a.err, step, 1, err);
         stream_particle<real, D>(sout, a.nalloc, i, q);
     }
     if (traj_on && I.loss_kind == kTrajVel) traj_accumulate<real, D>(a, I, ch.inst, active, i, q);
@@ -1650,7 +1659,7 @@ __global__ __launch_bounds__(kBlock, 6) void k_g2p2g(Args<real> a, const real* _
         chunk_origin(a.corig, a.chunk_base + blockIdx.x, org);
         real x1[D];
         const int err = g2p_update<real, D>(a, I, i, gv_in, sin, org, q, x1);
-        if (err) atomicOr(a.err, err);
+        if (err) report_error(a.err, step, 1, err);
 #pragma unroll
         for (int r = 0; r < D; ++r) {
             sout[(Cp::X + r) * S + i] = q.x[r];
@@ -1744,7 +1753,8 @@ __global__ void k_loss_finalize(Args<real> a, int n_inst, real* loss_out)
 
 template <typename real, int D>
 __global__ __launch_bounds__(kBlock) void k_seed(Args<real> a, const real* st, real* adj, const real* x0s,
-                                                 const real* target, const uint8_t* mask, const real* dloss)
+                                                 const real* target, const uint8_t* mask, const real* dloss,
+                                                 const int* __restrict__ id, const real* __restrict__ dx_final)
 {
     using Cp = Comp<D>;
     const ChunkDev ch = a.chunks[a.chunk_base + blockIdx.x];
@@ -1773,6 +1783,8 @@ __global__ __launch_bounds__(kBlock) void k_seed(Args<real> a, const real* st, r
         case kComDisp: s = -dl * m * e / M; break;
         default: s = 0.0; break;
         }
+        // an upstream gradient on the final positions (the caller's order)
+        if (dx_final) s += (double)dx_final[(int64_t)id[i] * D + k];
         xb[k] = (real)s;
     }
     if (I.loss_kind == kComDisp || I.loss_kind == kTrajVel)
@@ -2381,7 +2393,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(Args<real> a, const int* __re
     // inputs must be finite: a NaN mass would otherwise read as an empty node
     if (blockIdx.x == 0)
         for (int64_t j = t; j < n_prog; j += kBlock)
-            if (!rfinite(a.bprog[j])) atomicOr(a.err, kErrNonFinite);
+            if (!rfinite(a.bprog[j])) report_error(a.err, 0, 0, kErrNonFinite);
     if (!active) return;
     {
         bool fin = rfinite(phi_in[q]);
@@ -2390,7 +2402,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(Args<real> a, const int* __re
             fin = fin && isfinite(xa[k]) && rfinite(br_in[(int64_t)q * D + k]);
             if (tgt_in) fin = fin && rfinite(tgt_in[(int64_t)q * D + k]);
         }
-        if (!fin) atomicOr(a.err, kErrNonFinite);
+        if (!fin) report_error(a.err, 0, 0, kErrNonFinite);
     }
     id[i] = q;
 #pragma unroll

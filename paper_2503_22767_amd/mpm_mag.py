@@ -107,7 +107,7 @@ def lib():
     L.mpm_mag_create.restype = C.c_int
     L.mpm_mag_rollout.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int]
     L.mpm_mag_rollout.restype = C.c_int
-    L.mpm_mag_backward.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.mpm_mag_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.mpm_mag_backward.restype = C.c_int
     L.mpm_mag_destroy.argtypes = [vp]
     L.mpm_mag_destroy.restype = None
@@ -127,6 +127,10 @@ def lib():
     L.mpm_mag_kernel_flops.restype = C.c_int
     L.mpm_mag_device_bytes.argtypes = [vp]
     L.mpm_mag_device_bytes.restype = i64
+    L.mpm_mag_set_branch_trace.argtypes = [vp, vp, i64]
+    L.mpm_mag_set_branch_trace.restype = C.c_int
+    L.mpm_mag_trace_nodes.argtypes = [vp]
+    L.mpm_mag_trace_nodes.restype = i64
     _lib = L
     return L
 
@@ -207,13 +211,17 @@ class MpmMag:
         self._check(st, "mpm_mag_rollout")
         return loss, x_final
 
-    def backward(self, dloss, want=(True, True, True)):
+    def backward(self, dloss, want=(True, True, True), dx_final=None):
+        """Gradients (density, br, b_prog) of sum_k dloss[k] loss_k plus, when
+        dx_final [N, dim] is given, of sum_p dx_final_p . x_p(T)."""
         dloss = self._arg(dloss, (self.n_inst,), name="dloss")
+        dx_final = self._arg(dx_final, (self.N, self.dim), name="dx_final")
         gd = torch.empty(self.N, dtype=self.dtype, device=self.device) if want[0] else None
         gb = torch.empty((self.N, self.dim), dtype=self.dtype, device=self.device) if want[1] else None
         gp = torch.empty((self.S_tot, self.dim), dtype=self.dtype, device=self.device) if want[2] else None
         with torch.cuda.device(self.device):
-            st = lib().mpm_mag_backward(self._h, self._stream(), _ptr(dloss), _ptr(gd), _ptr(gb), _ptr(gp))
+            st = lib().mpm_mag_backward(self._h, self._stream(), _ptr(dloss), _ptr(dx_final), _ptr(gd), _ptr(gb),
+                                        _ptr(gp))
         self._check(st, "mpm_mag_backward")
         return gd, gb, gp
 
@@ -234,6 +242,23 @@ class MpmMag:
 
     def device_bytes(self) -> int:
         return int(lib().mpm_mag_device_bytes(self._h))
+
+    def trace_nodes(self) -> int:
+        return int(lib().mpm_mag_trace_nodes(self._h))
+
+    def set_branch_trace(self, trace: Optional[torch.Tensor]):
+        """Record the grid update's per-node branch decisions of the following
+        rollouts' forward steps into `trace` (a device int16/uint16 tensor with
+        n_steps * trace_nodes() elements), or stop with None."""
+        if trace is not None:
+            if trace.device.type != "cuda" or trace.element_size() != 2 or not trace.is_contiguous():
+                raise ValueError("branch trace: a contiguous 16-bit device tensor")
+            self._trace = trace
+            n = trace.numel()
+        else:
+            self._trace = None
+            n = 0
+        self._check(lib().mpm_mag_set_branch_trace(self._h, _ptr(trace), int(n)), "mpm_mag_set_branch_trace")
 
     def print_kernel_stats(self, file=None):
         """Per-kernel launches, time and rates since the last reset."""
@@ -266,21 +291,24 @@ class MpmMagFn(torch.autograd.Function):
     """loss[n_inst], x_final = MpmMagFn.apply(sim, x0, density, br, b_prog, target, mask).
 
     Backward returns the gradient with respect to density, br and b_prog,
-    computed by mpm_mag_backward over the recorded rollout. The final positions
-    are returned for inspection only (no gradient flows through them)."""
+    computed by mpm_mag_backward over the recorded rollout, of the losses and of
+    any function of the final positions the caller builds on x_final (its
+    gradient goes in as mpm_mag_backward's dx_final seed)."""
 
     @staticmethod
     def forward(ctx, sim: MpmMag, x0, density, br, b_prog, target=None, mask=None):
         loss, x_final = sim.rollout(x0, density, br, b_prog, target, mask, record=True)
         ctx.sim = sim
-        ctx.mark_non_differentiable(x_final)
+        ctx.set_materialize_grads(False)   # an unused output's gradient arrives as None
         return loss, x_final
 
     @staticmethod
     def backward(ctx, dloss, dx_final):
         sim = ctx.sim
         need = ctx.needs_input_grad
-        gd, gb, gp = sim.backward(dloss, want=(need[2], need[3], need[4]))
+        if dloss is None:
+            dloss = torch.zeros(sim.n_inst, dtype=sim.dtype, device=sim.device)
+        gd, gb, gp = sim.backward(dloss, want=(need[2], need[3], need[4]), dx_final=dx_final)
         return None, None, gd, gb, gp, None, None
 
 

@@ -2,6 +2,7 @@
 C ABI and through the FP64 oracle on the same seeded arrays, and compare with
 the parity metrics (positions: max abs error; gradients: norm-wise relative)."""
 import sys
+import time
 
 import numpy as np
 import torch
@@ -15,15 +16,31 @@ def log(*a):
     sys.stdout.flush()
 
 
-def gpu_run(instances, precision, record=True, backward=True, options=None, dloss=None):
+def gpu_run(instances, precision, record=True, backward=True, options=None, dloss=None, trace=False):
+    """Rollout (and gradient) through the C ABI. With trace, out["trace"] holds
+    the grid update's branch decisions per instance, [n_steps, n_nodes] each."""
     dtype = torch.float32 if precision == 4 else torch.float64
     sim = M.MpmMag([i.params for i in instances], [i.n for i in instances], precision=precision)
     try:
         for k, v in (options or {}).items():
             sim.set_option(k, v)
+        T = instances[0].params["n_steps"]
+        tr = None
+        if trace:
+            tr = torch.zeros(T * sim.trace_nodes(), dtype=torch.int16, device="cuda")
+            sim.set_branch_trace(tr)
         x0, density, br, b_prog, target, mask = M.instance_tensors(instances, dtype=dtype)
         loss, x = sim.rollout(x0, density, br, b_prog, target, mask, record=record)
         out = dict(loss=loss.double().cpu().numpy(), x=x.double().cpu().numpy())
+        if trace:
+            full = tr.cpu().numpy().view(np.uint16).reshape(T, sim.trace_nodes())
+            sim.set_branch_trace(None)
+            del tr
+            out["trace"], off = [], 0
+            for i in instances:
+                n = i.params["n_grid"] ** i.params["dim"]
+                out["trace"].append(np.ascontiguousarray(full[:, off:off + n]))
+                off += n
         if backward:
             dl = torch.ones(len(instances), dtype=dtype, device="cuda") if dloss is None else \
                 torch.as_tensor(dloss, dtype=dtype, device="cuda")
@@ -36,18 +53,38 @@ def gpu_run(instances, precision, record=True, backward=True, options=None, dlos
         sim.close()
 
 
-def oracle_run(instances, backward=True, ckpt_every=None):
-    xs, losses, gds, gbs, gps = [], [], [], [], []
-    for inst in instances:
+def oracle_run(instances, backward=True, ckpt_every=None, verbose=None, replay=None, record=False):
+    """The oracle's rollout (and gradient) of each instance. With verbose (by
+    default for runs of more than 1e8 particle-steps) each finished call is
+    logged, so a long reference run shows progress. replay: per-instance
+    branch tables for the oracle to follow (a device run's trace); record: keep
+    the oracle's own decisions in out["trace"]."""
+    if verbose is None:
+        verbose = sum(i.n * i.params["n_steps"] for i in instances) > 1e8
+    xs, losses, gds, gbs, gps, traces, mism = [], [], [], [], [], [], 0
+    for j, inst in enumerate(instances):
         p = inst.params
-        r = orc.rollout(p, inst.x0, inst.density, inst.br, inst.b_prog, inst.target, inst.mask)
+        t0 = time.time()
+        with orc.branch_trace(p, replay=None if replay is None else replay[j], record=record) as rec:
+            r = orc.rollout(p, inst.x0, inst.density, inst.br, inst.b_prog, inst.target, inst.mask)
+            mism += orc.branch_mass_mismatches()
+        traces.append(rec)
         xs.append(r["x"][:, :p["dim"]])
         losses.append(r["loss"])
+        if verbose:
+            log(f"  oracle instance {j}: rollout of {inst.n} particles x {p['n_steps']} steps "
+                f"in {time.time() - t0:.1f} s")
         if backward:
-            g = orc.backward(p, inst.x0, inst.density, inst.br, inst.b_prog, inst.target, inst.mask,
-                             ckpt_every=ckpt_every or max(1, int(np.sqrt(max(1, p["n_steps"])))))
+            t0 = time.time()
+            with orc.branch_trace(p, replay=None if replay is None else replay[j]):
+                g = orc.backward(p, inst.x0, inst.density, inst.br, inst.b_prog, inst.target, inst.mask,
+                                 ckpt_every=ckpt_every or max(1, int(np.sqrt(max(1, p["n_steps"])))))
             gds.append(g["g_density"]); gbs.append(g["g_br"]); gps.append(g["g_b_prog"])
-    out = dict(x=np.concatenate(xs), loss=np.array(losses))
+            if verbose:
+                log(f"  oracle instance {j}: gradient in {time.time() - t0:.1f} s")
+    out = dict(x=np.concatenate(xs), loss=np.array(losses), mass_mismatch=mism)
+    if record:
+        out["trace"] = traces
     if backward:
         out.update(g_density=np.concatenate(gds), g_br=np.concatenate(gbs), g_b_prog=np.concatenate(gps))
     return out
@@ -60,6 +97,18 @@ def rel_norm(a, b):
     return np.linalg.norm(a - b) / den if den > 0 else np.linalg.norm(a - b)
 
 
+def p99(a, b):
+    """99th percentile over elements of |a - b| / (|b| + 1e-3 rms(b)): the
+    element-wise companion of the norm-wise gradient metric (the floor keeps
+    elements near zero from dominating)."""
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    if b.size == 0:
+        return 0.0
+    floor = 1e-3 * np.sqrt(np.mean(b * b)) + 1e-300
+    return float(np.percentile(np.abs(a - b) / (np.abs(b) + floor), 99.0))
+
+
 def compare(gpu, ref, pos_tol, grad_tol, loss_tol=None, label=""):
     errs = dict(x=float(np.max(np.abs(gpu["x"] - ref["x"]))))
     if loss_tol is not None:
@@ -67,7 +116,8 @@ def compare(gpu, ref, pos_tol, grad_tol, loss_tol=None, label=""):
     for k in ("g_density", "g_br", "g_b_prog"):
         if k in gpu and k in ref:
             errs[k] = float(rel_norm(gpu[k], ref[k]))
-    log(label, {k: f"{v:.3e}" for k, v in errs.items()})
+    p = {k + "_p99": p99(gpu[k], ref[k]) for k in ("g_density", "g_br", "g_b_prog") if k in gpu and k in ref}
+    log(label, {k: f"{v:.3e}" for k, v in errs.items()}, "element-wise", {k: f"{v:.2e}" for k, v in p.items()})
     assert errs["x"] <= pos_tol, (label, errs)
     if loss_tol is not None:
         assert errs["loss"] <= loss_tol, (label, errs)
@@ -75,3 +125,20 @@ def compare(gpu, ref, pos_tol, grad_tol, loss_tol=None, label=""):
         if k in errs:
             assert errs[k] <= grad_tol, (label, k, errs)
     return errs
+
+
+def branch_flips(dev_traces, ref_traces):
+    """Per instance: grid nodes and steps whose branch decisions differ between
+    two runs (device trace, oracle record)."""
+    return [int(np.count_nonzero(a != b)) for a, b in zip(dev_traces, ref_traces)]
+
+
+def compare_on_device_branches(got, raw, replayed, pos_tol, grad_tol, label):
+    """FP32 parity: the device against the oracle replaying the device's branch
+    decisions (asserted); the device against the oracle deciding on its own,
+    with the number of decisions taken differently (logged)."""
+    flips = branch_flips(got["trace"], raw["trace"])
+    errs_raw = {k: f"{rel_norm(got[k], raw[k]):.3e}" for k in ("g_density", "g_br", "g_b_prog") if k in got}
+    log(label, "branch decisions differing from the FP64 oracle's:", flips, "gradients vs the unreplayed oracle:",
+        errs_raw, "replayed 'has mass' at massless oracle nodes:", replayed.get("mass_mismatch", 0))
+    return compare(got, replayed, pos_tol=pos_tol, grad_tol=grad_tol, label=label + " (on the device's branches)")

@@ -68,5 +68,7 @@ def test_create_rejects_bad_arguments_without_touching_the_device():
     descs[0].n_steps = -1
     assert L.mpm_mag_create(descs, 1, counts, 4, ctypes.byref(h)) == M.EINVAL  # negative step count
     assert L.mpm_mag_rollout(None, None, None, None, None, None, None, None, None, None, 0) == M.EINVAL
-    assert L.mpm_mag_backward(None, None, None, None, None, None) == M.EINVAL
+    assert L.mpm_mag_backward(None, None, None, None, None, None, None) == M.EINVAL
+    assert L.mpm_mag_set_branch_trace(None, None, 0) == M.EINVAL
+    assert L.mpm_mag_trace_nodes(None) == 0
     L.mpm_mag_destroy(None)

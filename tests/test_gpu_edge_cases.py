@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle as orc
 from paper_2503_22767_amd import mpm_mag as M
 from paper_2503_22767_amd import workloads as W
 
@@ -86,15 +87,39 @@ def test_particle_outside_the_grid_reports_edomain(dim):
         assert st == M.EDOMAIN, st
 
 
-def test_nonfinite_design_value_reports_an_error():
+@pytest.mark.parametrize("what", ["density", "br", "b_prog", "x0"])
+def test_nonfinite_input_reports_enonfinite(what):
+    """The rollout checks its inputs as it takes them: a NaN design value,
+    remanence, field value or position is ENONFINITE, in both precisions."""
     inst = _block(3, 4, floor=False)
-    dens = inst.density.copy()
-    dens[5] = np.nan
-    bad = W.Instance(dict(inst.params), inst.x0, dens, inst.br, inst.b_prog, inst.target, inst.mask)
+    arrs = dict(x0=inst.x0.copy(), density=inst.density.copy(), br=inst.br.copy(), b_prog=inst.b_prog.copy())
+    a = arrs[what]
+    a.reshape(-1)[min(5, a.size - 1)] = np.nan
+    bad = W.Instance(dict(inst.params), arrs["x0"], arrs["density"], arrs["br"], arrs["b_prog"], inst.target,
+                     inst.mask)
     for prec in (8, 4):
         st = _status_of(lambda: gpu_run([bad], precision=prec, backward=False))
-        log("nan density", prec, st)
-        assert st in (M.ENONFINITE, M.EDOMAIN, M.EINVERT), st
+        log("nan", what, prec, st)
+        assert st == M.ENONFINITE, st
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_inverted_deformation_reports_einvert(dim):
+    """A field three orders of magnitude beyond the workloads' drives the
+    magnetic stress of Eq. 7 so hard that det F drops below zero within two
+    steps: EINVERT, as the oracle reports for the same input."""
+    inst = W.make_tiny(seed=7, dim=dim, n_steps=2, n_grid=32, size=(0.2, 0.15, 0.15), corner=[0.4, 0.4, 0.4][:dim],
+                       n_segments=1)
+    prog = np.zeros((1, dim))
+    prog[0, 0] = 3e3
+    bad = W.Instance(dict(inst.params), inst.x0, inst.density, inst.br, prog, inst.target, inst.mask)
+    with pytest.raises(orc.OracleError) as e:
+        orc.rollout(bad.params, bad.x0, bad.density, bad.br, bad.b_prog, bad.target, bad.mask)
+    assert e.value.code == orc.EINVERT
+    for prec in (8, 4):
+        st = _status_of(lambda: gpu_run([bad], precision=prec, backward=False))
+        log("huge field", dim, prec, st)
+        assert st == M.EINVERT, st
 
 
 def test_backward_needs_a_recorded_rollout():
