@@ -111,6 +111,10 @@ typedef struct {
     int ckpt_every;          /* checkpoint spacing K of the recorded rollout (0: auto ~ sqrt(T)) */
     int n_obstacles;         /* 0..MPM_MAG_MAX_OBSTACLES                                      */
     mpm_mag_obstacle obstacles[MPM_MAG_MAX_OBSTACLES];
+    int64_t ckpt_budget_bytes; /* device bytes the recorded rollout may hold for the reverse
+                                  sweep (checkpoints, segment stash, grid ring, grid stores);
+                                  0: no bound. The handle takes the smallest positive value
+                                  over its instances (or the "ckpt_budget" option).        */
 } mpm_mag_instance_desc;
 
 /*

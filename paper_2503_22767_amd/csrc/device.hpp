@@ -18,18 +18,22 @@ constexpr int kGridThreadsMax = 1024;   // largest workgroup of the grid update 
 constexpr int kErrDomain = 1;
 constexpr int kErrInvert = 2;
 constexpr int kErrNonFinite = 4;
+constexpr int kErrStore = 8;   // a grid store entry to be read was not kept (internal)
 
 // The error word of a call keeps its earliest failure, as the key
 // (2 n + phase) * 4 + rank: phase 0 is step n's input (the stencils of the
 // state it starts from), phase 1 its G2P output (the new state); rank 0 a
-// non-finite value, 1 det F <= 0, 2 a stencil outside the grid. A key of all
+// non-finite value, 1 det F <= 0, 2 a stencil outside the grid, 3 a grid store
+// entry to be read that was not kept (an internal failure). A key of all
 // ones means no failure. (After a first failure later steps can fail as its
 // consequence, e.g. an inverted F gives a non-finite stress one step later; the
 // earliest one is the cause reported.)
 constexpr unsigned long long kNoError = ~0ull;
 __device__ __forceinline__ void report_error(unsigned long long* word, int step, int phase, int flags)
 {
-    const unsigned long long rank = (flags & kErrNonFinite) ? 0ull : ((flags & kErrInvert) ? 1ull : 2ull);
+    const unsigned long long rank = (flags & kErrNonFinite) ? 0ull
+                                  : (flags & kErrInvert)    ? 1ull
+                                  : (flags & kErrDomain)    ? 2ull : 3ull;
     atomicMin(word, ((unsigned long long)(2 * step + phase) << 2) | rank);
 }
 

@@ -212,6 +212,9 @@ public:
             while ((1 << abits) < d.n_grid) ++abits;
             max_axis_bits = std::max(max_axis_bits, abits);
             ckpt_desc_ = d.ckpt_every;
+            if (d.ckpt_budget_bytes < 0) return fail(MPM_MAG_EINVAL, "ckpt_budget_bytes must be >= 0");
+            if (d.ckpt_budget_bytes > 0 && (budget_desc_ == 0 || d.ckpt_budget_bytes < budget_desc_))
+                budget_desc_ = d.ckpt_budget_bytes;
         }
         if (grid > ((int64_t)1 << 31) / 4) return fail(MPM_MAG_EINVAL, "total grid too large");
         caller_start_h_.push_back(caller);
@@ -310,6 +313,11 @@ public:
             gs_budget_mib_ = value;   // applied at the next recorded rollout
             return MPM_MAG_OK;
         }
+        if (k == "ckpt_budget") {
+            if (value < 0) return fail(MPM_MAG_EINVAL, "ckpt_budget must be >= 0 bytes");
+            budget_opt_ = value;   // applied at the next recorded rollout
+            return MPM_MAG_OK;
+        }
         if (k == "ckpt_every") {
             if (value < 0 || value > (1 << 30)) return fail(MPM_MAG_EINVAL, "bad ckpt_every");
             ckpt_opt_ = (int)value;
@@ -394,10 +402,11 @@ public:
         }
         st = finish(s);
         if (st) return st;
-        if (record && gstore_) {
-            gs_base_h_.assign((size_t)gs_chains_ * (T_ + 1), 0);
+        if (record && T_ > 0) {
+            // per-step active block counts of every chain (and which steps the store kept)
+            gs_base_h_.assign((size_t)n_chains() * (T_ + 1), 0);
             MPM_HIP(hipMemcpy(gs_base_h_.data(), gs_base_, sizeof(int) * gs_base_h_.size(), hipMemcpyDeviceToHost));
-            gs_count_chains_ = gs_chains_;
+            gs_count_chains_ = n_chains();
             gs_valid_ = true;
         }
         recorded_ = record != 0;
@@ -415,8 +424,10 @@ public:
         MPM_HIP(hipMemsetAsync(gB_, 0, sizeof(double) * S_tot_ * D, s));
         MPM_HIP(hipMemcpyAsync(dloss_, dloss, sizeof(real) * n_inst_, hipMemcpyDeviceToDevice, s));
         MPM_HIP(hipMemsetAsync(active_, 0, sizeof(int) * 4 * kMaxChains, s));
+        int st = ensure_seg_store();
+        if (st) return st;
         Args<real> a = args();
-        int st = launch(K_SEED, s, n_chunks_, kBlock, k_seed<real, D>, a, (const real*)st_, adj_,
+        st = launch(K_SEED, s, n_chunks_, kBlock, k_seed<real, D>, a, (const real*)st_, adj_,
                         (const real*)x0s_, (const real*)tgt_, (const uint8_t*)mask_, (const real*)dloss_,
                         (const int*)id_, (const real*)dx_final);
         if (st) return st;
@@ -654,8 +665,7 @@ private:
             if (r) return r;
         }
         if (stored) {
-            r = launch(K_RESTORE, cs, grid_blocks_of(q), kGridBlock, k_grid_restore<real, D>, a, store_of(q, n, true),
-                       gv_slot(j), gm_slot(j));
+            r = restore(q, cs, c, n);
             if (r || n + 1 >= s1) return r;
             return launch(K_G2P, cs, nc, kBlock, k_g2p<real, D>, a, (const real*)gv_slot(j),
                           (const real*)seg_state(c, j), seg_state(c, j + 1), n, 0, lf(n), 1);
@@ -664,8 +674,10 @@ private:
             r = launch(K_P2G, cs, nc, kBlock, k_p2g<real, D>, a, (const real*)seg_state(c, j), n, lf(n));
             if (r) return r;
         }
+        // the step's grid goes to the dense ring for this pass and to the
+        // segment store for the transposed steps
         r = launch(K_GRID, cs, grid_blocks_of(q), grid_threads(), k_grid<real, D>, a, gv_slot(j), gm_slot(j), lf(n),
-                   store_of(q, n, false));
+                   seg_store_of(q, j, n));
         if (r) return r;
         if (n + 1 >= s1) return MPM_MAG_OK;
         if (fuse_fwd_)
@@ -719,6 +731,14 @@ private:
         int r = launch(K_GRID_ADJ, cs, grid_blocks_of(q), grid_threads(), k_grid_adj<real, D>, a, (const real*)gm_slot(j),
                        gpm_, lst(n), n);
         if (r) return r;
+        // the G2P transpose of step n - 1 needs its grid: the ring still holds
+        // the segment's last two steps from the recompute, earlier ones are
+        // rebuilt from their store (their ring slot's previous step, n + 1, is
+        // done with)
+        if (n > s0 && j - 1 < (s1 - s0) - 2) {
+            r = restore(q, cs, c, n - 1);
+            if (r) return r;
+        }
         if (n > s0 && fuse_adj_)
             return launch(K_ADJ_FUSED, cs, nc, kBlock, k_adj_fused<real, D>, a, (const real*)gpm_,
                           (const real*)seg_state(c, j), n, (const real*)gv_slot(j - 1), (const real*)seg_state(c, j - 1),
@@ -745,9 +765,20 @@ private:
         if (c * K_ + j + 1 < std::min(T_, (c + 1) * K_)) return seg_state(c, j + 1);
         return c + 1 < nck_ ? ckpt_slot(c + 1) : st_;
     }
-    // grid velocity / (momentum, mass) of step s0 + j of the segment being reversed
-    real* gv_slot(int j) { return gstash_ + (size_t)(2 * j) * 4 * G_; }
-    real* gm_slot(int j) { return gstash_ + (size_t)(2 * j + 1) * 4 * G_; }
+    // grid velocity / (momentum, mass) of step s0 + j of the segment being
+    // reversed: a ring of two dense grids, steps of equal parity sharing one
+    real* gv_slot(int j) { return ring_ + (size_t)(2 * (j & 1)) * 4 * G_; }
+    real* gm_slot(int j) { return ring_ + (size_t)(2 * (j & 1) + 1) * 4 * G_; }
+
+    // step n of segment c's grid, rebuilt in its ring slot from the store that
+    // holds it (the recorded forward's, or the segment store of its recompute)
+    int restore(int q, hipStream_t cs, int c, int n)
+    {
+        const int j = n - c * K_;
+        const GridStore<real> g = seg_stored(q, c) ? store_of(q, n, true) : seg_store_of(q, j, n);
+        return launch(K_RESTORE, cs, grid_blocks_of(q), kGridBlock, k_grid_restore<real, D>, args_of(q), g,
+                      gv_slot(j), gm_slot(j));
+    }
 
     int fail(int code, const std::string& msg)
     {
@@ -1016,19 +1047,34 @@ private:
             const std::string at = " (first at step " + std::to_string(step) + ")";
             if (rank == 0) return fail(MPM_MAG_ENONFINITE, "non-finite particle state" + at);
             if (rank == 1) return fail(MPM_MAG_EINVERT, "det F <= 0" + at);
-            return fail(MPM_MAG_EDOMAIN, "a particle stencil left the grid" + at);
+            if (rank == 2) return fail(MPM_MAG_EDOMAIN, "a particle stencil left the grid" + at);
+            return fail(MPM_MAG_EHIP, "grid store entry not kept" + at);
         }
         return MPM_MAG_OK;
     }
 
     // ------------------------------------------------------------ grid store
-    // The recorded forward keeps every step's active coarse blocks (GridStore)
-    // in one arena, split between the chains. Its size comes from the block
-    // counts of the last recorded rollout (a particle-count estimate before the
-    // first), within a budget: the grid_store option in MiB, or by default the
-    // free device memory less an eighth of the total. Steps beyond the arena
-    // are not kept; their segments are recomputed in full by the reverse sweep.
-    size_t store_block_bytes() const { return sizeof(real) * 8 * Coarse<D>::nodes; }
+    // The recorded forward keeps every step's active coarse blocks (GridStore:
+    // each node's summed (momentum, mass), the velocity being recomputed from
+    // it) in one arena, split between the chains; steps beyond it are not kept
+    // and their segments are recomputed in full by the reverse sweep, which
+    // then writes their grids to a segment store. The arena's size comes from
+    // the block counts of the last recorded rollout (a particle-count estimate
+    // before the first), within the memory bound: the checkpoint budget when
+    // one is set (it also covers the checkpoints, the segment stash, the grid
+    // ring and the segment store), else the grid_store option in MiB, else the
+    // free device memory less an eighth of the total.
+    size_t store_block_bytes() const { return sizeof(real) * 4 * Coarse<D>::nodes; }
+
+    // the handle's checkpoint budget in bytes, 0: none
+    int64_t budget() const { return budget_opt_ > 0 ? budget_opt_ : budget_desc_; }
+
+    // bytes of the checkpoints, the segment stash and the grid ring
+    int64_t ckpt_plan_bytes(int K) const
+    {
+        const int nck = std::max(1, (T_ + K - 1) / K);
+        return (int64_t)state_bytes() * (nck + std::max(1, K - 1)) + (int64_t)sizeof(real) * 2 * 2 * 4 * G_;
+    }
 
     GridStore<real> store_of(int q, int n, bool on) const
     {
@@ -1037,12 +1083,28 @@ private:
         g.blk = nullptr;
         g.base = nullptr;
         g.cap = 0;
+        g.idx = n;
         g.step = n;
-        if (!on || !gstore_ || q >= gs_chains_) return g;
-        g.data = gstore_ + (size_t)gs_off_[q] * 8 * Coarse<D>::nodes;
+        if (!on || !gs_base_) return g;
+        g.base = gs_base_ + (size_t)q * (T_ + 1);   // counted whenever recording
+        if (!gstore_ || q >= gs_chains_) return g;
+        g.data = gstore_ + (size_t)gs_off_[q] * 4 * Coarse<D>::nodes;
         g.blk = gs_blk_ + gs_off_[q];
-        g.base = gs_base_ + (size_t)q * (T_ + 1);
         g.cap = (int)gs_cap_[q];
+        return g;
+    }
+
+    // step n = s0 + j of a segment recomputed in full: its entry j of chain q's
+    // segment store
+    GridStore<real> seg_store_of(int q, int j, int n) const
+    {
+        GridStore<real> g;
+        g.data = seg_data_ ? seg_data_ + (size_t)seg_off_[q] * 4 * Coarse<D>::nodes : nullptr;
+        g.blk = seg_blk_ ? seg_blk_ + seg_off_[q] : nullptr;
+        g.base = seg_base_ ? seg_base_ + (size_t)q * (K_ + 1) : nullptr;
+        g.cap = (int)seg_cap_[q];
+        g.idx = j;
+        g.step = n;
         return g;
     }
 
@@ -1052,6 +1114,14 @@ private:
         if (!gs_valid_ || !gstore_ || q >= gs_chains_) return false;
         const int s1 = std::min(T_, (c + 1) * K_);
         return gs_base_h_[(size_t)q * (T_ + 1) + s1] <= gs_cap_[q];
+    }
+
+    // active blocks of segment c of chain q in the last recorded rollout
+    int64_t seg_blocks(int q, int c) const
+    {
+        const int s0 = c * K_, s1 = std::min(T_, s0 + K_);
+        const int* b = gs_base_h_.data() + (size_t)q * (T_ + 1);
+        return (int64_t)b[s1] - (s0 == 0 ? 0 : b[s0]);
     }
 
     void free_store()
@@ -1067,11 +1137,41 @@ private:
         ++plan_gen_;   // store addresses are baked into captured launches
     }
 
+    void free_seg_store()
+    {
+        if (seg_data_) (void)hipFree(seg_data_);
+        if (seg_blk_) (void)hipFree(seg_blk_);
+        bytes_ -= seg_bytes_;
+        seg_data_ = nullptr;
+        seg_blk_ = nullptr;
+        seg_bytes_ = 0;
+        for (int q = 0; q < kMaxChains; ++q) seg_off_[q] = seg_cap_[q] = 0;
+        ++plan_gen_;
+    }
+
+    // allocate slots for chain-split arenas; false when the device is out of memory
+    bool alloc_arena(real** data, int** blk, int64_t slots)
+    {
+        if (hipMalloc(data, store_block_bytes() * (size_t)slots) != hipSuccess) {
+            (void)hipGetLastError();
+            *data = nullptr;
+            return false;
+        }
+        if (hipMalloc(blk, sizeof(int) * (size_t)slots) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipFree(*data);
+            *data = nullptr;
+            *blk = nullptr;
+            return false;
+        }
+        return true;
+    }
+
     int ensure_store()
     {
         gs_valid_ = false;
         const int nq = n_chains();
-        if (gs_budget_mib_ == 0 || T_ == 0) {
+        if (T_ == 0) {
             if (gstore_) free_store();
             return MPM_MAG_OK;
         }
@@ -1082,37 +1182,53 @@ private:
             }
             bytes_ += sizeof(int) * (size_t)kMaxChains * (T_ + 1);
         }
-        // slots wanted per chain: the last count with a tenth more, else the estimate
+        const int64_t B = budget();
+        if (gs_budget_mib_ == 0) {   // option: no store
+            if (gstore_) free_store();
+            return MPM_MAG_OK;
+        }
+        // slots wanted per chain: the last count with a tenth more, else the
+        // estimate; and the largest segment, for the segment store
         const bool known = !gs_base_h_.empty() && gs_count_chains_ == nq;
-        std::vector<int64_t> want(nq, 0);
-        int64_t total = 0;
+        std::vector<int64_t> want(nq, 0), seg_want(nq, 0);
+        int64_t total = 0, seg_total = 0;
         for (int q = 0; q < nq; ++q) {
             if (known) {
                 const int64_t need = gs_base_h_[(size_t)q * (T_ + 1) + T_];
                 want[q] = need + need / 10 + 8;
+                for (int c = 0; c < nck_; ++c) seg_want[q] = std::max(seg_want[q], seg_blocks(q, c));
             } else {
                 int64_t per_step = 0;
                 for (int k = 0; k < n_inst_; ++k)
                     if (inst_h_[k].chunk_off >= chains_[q].c0 && inst_h_[k].chunk_off < chains_[q].c0 + chains_[q].nc)
                         per_step += est_cb_inst_[k];
                 want[q] = per_step * T_;
+                seg_want[q] = per_step * K_;
             }
+            seg_want[q] += seg_want[q] / 10 + 8;
             want[q] = std::min<int64_t>(want[q], kStoreCountMax);
             total += want[q];
+            seg_total += seg_want[q];
         }
         const size_t bb = store_block_bytes();
-        int64_t budget;
-        if (gs_budget_mib_ > 0) {
-            budget = gs_budget_mib_ << 20;
+        int64_t avail;   // bytes the arena may take
+        if (B > 0) {
+            avail = B - ckpt_plan_bytes(K_) - (int64_t)sizeof(int) * kMaxChains * (T_ + 1);
+            // a store short of the whole rollout leaves segments to recompute,
+            // whose grids go to the segment store: keep room for it
+            if (avail < (int64_t)(bb + sizeof(int)) * total) avail -= (int64_t)(bb + sizeof(int)) * seg_total;
+            if (gs_budget_mib_ > 0) avail = std::min<int64_t>(avail, gs_budget_mib_ << 20);
+        } else if (gs_budget_mib_ > 0) {
+            avail = gs_budget_mib_ << 20;
         } else {
             size_t fr = 0, tot = 0;
             if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
                 (void)hipGetLastError();
                 fr = tot = 0;
             }
-            budget = (int64_t)fr + (int64_t)gstore_bytes_ - (int64_t)(tot / 8);
+            avail = (int64_t)fr + (int64_t)gstore_bytes_ - (int64_t)(tot / 8);
         }
-        const int64_t max_slots = std::max<int64_t>(0, budget) / (int64_t)(bb + sizeof(int));
+        const int64_t max_slots = std::max<int64_t>(0, avail) / (int64_t)(bb + sizeof(int));
         if (total > max_slots) {
             int64_t t2 = 0;
             for (int q = 0; q < nq; ++q) {
@@ -1121,28 +1237,18 @@ private:
             }
             total = t2;
         }
-        // keep the arena when it fits every chain and is not more than twice the need
+        // keep the arena when it fits every chain and is not more than twice the
+        // need (and, under a budget, within it)
         bool keep = gstore_ && gs_chains_ == nq;
         int64_t cur = 0;
         for (int q = 0; keep && q < nq; ++q) {
             keep = gs_cap_[q] >= want[q];
             cur += gs_cap_[q];
         }
-        if (keep && cur <= 2 * total + 64) return MPM_MAG_OK;
+        if (keep && cur <= 2 * total + 64 && cur <= max_slots) return MPM_MAG_OK;
         if (gstore_) free_store();
         if (total <= 0) return MPM_MAG_OK;
-        if (hipMalloc(&gstore_, bb * (size_t)total) != hipSuccess) {
-            (void)hipGetLastError();   // no arena: every segment is recomputed
-            gstore_ = nullptr;
-            return MPM_MAG_OK;
-        }
-        if (hipMalloc(&gs_blk_, sizeof(int) * (size_t)total) != hipSuccess) {
-            (void)hipGetLastError();
-            (void)hipFree(gstore_);
-            gstore_ = nullptr;
-            gs_blk_ = nullptr;
-            return MPM_MAG_OK;
-        }
+        if (!alloc_arena(&gstore_, &gs_blk_, total)) return MPM_MAG_OK;   // no arena: every segment is recomputed
         gstore_bytes_ = (bb + sizeof(int)) * (size_t)total;
         bytes_ += gstore_bytes_;
         int64_t off = 0;
@@ -1156,6 +1262,56 @@ private:
         return MPM_MAG_OK;
     }
 
+    // Segment store for the segments the recorded forward could not keep,
+    // sized from the last recorded rollout's largest such segment per chain.
+    int ensure_seg_store()
+    {
+        const int nq = n_chains();
+        std::vector<int64_t> need(nq, 0);
+        int64_t total = 0;
+        const bool counted = gs_valid_ && gs_count_chains_ == nq;
+        for (int q = 0; q < nq; ++q) {
+            for (int c = 0; c < nck_; ++c) {
+                if (seg_stored(q, c)) continue;
+                need[q] = std::max(need[q], counted ? seg_blocks(q, c) : (int64_t)n_cb_ * K_);
+            }
+            if (need[q] > 0) need[q] += need[q] / 10 + 8;
+            total += need[q];
+        }
+        if (!seg_base_) {
+            if (hipMalloc(&seg_base_, sizeof(int) * (size_t)kMaxChains * (K_ + 1)) != hipSuccess) {
+                seg_base_ = nullptr;
+                return fail(MPM_MAG_ENOMEM, "segment store counters");
+            }
+            seg_base_k_ = K_;
+            bytes_ += sizeof(int) * (size_t)kMaxChains * (K_ + 1);
+        }
+        bool fits = seg_base_k_ >= K_;
+        for (int q = 0; fits && q < nq; ++q) fits = seg_cap_[q] >= need[q];
+        if (fits) return MPM_MAG_OK;
+        if (seg_base_k_ < K_) {
+            (void)hipFree(seg_base_);
+            bytes_ -= sizeof(int) * (size_t)kMaxChains * (seg_base_k_ + 1);
+            if (hipMalloc(&seg_base_, sizeof(int) * (size_t)kMaxChains * (K_ + 1)) != hipSuccess) {
+                seg_base_ = nullptr;
+                return fail(MPM_MAG_ENOMEM, "segment store counters");
+            }
+            seg_base_k_ = K_;
+            bytes_ += sizeof(int) * (size_t)kMaxChains * (K_ + 1);
+        }
+        free_seg_store();
+        if (!alloc_arena(&seg_data_, &seg_blk_, total)) return fail(MPM_MAG_ENOMEM, "segment store");
+        seg_bytes_ = (store_block_bytes() + sizeof(int)) * (size_t)total;
+        bytes_ += seg_bytes_;
+        int64_t off = 0;
+        for (int q = 0; q < nq; ++q) {
+            seg_off_[q] = off;
+            seg_cap_[q] = need[q];
+            off += need[q];
+        }
+        return MPM_MAG_OK;
+    }
+
     int ensure_checkpoints()
     {
         int K = ckpt_opt_ > 0 ? ckpt_opt_ : (ckpt_desc_ > 0 ? ckpt_desc_ : 0);
@@ -1163,15 +1319,20 @@ private:
         if (T_ == 0) K = 1;
         K = std::max(1, std::min(K, std::max(1, T_)));
         int nck = std::max(1, (T_ + K - 1) / K);
+        const int64_t B = budget();
+        if (B > 0 && ckpt_plan_bytes(K) > B)
+            return fail(MPM_MAG_ENOMEM, "checkpoint budget of " + std::to_string(B) + " bytes is below the " +
+                                            std::to_string(ckpt_plan_bytes(K)) + " the checkpoints, segment stash " +
+                                            "and grid ring need at spacing " + std::to_string(K));
         if (ckpt_ && K == K_ && nck == nck_) return MPM_MAG_OK;
         if (ckpt_) { (void)hipFree(ckpt_); bytes_ -= ckpt_bytes_; ckpt_ = nullptr; }
         if (stash_) { (void)hipFree(stash_); bytes_ -= stash_bytes_; stash_ = nullptr; }
-        if (gstash_) { (void)hipFree(gstash_); bytes_ -= gstash_bytes_; gstash_ = nullptr; }
+        if (ring_) { (void)hipFree(ring_); bytes_ -= ring_bytes_; ring_ = nullptr; }
         ckpt_bytes_ = state_bytes() * nck;
         stash_bytes_ = state_bytes() * std::max(1, K - 1);
-        gstash_bytes_ = sizeof(real) * (size_t)K * 2 * 4 * G_;
-        if (hipMalloc(&gstash_, gstash_bytes_) != hipSuccess) { gstash_ = nullptr; return fail(MPM_MAG_ENOMEM, "grid stash"); }
-        bytes_ += gstash_bytes_;
+        ring_bytes_ = sizeof(real) * (size_t)2 * 2 * 4 * G_;
+        if (hipMalloc(&ring_, ring_bytes_) != hipSuccess) { ring_ = nullptr; return fail(MPM_MAG_ENOMEM, "grid ring"); }
+        bytes_ += ring_bytes_;
         if (hipMalloc(&ckpt_, ckpt_bytes_) != hipSuccess) { ckpt_ = nullptr; return fail(MPM_MAG_ENOMEM, "checkpoint pool"); }
         if (hipMalloc(&stash_, stash_bytes_) != hipSuccess) {
             (void)hipFree(ckpt_); ckpt_ = nullptr;
@@ -1180,6 +1341,7 @@ private:
         bytes_ += ckpt_bytes_ + stash_bytes_;
         K_ = K;
         nck_ = nck;
+        gs_valid_ = false;   // segment boundaries moved
         ++plan_gen_;
         return MPM_MAG_OK;
     }
@@ -1286,8 +1448,13 @@ private:
         allocs_.clear();
         if (ckpt_) (void)hipFree(ckpt_);
         if (stash_) (void)hipFree(stash_);
-        if (gstash_) (void)hipFree(gstash_);
-        ckpt_ = stash_ = gstash_ = nullptr;
+        if (ring_) (void)hipFree(ring_);
+        ckpt_ = stash_ = ring_ = nullptr;
+        if (seg_data_) (void)hipFree(seg_data_);
+        if (seg_blk_) (void)hipFree(seg_blk_);
+        if (seg_base_) (void)hipFree(seg_base_);
+        seg_data_ = nullptr;
+        seg_blk_ = seg_base_ = nullptr;
         if (gstore_) (void)hipFree(gstore_);
         if (gs_blk_) (void)hipFree(gs_blk_);
         if (gs_base_) (void)hipFree(gs_base_);
@@ -1333,7 +1500,16 @@ private:
     int* active_ = nullptr;
     int* active_list_ = nullptr;
     real* gpm_ = nullptr;      // (pbar, mbar) of the grid transpose
-    real* gstash_ = nullptr;   // per-step grid of the segment being reversed
+    real* ring_ = nullptr;     // two dense grids (v, (p, m)) of the segment being reversed
+    size_t ring_bytes_ = 0;
+    // segment store: chain q owns slots [seg_off_[q], seg_off_[q] + seg_cap_[q])
+    real* seg_data_ = nullptr;
+    int* seg_blk_ = nullptr;
+    int* seg_base_ = nullptr;         // [kMaxChains][seg_base_k_ + 1]
+    int seg_base_k_ = 0;
+    size_t seg_bytes_ = 0;
+    int64_t seg_off_[kMaxChains] = {}, seg_cap_[kMaxChains] = {};
+    int64_t budget_desc_ = 0, budget_opt_ = 0;   // checkpoint budget (bytes): descriptors, option
     // grid store: chain q owns slots [gs_off_[q], gs_off_[q] + gs_cap_[q])
     real* gstore_ = nullptr;
     int* gs_blk_ = nullptr;
@@ -1348,7 +1524,6 @@ private:
     std::vector<int64_t> est_cb_inst_;
     std::vector<char> bwd_sig_;       // stored segments of the captured reverse sweep
     int64_t bwd_gen_ = 0;
-    size_t gstash_bytes_ = 0;
     std::vector<int> cb_inst_h_;
     int64_t n_cb_ = 0;
     int64_t trace_nodes_ = 0;       // sum of the instances' node counts

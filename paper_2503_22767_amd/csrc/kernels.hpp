@@ -99,20 +99,24 @@ struct Args {
     int64_t trace_nodes;   // nodes of all instances (sum of n_grid^D)
 };
 
-// Grid store: the recorded forward keeps each step's active coarse blocks
-// (node velocity, then the summed (momentum, mass) record: 8 values per node),
-// packed step after step, so that the reverse sweep can rebuild a step's
-// grid without recomputing its P2G. Step n of one chain owns the slots
-// [base[n], base[n + 1]); blk names the coarse block in each slot. base keeps
-// counting past cap, so a step is stored iff base[n + 1] <= cap.
+// Grid store: a step's active coarse blocks, each node's summed (momentum,
+// mass) record (4 values), packed step after step, so that the reverse sweep
+// can rebuild a step's grid without recomputing its P2G; the node velocity is
+// recomputed from the record by the same grid operation. Entry idx of one
+// chain owns the slots [base[idx], base[idx + 1]); blk names the coarse block
+// in each slot. base keeps counting past cap (and counts even without data),
+// so an entry is stored iff base[idx + 1] <= cap. The recorded forward keeps
+// the whole rollout (idx = step); the recompute of a segment the forward could
+// not keep writes its own steps to a segment store (idx = step in segment).
 constexpr int kStoreCountMax = 1 << 30;
 template <typename real>
 struct GridStore {
-    real* data;   // [cap][Coarse<D>::nodes][8], nullptr: not kept
+    real* data;   // [cap][Coarse<D>::nodes][4], nullptr: only counted
     int* blk;     // [cap]
-    int* base;    // [n_steps + 1]
+    int* base;    // [entries + 1], nullptr: neither kept nor counted
     int cap;      // slots
-    int step;
+    int idx;      // entry of this launch
+    int step;     // time step (moving obstacles)
 };
 
 // Slot of the particle that lane t of this block works on. The forward
@@ -1367,19 +1371,19 @@ void k_grid(Args<real> a, real* gv_out, real* gmd_out, int list, GridStore<real>
 {
   const int n_act = a.active[list];
   int sbase = -1;   // first store slot of this step, -1 when not kept
-  if (gs.data) {
-      const int s0 = gs.step == 0 ? 0 : gs.base[gs.step];
-      if ((int64_t)s0 + n_act <= gs.cap) sbase = s0;
+  if (gs.base) {
+      const int s0 = gs.idx == 0 ? 0 : gs.base[gs.idx];
+      if (gs.data && (int64_t)s0 + n_act <= gs.cap) sbase = s0;
       if (blockIdx.x == 0 && threadIdx.x == 0) {
-          if (gs.step == 0) gs.base[0] = 0;
+          if (gs.idx == 0) gs.base[0] = 0;
           const int64_t s1 = (int64_t)s0 + n_act;
-          gs.base[gs.step + 1] = s1 < kStoreCountMax ? (int)s1 : kStoreCountMax;
+          gs.base[gs.idx + 1] = s1 < kStoreCountMax ? (int)s1 : kStoreCountMax;
       }
   }
   for (int ai = blockIdx.x; ai < n_act; ai += gridDim.x) {
     const int b = a.active_list[list * a.n_coarse + ai];
     const InstDev<real>& I = a.inst[a.cb_inst[b]];
-    real* keep = sbase >= 0 ? gs.data + (size_t)(sbase + ai) * Coarse<D>::nodes * 8 : nullptr;
+    real* keep = sbase >= 0 ? gs.data + (size_t)(sbase + ai) * Coarse<D>::nodes * 4 : nullptr;
     if (keep && threadIdx.x == 0) gs.blk[sbase + ai] = b;
     gather_coarse<real, D>(a, I, b, a.gm, [&](int64_t g, const int g3[3], int ln, const real node[4]) {
         real v[D];
@@ -1408,44 +1412,63 @@ void k_grid(Args<real> a, real* gv_out, real* gmd_out, int list, GridStore<real>
 #pragma unroll
             for (int q = 0; q < 4; ++q) gmd_out[4 * g + q] = node[q];
         if (keep) {
-            real* o = keep + (size_t)ln * 8;
+            real* o = keep + (size_t)ln * 4;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) o[k] = k < D ? v[k] : real(0);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) o[4 + q] = node[q];
+            for (int q = 0; q < 4; ++q) o[q] = node[q];
         }
     });
   }
 }
 
-// Copies the blocks the recorded forward kept for one step back into the dense
-// velocity and (momentum, mass) arrays of the reverse sweep: the same nodes,
-// with the same values, that k_grid writes there when it recomputes the step.
+// Rebuilds one step's grid from a store entry into the dense velocity and
+// (momentum, mass) arrays of the reverse sweep: the same nodes, with the same
+// values, that k_grid writes there when it recomputes the step (the velocity
+// from the kept record by the same grid operation).
 template <typename real, int D>
 __global__ __launch_bounds__(kGridBlock) void k_grid_restore(Args<real> a, GridStore<real> gs, real* gv_out,
                                                              real* gmd_out)
 {
   using CB = Coarse<D>;
-  const int s0 = gs.step == 0 ? 0 : gs.base[gs.step];
-  const int s1 = gs.base[gs.step + 1];
+  const int s0 = gs.idx == 0 ? 0 : gs.base[gs.idx];
+  const int s1 = gs.base[gs.idx + 1];
+  if (s1 > gs.cap) {   // not kept: nothing to read (the host sizes stores so this does not happen)
+      if (blockIdx.x == 0 && threadIdx.x == 0) report_error(a.err, gs.step, 1, kErrStore);
+      return;
+  }
   for (int sl = s0 + blockIdx.x; sl < s1; sl += gridDim.x) {
     const int b = gs.blk[sl];
     const InstDev<real>& I = a.inst[a.cb_inst[b]];
     const int lb = b - I.cb_off;
     const int co[3] = {(lb % I.nb) * CB::edge, (D == 3 ? (lb / I.nb) % I.nb : lb / I.nb) * CB::edge,
                        D == 3 ? (lb / (I.nb * I.nb)) * CB::edge : 0};
-    const real* src = gs.data + (size_t)sl * CB::nodes * 8;
+    const real* src = gs.data + (size_t)sl * CB::nodes * 4;
     for (int ln = threadIdx.x; ln < CB::nodes; ln += blockDim.x) {
         const int g3[3] = {co[0] + ln % CB::edge, co[1] + (ln / CB::edge) % CB::edge,
                            D == 3 ? co[2] + ln / (CB::edge * CB::edge) : 0};
         if (g3[0] >= I.n_grid || g3[1] >= I.n_grid || (D == 3 && g3[2] >= I.n_grid)) continue;
         const int64_t g = (int64_t)I.grid_off + g3[0] +
                           (int64_t)I.n_grid * (g3[1] + (D == 3 ? (int64_t)I.n_grid * g3[2] : 0));
-        const real* r = src + (size_t)ln * 8;
+        real node[4];
 #pragma unroll
-        for (int k = 0; k < D; ++k) gv_out[4 * g + k] = r[k];
+        for (int q = 0; q < 4; ++q) node[q] = src[(size_t)ln * 4 + q];
+        real v[D];
+        if (node[3] > real(0)) {
+            int ijk[D];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) gmd_out[4 * g + q] = r[4 + q];
+            for (int k = 0; k < D; ++k) ijk[k] = g3[k];
+            real vh[D], u0[D], u1[D];
+            int wz[D];
+            bool cl;
+            node_velocity<real, D>(I, ijk, node[3], node, vh, u0, u1, v, wz, cl, (real)gs.step * I.dt,
+                                   (ObstTrace<real, D>*)nullptr);
+        } else {
+#pragma unroll
+            for (int k = 0; k < D; ++k) v[k] = real(0);
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) gv_out[4 * g + k] = v[k];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) gmd_out[4 * g + q] = node[q];
     }
   }
 }

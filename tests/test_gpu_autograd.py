@@ -102,7 +102,7 @@ def test_loss_on_final_positions_in_torch_matches_oracle(dim):
         sim.close()
     p = dict(inst.params, loss_kind=W.LOSS_FINAL_MSE)
     ref = orc.backward(p, inst.x0, inst.density, inst.br, inst.b_prog, inst.target, inst.mask, ckpt_every=5)
-    assert abs(float(g) - ref["loss"]) <= 1e-10 * abs(ref["loss"])
+    assert abs(float(g.detach()) - ref["loss"]) <= 1e-10 * abs(ref["loss"])
     for k in ("g_density", "g_br", "g_b_prog"):
         e = rel_norm(got[k], ref[k])
         log(f"dx_final d{dim} {k}: {e:.2e}")

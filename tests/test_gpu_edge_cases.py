@@ -192,9 +192,11 @@ def test_kernel_timing_env_var_prints_the_table(monkeypatch, capfd):
     err = capfd.readouterr().err
     rows = {line.split()[0]: line.split() for line in err.splitlines() if line.strip()}
     assert "kernel" in rows and "grid_update" in rows and "p2g_g2p_adj" in rows
-    # 6 forward steps; the reverse sweep restores the stored grids instead
+    # 6 forward steps; the reverse sweep restores the stored grids instead: two
+    # segments of 3 steps, each restored for its recompute (3) and before the
+    # transpose of its first step (the ring holds the last two)
     assert int(rows["grid_update"][1]) == 6 and float(rows["grid_update"][3]) > 0.0
-    assert int(rows["grid_restore"][1]) == 6
+    assert int(rows["grid_restore"][1]) == 2 * (3 + 1)
 
 
 def _crowded_coarse_block(n_steps=4, seed=12):

@@ -1,7 +1,11 @@
 """The grid store: the recorded forward keeps every step's active grid blocks,
 so the reverse sweep rebuilds a stored segment's grids from it and runs only
 the G2P to regain the segment's states; segments beyond the store are
-recomputed in full. Every mix gives the oracle's results."""
+recomputed in full, writing their grids to a segment store. The reverse sweep
+keeps two dense grids and rebuilds each earlier step's grid before its
+transpose. Restores per segment of K' steps: K' + (K' - 2) when stored (the
+recompute's and the reverse's), K' - 2 when recomputed. Every mix gives the
+oracle's results; a checkpoint budget bounds the memory all of it takes."""
 import pytest
 import torch
 
@@ -13,9 +17,10 @@ from gpu_util import compare, log, oracle_run
 pytestmark = pytest.mark.gpu
 
 
-def _run_twice(insts, precision, options):
+def _run_twice(insts, precision, options, mem=None):
     """Two recorded rollouts and backward passes on one handle; the first sizes
-    the store from an estimate, the second from the first one's counts."""
+    the store from an estimate, the second from the first one's counts. mem
+    (a list) receives the device bytes the recorded passes added."""
     dtype = torch.float32 if precision == 4 else torch.float64
     sim = M.MpmMag([i.params for i in insts], [i.n for i in insts], precision=precision)
     outs = []
@@ -23,6 +28,7 @@ def _run_twice(insts, precision, options):
         for k, v in options.items():
             sim.set_option(k, v)
         x0, density, br, b_prog, target, mask = M.instance_tensors(insts, dtype=dtype)
+        base = sim.device_bytes()
         for _ in range(2):
             sim.kernel_stats(reset=True)
             loss, x = sim.rollout(x0, density, br, b_prog, target, mask, record=True)
@@ -33,6 +39,8 @@ def _run_twice(insts, precision, options):
                               g_density=gd.double().cpu().numpy(), g_br=gb.double().cpu().numpy(),
                               g_b_prog=gp.double().cpu().numpy()),
                          st["grid_restore"]["launches"], st["p2g"]["launches"] + st["g2p_p2g"]["launches"]))
+            if mem is not None:
+                mem.append(sim.device_bytes() - base)
     finally:
         sim.close()
     return outs
@@ -41,7 +49,7 @@ def _run_twice(insts, precision, options):
 @pytest.mark.parametrize("graph", [0, 1])
 def test_whole_store_matches_oracle_fp64(graph):
     """Everything stored from the second rollout on: the reverse sweep restores
-    every step's grid (one restore per step) and runs no P2G."""
+    every step's grid and runs no P2G (segments of 5, 5, 5, 5, 4 steps)."""
     inst = W.make_tiny(seed=5, dim=3, n_steps=24, loss_kind=W.LOSS_TRAJ_VEL, floor=True, gravity=1.0,
                        size=(0.3, 0.2, 0.25), n_grid=16, n_segments=4)
     ref = oracle_run([inst])
@@ -49,16 +57,16 @@ def test_whole_store_matches_oracle_fp64(graph):
         log("whole store", f"graph={graph} pass {k}: restores {restores}, forward P2G launches {p2g}")
         compare(got, ref, pos_tol=1e-10, grad_tol=1e-9, loss_tol=1e-9, label=f"store pass {k} fp64")
         if k == 1:
-            assert restores == 24
+            assert restores == 4 * (5 + 3) + (4 + 2)
             # the recorded forward's P2G launches only (24 steps, the first unfused)
             assert p2g == 24
 
 
 @pytest.mark.parametrize("graph", [0, 1])
 def test_partial_store_matches_oracle_fp32(graph):
-    """A 5 MiB store (639 FP32 block slots; the walker's steps touch 20 to 39
-    coarse blocks) holds the first of its ten 16-step segments only:
-    that one is restored, the other nine are recomputed."""
+    """A 5 MiB store (1279 FP32 block slots; the walker's steps touch 20 to 39
+    coarse blocks) holds the first of its ten 16-step segments or two: those
+    are restored, the others recomputed."""
     wl = W.make_walker2d(n_steps=160)
     inst = wl.instances[0]
     ref = oracle_run([inst], ckpt_every=16)
@@ -66,8 +74,9 @@ def test_partial_store_matches_oracle_fp32(graph):
                                                                       "grid_store": 5})):
         log("partial store", f"graph={graph} pass {k}: restores {restores}, P2G launches {p2g}")
         compare(got, ref, pos_tol=1e-4, grad_tol=1e-3, label=f"walker2d[:160] partial store pass {k}")
-        assert 0 < restores < 160 and restores % 16 == 0
-        assert p2g == 160 + (160 - restores)
+        stored = (320 - p2g) // 16          # segments whose recompute ran no P2G
+        assert 0 < stored < 10 and p2g == 160 + 16 * (10 - stored)
+        assert restores == 16 * stored + 14 * 10
 
 
 def test_store_off_recomputes_every_segment():
@@ -76,7 +85,7 @@ def test_store_off_recomputes_every_segment():
     ref = oracle_run([inst])
     for k, (got, restores, p2g) in enumerate(_run_twice([inst], 8, {"grid_store": 0})):
         compare(got, ref, pos_tol=1e-10, grad_tol=1e-9, loss_tol=1e-9, label=f"store off pass {k}")
-        assert restores == 0 and p2g == 40
+        assert restores == 4 * 3 and p2g == 40
 
 
 def test_batched_chains_share_the_store_fp32():
@@ -90,4 +99,53 @@ def test_batched_chains_share_the_store_fp32():
     for k, (got, restores, _) in enumerate(_run_twice(insts, 4, {"streams": 3})):
         compare(got, ref, pos_tol=1e-4, grad_tol=1e-3, label=f"batched store pass {k}")
         if k == 1:
-            assert restores == 3 * 30
+            assert restores == 3 * 5 * (6 + 4)
+
+
+def test_checkpoint_budget_bounds_memory_fp32():
+    """The ckpt_budget option bounds what the recorded rollout and the reverse
+    sweep hold: checkpoints, segment stash, grid ring and stores. The walker's
+    160 steps at K = 16 with no bound, then within 85% of what they took:
+    less is stored, more recomputed, the results still the oracle's, and the
+    memory within the bound; a bound below the checkpoints' is ENOMEM."""
+    wl = W.make_walker2d(n_steps=160)
+    inst = wl.instances[0]
+    ref = oracle_run([inst], ckpt_every=16)
+    mem = []
+    full = _run_twice([inst], 4, {"ckpt_every": 16}, mem)
+    free_bytes = mem[-1]
+    budget = int(0.85 * free_bytes)
+    mem = []
+    outs = _run_twice([inst], 4, {"ckpt_every": 16, "ckpt_budget": budget}, mem)
+    for k, (got, restores, p2g) in enumerate(outs):
+        log("budget", f"pass {k}: {mem[k]} bytes of {budget} (unbounded {free_bytes}), restores {restores}, "
+                      f"P2G launches {p2g} (unbounded {full[k][2]})")
+        compare(got, ref, pos_tol=1e-4, grad_tol=1e-3, label=f"walker2d[:160] budget pass {k}")
+        assert mem[k] <= budget
+    assert outs[1][2] > full[1][2]          # fewer segments kept, more recomputed
+    sim = M.MpmMag([inst.params], [inst.n], precision=4)
+    try:
+        sim.set_option("ckpt_every", 16)
+        sim.set_option("ckpt_budget", 1 << 20)
+        tens = M.instance_tensors([inst], dtype=torch.float32)
+        with pytest.raises(M.MpmMagError) as e:
+            sim.rollout(*tens, record=True)
+        assert e.value.status == M.ENOMEM
+        sim.rollout(*tens, record=False)    # a plain rollout needs no checkpoints
+    finally:
+        sim.close()
+
+
+def test_budget_from_the_instance_descriptor():
+    """ckpt_budget_bytes of the descriptor (the smallest positive one of a
+    handle's instances) acts as the option does."""
+    inst = W.make_tiny(seed=8, dim=2, n_steps=12, size=(0.3, 0.2, 0.2), n_grid=16)
+    p = dict(inst.params, ckpt_budget_bytes=4096)
+    sim = M.MpmMag([p], [inst.n], precision=8)
+    try:
+        tens = M.instance_tensors([inst], dtype=torch.float64)
+        with pytest.raises(M.MpmMagError) as e:
+            sim.rollout(*tens, record=True)
+        assert e.value.status == M.ENOMEM
+    finally:
+        sim.close()
