@@ -7,11 +7,14 @@ transposed G2P, grid and P2G kernels) down to d(loss)/d(density, remanence,
 field program). Inputs are resident in HBM before the timed region.
 
 Prints one JSON line. Besides the contract fields it carries the plain-forward
-rate, the adjoint/forward cost ratio, the dominant kernel's HBM roofline
-fraction (algorithmic bytes per launch over the average launch time measured
-with HIP events on the library's stream), and the FP64 CPU oracle timed on a
-bounded sample of the same workload, whose gradient is also compared with the
-device's on that sample.
+rate, the adjoint/forward cost ratio, the dominant kernel's roofline fraction
+(algorithmic FLOPs or bytes per launch over the average launch time measured
+with HIP events on the library's stream), the device memory the handle holds,
+and the FP64 CPU oracle timed on a bounded sample of the same workload (on all
+host cores, and on one), whose gradient is also compared with the device's on
+that sample. The recorded rollout runs within a checkpoint budget (64 GB by
+default): checkpoints, segment stash, grid ring and grid stores together; the
+rate of the same handle without a bound is reported beside it.
 """
 import argparse
 import json
@@ -32,8 +35,13 @@ from paper_2503_22767_amd import workloads as W  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 METRIC = "particle-steps/s fwd+adjoint vs plain fwd; grad rel err vs FP64 oracle"
 
-# particle-steps the oracle sample covers, per workload: (instances, steps)
-CPU_SAMPLE = {"cantilever2d": (1, 500), "walker2d": (1, 200), "plate3d": (1, 300), "batch2d": (4, 100), "quadruped3d": (1, 6)}
+# particle-steps the oracle samples cover, per workload: (instances, steps) on
+# all host cores (also the gradient check: for the quadruped one whole
+# checkpoint segment of task 0), and (instances, steps) on one core
+CPU_SAMPLE = {"cantilever2d": (1, 500), "walker2d": (1, 400), "plate3d": (1, 300), "batch2d": (4, 200),
+              "quadruped3d": (1, 64)}
+CPU_SAMPLE_1CORE = {"cantilever2d": (1, 500), "walker2d": (1, 100), "plate3d": (1, 60), "batch2d": (2, 60),
+                    "quadruped3d": (1, 6)}
 
 
 def log(*a):
@@ -173,43 +181,84 @@ def separate(wl, opts, reps=2):
     return t
 
 
-def cpu_baseline(wl_name, wl, sim_tol_check=True):
-    """FP64 oracle on a bounded sample of the workload: the first instances and
-    steps listed in CPU_SAMPLE. Returns the baseline record and the sample."""
+def _oracle_sample(wl_name, wl, sample, threads):
+    """FP64 oracle forward + checkpointed adjoint on the first instances and
+    steps of the workload, on `threads` host threads (0: all)."""
     import oracle as orc
-    n_inst, steps = CPU_SAMPLE[wl_name]
+    n_inst, steps = sample
     insts = []
     for inst in wl.instances[:n_inst]:
         p = dict(inst.params)
         p["n_steps"] = steps
         insts.append(W.Instance(p, inst.x0, inst.density, inst.br, inst.b_prog, inst.target, inst.mask, inst.group))
     ps = sum(i.n * steps for i in insts)
-    t0 = time.perf_counter()
-    grads = []
-    for inst in insts:
-        g = orc.backward(inst.params, inst.x0, inst.density, inst.br, inst.b_prog, inst.target, inst.mask,
-                         ckpt_every=max(1, int(math.isqrt(steps))))
-        grads.append(g)
-    dt = time.perf_counter() - t0
-    rec = dict(value=round(ps / dt, 1), unit="particle-steps/s fwd+adjoint", cores=1, kind="oracle",
+    orc.set_threads(threads)
+    cores = orc.get_threads()
+    try:
+        t0 = time.perf_counter()
+        grads = []
+        for inst in insts:
+            g = orc.backward(inst.params, inst.x0, inst.density, inst.br, inst.b_prog, inst.target, inst.mask,
+                             ckpt_every=max(1, int(math.isqrt(steps))))
+            grads.append(g)
+        dt = time.perf_counter() - t0
+    finally:
+        orc.set_threads(0)
+    rec = dict(value=round(ps / dt, 1), unit="particle-steps/s fwd+adjoint", cores=cores, kind="oracle",
                sample=f"{wl_name}: first {n_inst} instance(s), first {steps} steps, {ps} particle-steps, "
-                      f"FP64 forward + checkpointed adjoint, {dt:.1f} s")
+                      f"FP64 forward + checkpointed adjoint, {dt:.1f} s on {cores} thread(s)")
+    return rec, insts, grads
+
+
+def cpu_baseline(wl_name, wl):
+    """The FP64 oracle on all host cores (the baseline record; its sample also
+    serves the gradient check) and on one core (reported beside it)."""
+    rec, insts, grads = _oracle_sample(wl_name, wl, CPU_SAMPLE[wl_name], 0)
+    one, _, _ = _oracle_sample(wl_name, wl, CPU_SAMPLE_1CORE[wl_name], 1)
+    rec["one_core"] = dict(value=one["value"], cores=1, sample=one["sample"])
+    rec["host_cpus"] = os.cpu_count()
     return rec, insts, grads
 
 
 def grad_error(wl, insts, oracle_grads):
-    """Device gradient on the oracle's sample vs the oracle (norm-wise relative)."""
+    """Device gradient on the oracle's sample vs the oracle (norm-wise
+    relative): against the oracle deciding its own branches of the grid
+    operation, and against the oracle replaying the device's (the decisions
+    the FP32 run takes differently near ties are counted)."""
+    import oracle as orc
     sub = W.Workload(wl.name, insts, wl.precision)
     sim, tens, dtype = make_sim(sub)
+    T = insts[0].params["n_steps"]
+    trace = torch.zeros(T * sim.trace_nodes(), dtype=torch.int16, device="cuda")
+    sim.set_branch_trace(trace)
     dl = torch.ones(len(insts), dtype=dtype, device="cuda")
     sim.rollout(*tens, record=True, want_x=False)
     gd, gb, gp = sim.backward(dl)
     torch.cuda.synchronize()
+    full = trace.cpu().numpy().view(np.uint16).reshape(T, -1)
+    sim.set_branch_trace(None)
     sim.close()
-    ref = {k: np.concatenate([g[k].ravel() for g in oracle_grads]) for k in ("g_density", "g_br", "g_b_prog")}
     got = dict(g_density=gd.double().cpu().numpy().ravel(), g_br=gb.double().cpu().numpy().ravel(),
                g_b_prog=gp.double().cpu().numpy().ravel())
-    return {k: float(np.linalg.norm(got[k] - ref[k]) / max(1e-300, np.linalg.norm(ref[k]))) for k in ref}
+    rel = lambda a, b: float(np.linalg.norm(a - b) / max(1e-300, np.linalg.norm(b)))
+    ref = {k: np.concatenate([g[k].ravel() for g in oracle_grads]) for k in got}
+    out = dict(own_branches={k: rel(got[k], ref[k]) for k in got})
+    # the oracle on the device's branches, and the oracle's own decisions
+    reps, flips, off = [], 0, 0
+    for inst in insts:
+        n = inst.params["n_grid"] ** inst.params["dim"]
+        tab = np.ascontiguousarray(full[:, off:off + n])
+        off += n
+        with orc.branch_trace(inst.params, record=True) as own:
+            orc.rollout(inst.params, inst.x0, inst.density, inst.br, inst.b_prog, inst.target, inst.mask)
+        flips += int(np.count_nonzero(own != tab))
+        with orc.branch_trace(inst.params, replay=tab):
+            reps.append(orc.backward(inst.params, inst.x0, inst.density, inst.br, inst.b_prog, inst.target,
+                                     inst.mask, ckpt_every=max(1, int(math.isqrt(T)))))
+    rref = {k: np.concatenate([g[k].ravel() for g in reps]) for k in got}
+    out["device_branches"] = {k: rel(got[k], rref[k]) for k in got}
+    out["branch_decisions_differing"] = flips
+    return out
 
 
 def front_end(wl, reps=20):
@@ -377,6 +426,10 @@ def main():
     ap.add_argument("--front-end-only", action="store_true", help="run only the design front-end leg")
     ap.add_argument("--compare-separate", action="store_true",
                     help="also time one handle per instance (default for the batched workload)")
+    ap.add_argument("--budget-gb", type=float, default=64.0,
+                    help="checkpoint budget of the recorded rollout in GB (1e9 bytes): checkpoints, segment "
+                         "stash, grid ring and grid stores; 0: no bound")
+    ap.add_argument("--no-unbounded", action="store_true", help="skip the leg without a checkpoint budget")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not built.",
@@ -414,14 +467,20 @@ def main():
         tuned = A.autotune(wl.instances, wl.precision, log=log)
         log(f"[bench] autotune {tuned['key']}: {tuned['options']} ({'cached' if tuned['cached'] else 'timed'})")
         opts = {**tuned["options"], **opts}
+    budget = int(args.budget_gb * 1e9)
+    if budget > 0 and "ckpt_budget" not in opts:
+        opts["ckpt_budget"] = budget
     sim, tens, dtype = make_sim(wl, opts)
     dloss = torch.ones(len(wl.instances), dtype=dtype, device="cuda")
-    log(f"[bench] device bytes {sim.device_bytes() / 2**30:.2f} GiB (before checkpoints)")
+    base_bytes = sim.device_bytes()
+    log(f"[bench] device bytes {base_bytes / 2**30:.2f} GiB (before checkpoints)")
     for w in range(args.warmup):
         run_step(sim, tens, dloss)
         torch.cuda.synchronize()
         log(f"[bench] warmup {w + 1}/{args.warmup} done")
-    log(f"[bench] device bytes {sim.device_bytes() / 2**30:.2f} GiB (with checkpoints)")
+    held = sim.device_bytes()
+    log(f"[bench] device bytes {held / 2**30:.2f} GiB (with checkpoints and stores; "
+        f"{(held - base_bytes) / 1e9:.2f} GB for the reverse sweep, budget {opts.get('ckpt_budget', 0) / 1e9:.1f} GB)")
     t_step = timed(lambda: run_step(sim, tens, dloss), args.steps)
     log(f"[bench] fwd+adj step {t_step * 1e3:.1f} ms")
     t_fwd = timed(lambda: run_step(sim, tens, dloss, record=False, backward=False), max(1, args.steps))
@@ -436,7 +495,9 @@ def main():
                            particles=wl.n_particles, steps_per_rollout=wl.n_steps,
                            grid=[i.params["n_grid"] for i in wl.instances[:1]][0], parallelism="single-gpu"),
                fwd_value=round(ps / t_fwd, 1), fwd_ms=round(t_fwd * 1e3, 3),
-               adj_over_fwd=round((t_step - t_rec) / t_fwd, 3), fwdadj_over_fwd=round(t_step / t_fwd, 3))
+               adj_over_fwd=round((t_step - t_rec) / t_fwd, 3), fwdadj_over_fwd=round(t_step / t_fwd, 3),
+               ckpt_budget_bytes=opts.get("ckpt_budget", 0), device_bytes=held,
+               reverse_sweep_bytes=held - base_bytes)
     if tuned is not None:
         rec["tuned_options"] = tuned["options"]
     if args.compare_separate or wl.name == "batch2d":
@@ -451,6 +512,20 @@ def main():
                           for k, v in per_kernel.items()}
         log(f"[bench] roofline {rl}")
     sim.close()
+    if budget > 0 and not args.no_unbounded:
+        # the same handle options without the bound (grid store as large as the
+        # rollout needs, within the free memory)
+        u_opts = {k: v for k, v in opts.items() if k != "ckpt_budget"}
+        usim, utens, _ = make_sim(wl, u_opts)
+        ub = usim.device_bytes()
+        run_step(usim, utens, dloss)
+        t_u = timed(lambda: run_step(usim, utens, dloss), max(1, min(3, args.steps)))
+        t_urec = timed(lambda: run_step(usim, utens, dloss, record=True, backward=False), 1)
+        rec["unbounded"] = dict(value=round(ps / t_u, 1), ms_per_step=round(t_u * 1e3, 3),
+                                adj_over_fwd=round((t_u - t_urec) / t_fwd, 3), device_bytes=usim.device_bytes(),
+                                reverse_sweep_bytes=usim.device_bytes() - ub)
+        usim.close()
+        log(f"[bench] without the checkpoint budget {rec['unbounded']}")
     if not args.no_front_end:
         rec["front_end"] = front_end(wl)
         log(f"[bench] front end {rec['front_end']}")
@@ -466,8 +541,12 @@ def main():
         log("[bench] cpu baseline (oracle) ...")
         cb, insts, grads = cpu_baseline(wl.name, wl)
         rec["cpu_baseline"] = cb
-        rec["grad_rel_err_vs_oracle"] = {k: float(f"{v:.3e}") for k, v in grad_error(wl, insts, grads).items()}
+        ge = grad_error(wl, insts, grads)
+        rec["grad_rel_err_vs_oracle"] = {k: float(f"{v:.3e}") for k, v in ge["own_branches"].items()}
+        rec["grad_rel_err_vs_oracle_on_device_branches"] = {k: float(f"{v:.3e}") for k, v in ge["device_branches"].items()}
+        rec["branch_decisions_differing"] = ge["branch_decisions_differing"]
         rec["grad_rel_err_sample"] = cb["sample"].split(",")[0] + ", same sample as cpu_baseline"
+        log(f"[bench] gradient vs oracle {ge}")
         log(f"[bench] cpu baseline {cb}")
     print(json.dumps(rec), flush=True)
 
