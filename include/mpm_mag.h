@@ -238,6 +238,28 @@ int mpm_mag_kernel_flops(mpm_mag* h, int kernel, double* flops);
 int64_t mpm_mag_device_bytes(const mpm_mag* h);
 
 /*
+ * Allocation-free plain rollout, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same forward rollout and losses as
+ * mpm_mag_create + mpm_mag_rollout(record = 0) + mpm_mag_destroy, with the
+ * same arguments, computed by the same kernels, but every device buffer of
+ * the rollout (particle state, grids, staging boxes, sort keys, tables) is
+ * carved from a static device array of mpm_mag_noalloc_scratch_bytes() (64 MiB)
+ * that each GPU the library runs on holds until the process ends. It calls no
+ * hipMalloc, hipFree or other allocating routine; the caller passes the inputs
+ * and outputs (device arrays as for mpm_mag_rollout). Returns ENOMEM with a
+ * message (mpm_mag_last_error(NULL)) when the problem needs more scratch than
+ * that. All calls on one GPU share its array: calls that overlap on one GPU
+ * (other threads, other streams) race; the call returns after its stream has
+ * finished with the array.
+ */
+int mpm_mag_rollout_noalloc(const mpm_mag_instance_desc* descs, int n_inst, const int64_t* n_particles,
+                            int precision, void* stream, const void* x0, const void* density, const void* br,
+                            const void* b_prog, const void* loss_target, const uint8_t* loss_mask, void* x_final,
+                            void* loss_out);
+int64_t mpm_mag_noalloc_scratch_bytes(void);
+
+/*
  * Branch trace (instrumentation for parity checks). The grid operation of
  * Eqs. 16-18 takes integer decisions from floating-point node velocities:
  * whether the node has mass, which branch of Eq. 18 the floor and each

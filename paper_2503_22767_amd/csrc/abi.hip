@@ -2,6 +2,7 @@
 // for (precision, dim), status strings. No exception crosses this boundary.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -15,6 +16,17 @@ struct mpm_mag {
 
 namespace {
 thread_local std::string g_create_error;
+
+// Static scratch of mpm_mag_rollout_noalloc: every device buffer of its plain
+// rollout is carved from this array (one copy per GPU, held until the process
+// ends). Host code must not pass the array's name to kernels or copies (it is
+// a host-side stand-in); the device address of each GPU's copy comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
 
 int record(mpm_mag* h, int st)
 {
@@ -137,6 +149,65 @@ int mpm_mag_kernel_stats(mpm_mag* h, int kernel, int64_t* launches, double* tota
 }
 
 int64_t mpm_mag_device_bytes(const mpm_mag* h) { return h ? h->eng->device_bytes() : 0; }
+
+int mpm_mag_rollout_noalloc(const mpm_mag_instance_desc* descs, int n_inst, const int64_t* n_particles,
+                            int precision, void* stream, const void* x0, const void* density, const void* br,
+                            const void* b_prog, const void* loss_target, const uint8_t* loss_mask, void* x_final,
+                            void* loss_out)
+{
+    g_create_error.clear();
+    if (!descs || !n_particles || n_inst < 1 || (precision != 4 && precision != 8)) return MPM_MAG_EINVAL;
+    const int dim = descs[0].dim;
+    if (dim != 2 && dim != 3) return MPM_MAG_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        g_create_error = "no current HIP device (or more than 64)";
+        return MPM_MAG_EHIP;
+    }
+    void* ws = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            void* p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p) {
+                g_create_error = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+                return MPM_MAG_EHIP;
+            }
+            g_scratch_ptr[dev] = p;
+        }
+        ws = g_scratch_ptr[dev];
+    }
+    int st = MPM_MAG_OK;
+    std::string msg;
+    mpm::EngineBase* e = nullptr;
+    try {
+        if (precision == 4)
+            e = dim == 2 ? mpm::make_engine_f2(descs, n_inst, n_particles, &st, &msg, ws, kScratchBytes)
+                         : mpm::make_engine_f3(descs, n_inst, n_particles, &st, &msg, ws, kScratchBytes);
+        else
+            e = dim == 2 ? mpm::make_engine_d2(descs, n_inst, n_particles, &st, &msg, ws, kScratchBytes)
+                         : mpm::make_engine_d3(descs, n_inst, n_particles, &st, &msg, ws, kScratchBytes);
+    } catch (...) {
+        g_create_error = "unexpected host exception";
+        return MPM_MAG_ENOMEM;
+    }
+    if (!e) {
+        g_create_error = msg;
+        return st ? st : MPM_MAG_ENOMEM;
+    }
+    try {
+        st = e->rollout((hipStream_t)stream, x0, density, br, b_prog, loss_target, loss_mask, x_final, loss_out, 0);
+    } catch (...) {
+        st = MPM_MAG_ENOMEM;
+        e->err = "unexpected host exception";
+    }
+    if (st) g_create_error = e->err;
+    delete e;
+    return st;
+}
+
+int64_t mpm_mag_noalloc_scratch_bytes(void) { return (int64_t)kScratchBytes; }
 
 int mpm_mag_set_branch_trace(mpm_mag* h, uint16_t* trace, int64_t elems)
 {

@@ -90,8 +90,15 @@ public:
     ~Engine() override { release(); }
 
     // ------------------------------------------------------------------ setup
-    int init(const mpm_mag_instance_desc* descs, int n_inst, const int64_t* np)
+    // ws: a device range the handle's buffers are carved from instead of being
+    // allocated (the allocation-free entry point); the handle then runs plain
+    // rollouts only, on the call's stream, and allocates no device memory.
+    int init(const mpm_mag_instance_desc* descs, int n_inst, const int64_t* np, void* ws = nullptr,
+             size_t ws_bytes = 0)
     {
+        ws_ = (uint8_t*)ws;
+        ws_bytes_ = ws ? ws_bytes : 0;
+        ws_used_ = 0;
         if (!descs || !np || n_inst < 1 || n_inst > 4096) return fail(MPM_MAG_EINVAL, "bad instance list");
         n_inst_ = n_inst;
         T_ = descs[0].n_steps;
@@ -351,6 +358,7 @@ public:
         for (auto& I : inst_h_) need_target |= I.loss_kind == kFinalMse;
         if (need_target && !target) return fail(MPM_MAG_EINVAL, "a FINAL_MSE instance needs loss_target");
         has_target_ = target != nullptr;
+        if (record && ws_) return fail(MPM_MAG_EINVAL, "a handle on static scratch runs plain rollouts (record = 0)");
         if (record) {
             int st = ensure_checkpoints();
             if (st) return st;
@@ -521,6 +529,7 @@ private:
     {
         const int n_inst = n_inst_;
         int want = streams_opt_ > 0 ? streams_opt_ : std::min(3, n_inst);
+        if (ws_) want = 1;   // no streams of its own
         want = std::max(1, std::min({want, n_inst, kMaxChains}));
         std::vector<int> inst_chunks(n_inst), inst_cb(n_inst);
         for (int k = 0; k < n_inst; ++k) {
@@ -1350,6 +1359,18 @@ private:
     int dalloc(T** p, size_t n)
     {
         size_t b = sizeof(T) * std::max<size_t>(n, 1);
+        if (ws_) {   // carved from the workspace, 256-byte aligned
+            const size_t off = (ws_used_ + 255) & ~(size_t)255;
+            if (off + b > ws_bytes_) {
+                *p = nullptr;
+                return fail(MPM_MAG_ENOMEM, "the problem needs more than the " + std::to_string(ws_bytes_ >> 20) +
+                                                " MiB of static scratch");
+            }
+            *p = (T*)(ws_ + off);
+            ws_used_ = off + b;
+            bytes_ += b;
+            return MPM_MAG_OK;
+        }
         if (hipMalloc((void**)p, b) != hipSuccess) { *p = nullptr; return fail(MPM_MAG_ENOMEM, "device allocation"); }
         allocs_.push_back((void*)*p);
         bytes_ += b;
@@ -1398,8 +1419,11 @@ private:
             st |= dalloc(&vals_[b], (size_t)N_);
         }
         st |= dalloc(&hist_, (size_t)256 * sort_blocks_);
-        if (st) return fail(MPM_MAG_ENOMEM, "device allocation failed");
-        if (hipHostMalloc((void**)&err_h_, sizeof(*err_h_)) != hipSuccess) return fail(MPM_MAG_ENOMEM, "pinned error word");
+        if (st) return ws_ ? MPM_MAG_ENOMEM : fail(MPM_MAG_ENOMEM, "device allocation failed");
+        if (ws_)
+            err_h_ = &err_host_;   // a pageable word: no host allocation either
+        else if (hipHostMalloc((void**)&err_h_, sizeof(*err_h_)) != hipSuccess)
+            return fail(MPM_MAG_ENOMEM, "pinned error word");
         MPM_HIP(hipMemcpy(inst_d_, inst_h_.data(), sizeof(InstDev<real>) * inst_h_.size(), hipMemcpyHostToDevice));
         MPM_HIP(hipMemcpy(chunks_d_, chunks_h_.data(), sizeof(ChunkDev) * chunks_h_.size(), hipMemcpyHostToDevice));
         MPM_HIP(hipMemcpy(gblock_d_, gblock_h_.data(), sizeof(int) * gblock_h_.size(), hipMemcpyHostToDevice));
@@ -1460,7 +1484,7 @@ private:
         if (gs_base_) (void)hipFree(gs_base_);
         gstore_ = nullptr;
         gs_blk_ = gs_base_ = nullptr;
-        if (err_h_) (void)hipHostFree(err_h_);
+        if (err_h_ && !ws_) (void)hipHostFree(err_h_);
         err_h_ = nullptr;
         for (auto e : events_) (void)hipEventDestroy(e);
         events_.clear();
@@ -1532,6 +1556,9 @@ private:
     real* dloss_ = nullptr;   // copy of the upstream loss gradient (stable address for graphs)
     unsigned long long* err_d_ = nullptr;   // earliest failure of the call (report_error)
     unsigned long long* err_h_ = nullptr;
+    unsigned long long err_host_ = 0;   // error word copy of a handle on a workspace
+    uint8_t* ws_ = nullptr;             // workspace the buffers are carved from, or nullptr
+    size_t ws_bytes_ = 0, ws_used_ = 0;
     uint32_t* keys_[2] = {nullptr, nullptr};
     uint32_t* vals_[2] = {nullptr, nullptr};
     uint32_t* hist_ = nullptr;
@@ -1560,9 +1587,15 @@ private:
     std::vector<Pending> pending_;
 };
 
-EngineBase* make_engine_f2(const mpm_mag_instance_desc*, int, const int64_t*, int*, std::string*);
-EngineBase* make_engine_f3(const mpm_mag_instance_desc*, int, const int64_t*, int*, std::string*);
-EngineBase* make_engine_d2(const mpm_mag_instance_desc*, int, const int64_t*, int*, std::string*);
-EngineBase* make_engine_d3(const mpm_mag_instance_desc*, int, const int64_t*, int*, std::string*);
+// ws / ws_bytes: carve the engine's buffers from that device range (plain
+// rollouts only) instead of allocating them
+EngineBase* make_engine_f2(const mpm_mag_instance_desc*, int, const int64_t*, int*, std::string*, void* ws = nullptr,
+                           size_t ws_bytes = 0);
+EngineBase* make_engine_f3(const mpm_mag_instance_desc*, int, const int64_t*, int*, std::string*, void* ws = nullptr,
+                           size_t ws_bytes = 0);
+EngineBase* make_engine_d2(const mpm_mag_instance_desc*, int, const int64_t*, int*, std::string*, void* ws = nullptr,
+                           size_t ws_bytes = 0);
+EngineBase* make_engine_d3(const mpm_mag_instance_desc*, int, const int64_t*, int*, std::string*, void* ws = nullptr,
+                           size_t ws_bytes = 0);
 
 }  // namespace mpm

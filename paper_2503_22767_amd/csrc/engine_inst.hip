@@ -15,14 +15,15 @@
 
 namespace mpm {
 
-EngineBase* MPM_FACTORY(const mpm_mag_instance_desc* d, int n, const int64_t* np, int* status, std::string* msg)
+EngineBase* MPM_FACTORY(const mpm_mag_instance_desc* d, int n, const int64_t* np, int* status, std::string* msg,
+                        void* ws, size_t ws_bytes)
 {
     auto* e = new (std::nothrow) Engine<MPM_REAL, MPM_DIM>();
     if (!e) {
         *status = MPM_MAG_ENOMEM;
         return nullptr;
     }
-    *status = e->init(d, n, np);
+    *status = e->init(d, n, np, ws, ws_bytes);
     if (*status != MPM_MAG_OK) {
         *msg = e->err;
         delete e;

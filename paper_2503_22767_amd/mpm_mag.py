@@ -128,6 +128,11 @@ def lib():
     L.mpm_mag_kernel_flops.restype = C.c_int
     L.mpm_mag_device_bytes.argtypes = [vp]
     L.mpm_mag_device_bytes.restype = i64
+    L.mpm_mag_rollout_noalloc.argtypes = [C.POINTER(InstanceDesc), C.c_int, C.POINTER(i64), C.c_int, vp, vp, vp, vp,
+                                          vp, vp, vp, vp, vp]
+    L.mpm_mag_rollout_noalloc.restype = C.c_int
+    L.mpm_mag_noalloc_scratch_bytes.argtypes = []
+    L.mpm_mag_noalloc_scratch_bytes.restype = i64
     L.mpm_mag_set_branch_trace.argtypes = [vp, vp, i64]
     L.mpm_mag_set_branch_trace.restype = C.c_int
     L.mpm_mag_trace_nodes.argtypes = [vp]
@@ -286,6 +291,30 @@ class MpmMag:
             self.close()
         except Exception:
             pass
+
+
+def rollout_noalloc(params, n_particles, precision, x0, density, br, b_prog, target=None, mask=None,
+                    device="cuda"):
+    """Plain rollout through mpm_mag_rollout_noalloc (no device allocation in
+    the library: its buffers come from a static per-GPU scratch array). Inputs
+    are device tensors of the precision's dtype as for MpmMag.rollout; returns
+    (loss[n_inst], x_final[N, dim]), allocated here by the caller's side."""
+    L = lib()
+    n_inst = len(params)
+    descs = (InstanceDesc * n_inst)(*[desc_from_params(p) for p in params])
+    counts = (C.c_int64 * n_inst)(*[int(n) for n in n_particles])
+    dtype = torch.float32 if precision == 4 else torch.float64
+    N, d = int(sum(n_particles)), int(params[0]["dim"])
+    loss = torch.empty(n_inst, dtype=dtype, device=device)
+    x_final = torch.empty((N, d), dtype=dtype, device=device)
+    with torch.cuda.device(device):
+        st = L.mpm_mag_rollout_noalloc(descs, n_inst, counts, int(precision),
+                                       C.c_void_p(torch.cuda.current_stream(device).cuda_stream), _ptr(x0),
+                                       _ptr(density), _ptr(br), _ptr(b_prog), _ptr(target), _ptr(mask),
+                                       _ptr(x_final), _ptr(loss))
+    if st != OK:
+        raise MpmMagError(st, "mpm_mag_rollout_noalloc", L.mpm_mag_last_error(None).decode())
+    return loss, x_final
 
 
 class MpmMagFn(torch.autograd.Function):
