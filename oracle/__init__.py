@@ -43,6 +43,7 @@ class Params(C.Structure):
         ("n_segments", C.c_int), ("seg_steps", C.c_int), ("periodic", C.c_int),
         ("loss_kind", C.c_int), ("loss_dir", C.c_double * 3),
         ("n_obstacles", C.c_int), ("obst", Obstacle * MAX_OBSTACLES),
+        ("mass_eps", C.c_double),
     ]
 
 
@@ -64,6 +65,8 @@ def params(p: dict) -> Params:
     for name, _ in Params._fields_:
         if name in ("n_obstacles", "obst"):
             continue
+        if name == "mass_eps" and name not in p:
+            continue   # default 0: Eq. 33
         val = p[name]
         if name in ("gravity", "loss_dir"):
             arr = (C.c_double * 3)(*[float(v) for v in list(val) + [0.0] * (3 - len(val))][:3])

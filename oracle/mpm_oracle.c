@@ -93,6 +93,7 @@ typedef struct {
     double loss_dir[3];
     int n_obstacles;
     orc_obstacle obst[ORC_MAX_OBST];
+    double mass_eps;   /* floor of the mass interpolation: m = (eps + (1 - eps) phi) rho V; 0 gives Eq. 33 */
 } orc_params;
 
 typedef struct {
@@ -452,7 +453,15 @@ static void field_at(const orc_params* P, const double* bprog, int n, double B[3
     for (int j = 0; j < 3; ++j) B[j] = j < P->dim ? bprog[k * P->dim + j] : 0.0;
 }
 
-static double particle_mass(const orc_params* P, double phi) { return phi * P->rho * P->particle_volume; }
+/* Eq. 33, m = phi rho V, with a floor for void particles: m = (eps_m + (1 -
+ * eps_m) phi) rho V, linear in phi like the stiffness interpolation of Eq. 31
+ * (its eps); eps_m = 0 is Eq. 33 itself. */
+static double particle_mass(const orc_params* P, double phi)
+{
+    return (P->mass_eps + (1.0 - P->mass_eps) * phi) * P->rho * P->particle_volume;
+}
+/* d m / d phi */
+static double particle_mass_d(const orc_params* P) { return (1.0 - P->mass_eps) * P->rho * P->particle_volume; }
 
 /* ------------------------------------------------------------------------- */
 /* forward pieces                                                            */
@@ -1096,7 +1105,7 @@ int orc_p2g_adj(const orc_params* P, int N, const orc_particle* s, const double*
                     if (k / 3 == 2 || k % 3 == 2) { a->F[k] = 0.0; a->C[k] = 0.0; }
             }
             /* P = s_e(phi) P_e + s_m(phi) P_m ; m = phi rho V */
-            gphi[q] += P->rho * V * mb + simp_e_d(P, phi[q]) * ddot9(Pb, Pe) + simp_m_d(P, phi[q]) * ddot9(Pb, Pm);
+            gphi[q] += particle_mass_d(P) * mb + simp_e_d(P, phi[q]) * ddot9(Pb, Pe) + simp_m_d(P, phi[q]) * ddot9(Pb, Pm);
             /* P_m = -(1/mu0) B (x) Br */
             for (int j = 0; j < 3; ++j) {
                 double PtB = 0.0, PBr = 0.0;
@@ -1371,14 +1380,14 @@ int orc_backward(const orc_params* P, int N, const double* x0, const double* phi
                 adj[q].x[k] = -dloss * mq * e[k] / M;
                 dxe += e[k] * (cur[q].x[k] - x0[q * d + k]);
             }
-            gphi[q] += dloss * P->rho * P->particle_volume * (-dxe / M - L / M);
+            gphi[q] += dloss * particle_mass_d(P) * (-dxe / M - L / M);
         }
     } else {
         /* trajectory loss: per-step velocity seeds are injected in reverse_step */
         for (int q = 0; q < N; ++q) {
             double ve = 0.0;
             for (int k = 0; k < d; ++k) ve += e[k] * vsum[3 * q + k];
-            gphi[q] += dloss * P->rho * P->particle_volume * (-P->dt * ve / M - L / M);
+            gphi[q] += dloss * particle_mass_d(P) * (-P->dt * ve / M - L / M);
         }
     }
 
