@@ -405,6 +405,51 @@ def codesign(wl, iters=2):
                 ms_per_iteration=round(ms, 1), loss_history=hist)
 
 
+def walker_codesign(max_iters=400, mass_eps=1e-3, lr=0.01):
+    """The co-design loop on the 2D walker (30,593 particles, 2,000 steps,
+    floor contact, a harmonic stimulus, 8 magnetization regions by x slab,
+    per-particle topology) with void particles' mass floored at mass_eps: beta
+    doubles every 10 iterations from 1 to 128, and the loop runs until the
+    paper's convergence rule holds over the iterations at beta = 128 (or
+    max_iters). Host clock around the iterations; one iteration is front end,
+    stimulus, recorded rollout, adjoint, transposes and Adam."""
+    from paper_2503_22767_amd import codesign as CD
+    inst = W.make_walker2d().instances[0]
+    p = dict(inst.params)
+    T, dt = p["n_steps"], p["dt"]
+    p.update(n_segments=T, seg_steps=1, periodic=0, mass_eps=mass_eps)
+    x0 = inst.x0
+    h = p["particle_volume"] ** 0.5
+    region = np.clip(((x0[:, 0] - x0[:, 0].min()) / np.ptp(x0[:, 0]) * 8).astype(np.int32), 0, 7)
+    cfg = CD.CoDesignConfig(radius=1.5 * h, b_max=0.15, f_min=2.0 / (T * dt), f_max=20.0 / (T * dt), br_max=0.5,
+                            lr=lr)
+    cd = CD.CoDesign([p], x0, cfg, region=region, n_regions=8, precision=4, seed=3)
+    out = dict(particles=len(x0), steps=T, regions=8, mass_eps=mass_eps, lr=cfg.lr, b_max=cfg.b_max,
+               br_max=cfg.br_max)
+    err = None
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while cd.iteration < max_iters:
+            try:
+                cd.step()
+            except M.MpmMagError as e:
+                err = f"iteration {cd.iteration} (beta {cd.beta:g}): {e}"
+                break
+            if cd.converged(at_final_beta=True):
+                break
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+    finally:
+        cd.close()
+    hist = cd.history
+    out.update(iterations=len(hist), converged=cd.converged(at_final_beta=True), final_beta=cd.betas[-1] if hist else None,
+               ms_per_iteration=round(el * 1e3 / max(1, len(hist)), 1), loss_first=hist[0] if hist else None,
+               loss_last=hist[-1] if hist else None, error=err,
+               loss_every_10=[float(f"{v:.4g}") for v in hist[::10]])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -430,6 +475,11 @@ def main():
                     help="checkpoint budget of the recorded rollout in GB (1e9 bytes): checkpoints, segment "
                          "stash, grid ring and grid stores; 0: no bound")
     ap.add_argument("--no-unbounded", action="store_true", help="skip the leg without a checkpoint budget")
+    ap.add_argument("--no-walker-codesign", action="store_true",
+                    help="skip the walker co-design run through beta = 128 to convergence")
+    ap.add_argument("--walker-codesign-only", action="store_true", help="run only the walker co-design leg")
+    ap.add_argument("--walker-max-iters", type=int, default=400)
+    ap.add_argument("--walker-lr", type=float, default=0.01)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not built.",
@@ -456,6 +506,11 @@ def main():
         opts[k] = int(v)
     log(f"[bench] workload {wl.name}: {wl.description}; {len(wl.instances)} instance(s), "
         f"N={wl.n_particles}, T={wl.n_steps}")
+    if args.walker_codesign_only:
+        wc = walker_codesign(args.walker_max_iters, lr=args.walker_lr)
+        log(f"[bench] walker co-design {wc}")
+        print(json.dumps(dict(walker_codesign=wc)), flush=True)
+        return
     if args.front_end_only:
         fe = front_end(wl)
         log(f"[bench] front end {fe}")
@@ -537,6 +592,9 @@ def main():
         if cd is not None:
             rec["codesign"] = cd
             log(f"[bench] co-design {cd}")
+    if not args.no_walker_codesign:
+        rec["walker_codesign"] = walker_codesign(args.walker_max_iters, lr=args.walker_lr)
+        log(f"[bench] walker co-design {rec['walker_codesign']}")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         cb, insts, grads = cpu_baseline(wl.name, wl)

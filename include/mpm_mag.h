@@ -115,6 +115,8 @@ typedef struct {
                                   sweep (checkpoints, segment stash, grid ring, grid stores);
                                   0: no bound. The handle takes the smallest positive value
                                   over its instances (or the "ckpt_budget" option).        */
+    double mass_eps;         /* floor of the mass interpolation for void particles, in [0, 1]:
+                                m_p = (mass_eps + (1 - mass_eps) phi_p) rho V_p; 0 is Eq. 33  */
 } mpm_mag_instance_desc;
 
 /*

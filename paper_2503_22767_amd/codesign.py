@@ -138,6 +138,7 @@ class CoDesign:
         self.v = {k: torch.zeros_like(t) for k, t in self.var.items()}
         self.dloss = torch.ones(L, dtype=self.dtype, device=dev)
         self.history: List[float] = []
+        self.betas: List[float] = []     # the sharpness each history entry was taken at
         self.iteration = 0
 
     @property
@@ -176,11 +177,18 @@ class CoDesign:
             adam_step(self.var[k], g, self.m[k], self.v[k], t, self.cfg.lr, lo, hi)
         total = float(loss.double().sum())
         self.history.append(total)
+        self.betas.append(self.beta)
         self.iteration += 1
         return total
 
-    def converged(self) -> bool:
-        return converged(self.history)
+    def converged(self, at_final_beta: bool = False) -> bool:
+        """The paper's convergence rule over the loss history; with
+        at_final_beta, over the iterations taken at the capped sharpness only
+        (the loss moves each time beta rises)."""
+        if not at_final_beta:
+            return converged(self.history)
+        k = next((i for i, b in enumerate(self.betas) if b >= self.cfg.beta_max), None)
+        return k is not None and converged(self.history[k:])
 
     def close(self):
         self.fe.close()

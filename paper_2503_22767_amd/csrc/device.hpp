@@ -54,7 +54,8 @@ struct InstDev {
     int trace_off;                       // first node of the instance in a branch trace step
     real dx, inv_dx, dt, kappa_vol;      // kappa_vol = 4 dt / dx^2 * V
     real lam;                            // 4 / dx^2
-    real G, K, mass_p;                   // mass_p = rho V (m = phi mass_p)
+    real G, K;
+    real mass_a, mass_b;                 // particle mass m = mass_a + mass_b phi (Eq. 33 with its floor)
     real inv_mu0, simp_eps, simp_q, damp; // damp = 1 - c dt
     real gdt[3];                         // g dt
     real floor_mu;

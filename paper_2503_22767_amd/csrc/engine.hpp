@@ -155,7 +155,9 @@ public:
             I.lam = (real)(4.0 / (dx * dx));
             I.G = (real)(d.E / (2.0 * (1.0 + d.nu)));
             I.K = (real)(d.E / (3.0 * (1.0 - 2.0 * d.nu)));
-            I.mass_p = (real)(d.rho * d.particle_volume);
+            if (!(d.mass_eps >= 0.0 && d.mass_eps <= 1.0)) return fail(MPM_MAG_EINVAL, "mass_eps must be in [0, 1]");
+            I.mass_a = (real)(d.mass_eps * d.rho * d.particle_volume);
+            I.mass_b = (real)((1.0 - d.mass_eps) * d.rho * d.particle_volume);
             I.inv_mu0 = (real)(1.0 / d.mu0);
             I.simp_eps = (real)d.simp_eps;
             I.simp_q = (real)d.simp_q;

@@ -879,7 +879,7 @@ __device__ __forceinline__ void p2g_terms(const InstDev<real>& I, const Particle
     T.sm = pq;
     T.dse = (real(1) - I.simp_eps) * dpq;
     T.dsm = dpq;
-    T.m = phi * I.mass_p;
+    T.m = I.mass_a + phi * I.mass_b;
     elastic_stress<real, D>(q.F, I.G, I.K, T.Pe, T.ctx);
 #pragma unroll
     for (int i = 0; i < D; ++i)
@@ -1597,7 +1597,7 @@ __device__ __forceinline__ void traj_accumulate(const Args<real>& a, const InstD
         real ve = 0;
 #pragma unroll
         for (int r = 0; r < D; ++r) ve += I.loss_dir[r] * q.v[r];
-        traj = (double)(a.phi[i] * I.mass_p) * (double)ve;
+        traj = (double)(I.mass_a + a.phi[i] * I.mass_b) * (double)ve;
     }
     double v1[1] = {traj};
     block_sum<1>(v1);
@@ -1723,7 +1723,7 @@ __global__ __launch_bounds__(kBlock) void k_loss_sums(Args<real> a, const real* 
     const int64_t S = a.nalloc;
     double v[5] = {0, 0, 0, 0, 0};
     if (t < ch.count) {
-        double m = (double)a.phi[i] * (double)I.mass_p;
+        double m = (double)I.mass_a + (double)a.phi[i] * (double)I.mass_b;
         int mk = mask ? mask[i] : 1;
         double de = 0, sq = 0;
 #pragma unroll
@@ -1790,7 +1790,7 @@ __global__ __launch_bounds__(kBlock) void k_seed(Args<real> a, const real* st, r
     const double dl = (double)dloss[ch.inst];
     const double M = acc[kAccMass];
     const double L = a.loss_val[ch.inst];
-    const double m = (double)a.phi[i] * (double)I.mass_p;
+    const double m = (double)I.mass_a + (double)a.phi[i] * (double)I.mass_b;
     const int mk = mask ? mask[i] : 1;
     double gphi = 0, de = 0;
     real xb[D];
@@ -1811,7 +1811,7 @@ __global__ __launch_bounds__(kBlock) void k_seed(Args<real> a, const real* st, r
         xb[k] = (real)s;
     }
     if (I.loss_kind == kComDisp || I.loss_kind == kTrajVel)
-        gphi = dl * (double)I.mass_p * (-de / M - L / M);
+        gphi = dl * (double)I.mass_b * (-de / M - L / M);
 #pragma unroll
     for (int c = 0; c < Cp::NC; ++c) adj[c * S + i] = real(0);
 #pragma unroll
@@ -1861,7 +1861,8 @@ __device__ __forceinline__ void g2p_adj_phase(const Args<real>& a, const InstDev
         load_xF<real, D>(st, a.x0s, S, i, x, F);
         if (I.loss_kind == kTrajVel) {
             const double M = a.acc[inst * kAccCount + kAccMass];
-            const double sc = -(double)dloss[inst] * (double)I.dt * (double)a.phi[i] * (double)I.mass_p / M;
+            const double sc = -(double)dloss[inst] * (double)I.dt *
+                              ((double)I.mass_a + (double)a.phi[i] * (double)I.mass_b) / M;
 #pragma unroll
             for (int k = 0; k < D; ++k) A1.v[k] += (real)(sc * (double)I.loss_dir[k]);
         }
@@ -2286,7 +2287,7 @@ __device__ __forceinline__ void p2g_adj_phase(const Args<real>& a, const InstDev
                 PbBBr += Pb[r][c] * B[r] * br[c];
             }
         }
-        real gphi = I.mass_p * mb + T.dse * PbPe - T.dsm * I.inv_mu0 * PbBBr;
+        real gphi = I.mass_b * mb + T.dse * PbPe - T.dsm * I.inv_mu0 * PbBBr;
         a.gphi[i] += gphi;
 #pragma unroll
         for (int k = 0; k < D; ++k) {

@@ -51,7 +51,7 @@ class InstanceDesc(C.Structure):
         ("particle_volume", C.c_double), ("n_segments", C.c_int), ("seg_steps", C.c_int),
         ("periodic", C.c_int), ("loss_kind", C.c_int), ("loss_dir", C.c_double * 3),
         ("ckpt_every", C.c_int), ("n_obstacles", C.c_int), ("obstacles", ObstacleDesc * MAX_OBSTACLES),
-        ("ckpt_budget_bytes", C.c_int64),
+        ("ckpt_budget_bytes", C.c_int64), ("mass_eps", C.c_double),
     ]
 
 

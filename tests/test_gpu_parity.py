@@ -186,3 +186,24 @@ def test_fp32_mixed_density_chunks_match_oracle(dim):
     ev = np.max(np.abs(got["x"][void] - rep["x"][void]))
     log(f"  void particles' positions: max error {ev:.2e}")
     assert ev <= 1e-4
+
+
+@pytest.mark.parametrize("precision", [8, 4])
+def test_mass_floor_matches_oracle(precision):
+    """The mass floor of void particles (m = (eps_m + (1 - eps_m) phi) rho V,
+    eps_m = 1e-2) on a block whose right half is nearly void (phi = 1e-3):
+    positions and gradients against the oracle, FP64 at 1e-10 / 1e-9 and FP32
+    at 1e-4 / 1e-3 on the device's branch decisions."""
+    from gpu_util import compare_on_device_branches
+    inst = W.make_tiny(seed=95, dim=2, n_steps=40, loss_kind=W.LOSS_COM_DISP, floor=True, gravity=1.0,
+                       size=(0.4, 0.2, 0.2), n_grid=32, n_segments=4)
+    dens = np.where(inst.x0[:, 0] > np.median(inst.x0[:, 0]), 1e-3, 1.0)
+    p = dict(inst.params, mass_eps=1e-2)
+    blk = W.Instance(p, inst.x0, dens, inst.br, inst.b_prog, inst.target, inst.mask)
+    if precision == 8:
+        compare(gpu_run([blk], precision=8), oracle_run([blk]), pos_tol=1e-10, grad_tol=1e-9, loss_tol=1e-9,
+                label="mass floor fp64")
+    else:
+        got = gpu_run([blk], precision=4, trace=True)
+        compare_on_device_branches(got, oracle_run([blk], record=True), oracle_run([blk], replay=got["trace"]),
+                                   pos_tol=1e-4, grad_tol=1e-3, label="mass floor fp32")
