@@ -722,20 +722,27 @@ __device__ __forceinline__ NodeBox<D> stage_nodes(const InstDev<real>& I, bool a
     return nb;
 }
 
-// record of stencil node (base + a): from the staged box when there is one
-template <typename real, int D>
-__device__ __forceinline__ const real* node_rec(const NodeBox<D>& nb, const real* lds, const real* src,
-                                                const int base[D], const int a[D], int n)
+__device__ constexpr int kZero3[3] = {0, 0, 0};
+
+// Calls body(g0, sy, sz) with the record of the particle's first stencil node
+// and the strides (values) of one node step along y and z: in the staged box
+// when there is one, else in the instance grid. The two calls are separate
+// instantiations, so the staged one reads with LDS instructions rather than
+// generic (flat) loads, and every node of a stencil row sits at a constant
+// offset (4, 8) from the row's first.
+template <typename real, int D, typename Body>
+__device__ __forceinline__ void with_stencil_rows(const NodeBox<D>& nb, const real* lds, const real* src,
+                                                  const int base[D], int n, Body body)
 {
     if (nb.staged) {
-        int l = (base[0] + a[0] - nb.lo[0]) +
-                nb.ext[0] * ((base[1] + a[1] - nb.lo[1]) + (D == 3 ? nb.ext[1] * (base[D - 1] + a[D - 1] - nb.lo[D - 1]) : 0));
-        return lds + 4 * l;
+        const int l = (base[0] - nb.lo[0]) +
+                      nb.ext[0] * ((base[1] - nb.lo[1]) + (D == 3 ? nb.ext[1] * (base[D - 1] - nb.lo[D - 1]) : 0));
+        body(lds + 4 * l, 4 * nb.ext[0], 4 * nb.ext[0] * nb.ext[1]);
+    } else {
+        body(src + 4 * ((int64_t)base[0] + (int64_t)n * (base[1] + (D == 3 ? (int64_t)n * base[D - 1] : 0))), 4 * n,
+             4 * n * n);
     }
-    return src + 4 * ((int64_t)(base[0] + a[0]) + (int64_t)n * ((base[1] + a[1]) + (D == 3 ? (int64_t)n * (base[D - 1] + a[D - 1]) : 0)));
 }
-
-__device__ constexpr int kZero3[3] = {0, 0, 0};
 
 template <typename real, int D>
 __device__ __forceinline__ int64_t node_index(const int base[D], const int a[D], int n)
@@ -1904,51 +1911,58 @@ __device__ __forceinline__ void g2p_adj_phase(const Args<real>& a, const InstDev
     // (the last term is lam Cbt^T v', with v' = sum w v_i the velocity of
     // state n+1)
     if (active) {
-        // lam Cbt, and dpos_x of the three x offsets
-        real lC[D][D], d0[3];
+        // lam Cbt, and dpos_x and the x factors of the weights of the three
+        // x offsets (the weights factor as in the P2G transpose)
+        real lC[D][D], d0[3], wx[3], dwx[3];
 #pragma unroll
         for (int r = 0; r < D; ++r)
 #pragma unroll
             for (int c = 0; c < D; ++c) lC[r][c] = lam * Cbt[r][c];
 #pragma unroll
-        for (int a0 = 0; a0 < 3; ++a0) d0[a0] = (real(a0) - Sx.f[0]) * dx;
+        for (int a0 = 0; a0 < 3; ++a0) {
+            d0[a0] = (real(a0) - Sx.f[0]) * dx;
+            wx[a0] = Sx.w[0][a0];
+            dwx[a0] = Sx.dw[0][a0];
+        }
+        with_stencil_rows<real, D>(nbx, glds, gv, Sx.base, I.n_grid, [&](const real* g0, int sy, int sz) {
 #pragma unroll 1
-        for (int a2 = 0; a2 < (D == 3 ? 3 : 1); ++a2)
+            for (int a2 = 0; a2 < (D == 3 ? 3 : 1); ++a2)
 #pragma unroll 1
-            for (int a1 = 0; a1 < 3; ++a1) {
-                const real d1 = (real(a1) - Sx.f[1]) * dx;
-                const real d2 = D == 3 ? (real(a2) - Sx.f[D - 1]) * dx : real(0);
-                const real wz = D == 3 ? sel3(Sx.w[D - 1], a2) : real(1);
-                const real dwz = D == 3 ? sel3(Sx.dw[D - 1], a2) : real(0);
-                const real wy = sel3(Sx.w[1], a1), dwy = sel3(Sx.dw[1], a1);
-                const real wyz = wy * wz, dwyz = dwy * wz, wydz = wy * dwz;
-                real h[D];   // u_i = vbt + lam Cbt dpos_i without its x term
+                for (int a1 = 0; a1 < 3; ++a1) {
+                    const real* row = g0 + sy * a1 + (D == 3 ? sz * a2 : 0);
+                    const real d1 = (real(a1) - Sx.f[1]) * dx;
+                    const real d2 = D == 3 ? (real(a2) - Sx.f[D - 1]) * dx : real(0);
+                    const real wz = D == 3 ? sel3(Sx.w[D - 1], a2) : real(1);
+                    const real dwz = D == 3 ? sel3(Sx.dw[D - 1], a2) : real(0);
+                    const real wy = sel3(Sx.w[1], a1), dwy = sel3(Sx.dw[1], a1);
+                    const real wyz = wy * wz, dwyz = dwy * wz, wydz = wy * dwz;
+                    real h[D];   // u_i = vbt + lam Cbt dpos_i without its x term
 #pragma unroll
-                for (int r = 0; r < D; ++r) {
-                    real u = vbt[r];
-                    if (D == 3) u += lC[r][D - 1] * d2;
-                    h[r] = u + lC[r][1] * d1;
+                    for (int r = 0; r < D; ++r) {
+                        real u = vbt[r];
+                        if (D == 3) u += lC[r][D - 1] * d2;
+                        h[r] = u + lC[r][1] * d1;
+                    }
+                    real cdx = 0, cwx = 0;   // row sums of (v_i . u_i) dwx and (v_i . u_i) wx
+#pragma unroll
+                    for (int a0 = 0; a0 < 3; ++a0) {
+                        real vi[D];
+                        load_vec<real, D>(row + 4 * a0, vi);
+                        real vh = 0, vc = 0;
+#pragma unroll
+                        for (int r = 0; r < D; ++r) {
+                            vh += vi[r] * h[r];
+                            vc += vi[r] * lC[r][0];
+                        }
+                        const real vu = vh + d0[a0] * vc;
+                        cdx += vu * dwx[a0];
+                        cwx += vu * wx[a0];
+                    }
+                    xb[0] += wyz * cdx;
+                    xb[1] += dwyz * cwx;
+                    if (D == 3) xb[D - 1] += wydz * cwx;
                 }
-#pragma unroll
-                for (int a0 = 0; a0 < 3; ++a0) {
-                    int oa[D];
-                    oa[0] = a0;
-                    oa[1] = a1;
-                    if (D == 3) oa[D - 1] = a2;
-                    const real wx = Sx.w[0][a0], dwx = Sx.dw[0][a0];
-                    real gw[D];
-                    gw[0] = dwx * wyz;
-                    gw[1] = wx * dwyz;
-                    if (D == 3) gw[D - 1] = wx * wydz;
-                    real vi[D];
-                    load_vec<real, D>(node_rec<real, D>(nbx, glds, gv, Sx.base, oa, I.n_grid), vi);
-                    real vu = 0;
-#pragma unroll
-                    for (int r = 0; r < D; ++r) vu += vi[r] * (h[r] + lC[r][0] * d0[a0]);
-#pragma unroll
-                    for (int r = 0; r < D; ++r) xb[r] += vu * gw[r];
-                }
-            }
+        });
         real v1[D];
 #pragma unroll
         for (int r = 0; r < D; ++r) v1[r] = st_next[(Cp::V + r) * S + i];
@@ -2178,68 +2192,80 @@ __device__ __forceinline__ void p2g_adj_phase(const Args<real>& a, const InstDev
 #pragma unroll
             for (int c = 0; c < D; ++c) Ab[r][c] = 0;
         }
-        // outer (z, y) offsets run-time, x offsets unrolled; sums over the
-        // three x nodes of a row are combined once per row
-        real d0[3];
+        // Outer (z, y) offsets run-time, x offsets unrolled. Every weight
+        // factors into its x part and its (y, z) part, so the three nodes of a
+        // row sum with their x factors only and the (y, z) factor multiplies
+        // the row sums once: xb += coef grad w splits into
+        // wyz sum coef dwx, dwyz sum coef wx and wydz sum coef wx.
+        real d0[3], wx[3], dwx[3], wd0[3];
 #pragma unroll
-        for (int a0 = 0; a0 < 3; ++a0) d0[a0] = (real(a0) - Sx.f[0]) * I.dx;
+        for (int a0 = 0; a0 < 3; ++a0) {
+            d0[a0] = (real(a0) - Sx.f[0]) * I.dx;
+            wx[a0] = Sx.w[0][a0];
+            dwx[a0] = Sx.dw[0][a0];
+            wd0[a0] = wx[a0] * d0[a0];
+        }
+        with_stencil_rows<real, D>(nbx, lds, gsrc, Sx.base, I.n_grid, [&](const real* g0, int sy, int sz) {
 #pragma unroll 1
-        for (int a2 = 0; a2 < (D == 3 ? 3 : 1); ++a2)
+            for (int a2 = 0; a2 < (D == 3 ? 3 : 1); ++a2)
 #pragma unroll 1
-            for (int a1 = 0; a1 < 3; ++a1) {
-                const real d1 = (real(a1) - Sx.f[1]) * I.dx;
-                const real d2 = D == 3 ? (real(a2) - Sx.f[D - 1]) * I.dx : real(0);
-                const real wz = D == 3 ? sel3(Sx.w[D - 1], a2) : real(1);
-                const real dwz = D == 3 ? sel3(Sx.dw[D - 1], a2) : real(0);
-                const real wy = sel3(Sx.w[1], a1), dwy = sel3(Sx.dw[1], a1);
-                const real wyz = wy * wz, dwyz = dwy * wz, wydz = wy * dwz;
-                real h[D];   // m v + A dpos without its x term
-#pragma unroll
-                for (int r = 0; r < D; ++r) {
-                    real u = mv[r];
-                    if (D == 3) u += T.A[r][D - 1] * d2;
-                    h[r] = u + T.A[r][1] * d1;
-                }
-                real U[D], V[D];   // row sums of w pbar and of w dpos_x pbar
-#pragma unroll
-                for (int r = 0; r < D; ++r) U[r] = V[r] = real(0);
-#pragma unroll
-                for (int a0 = 0; a0 < 3; ++a0) {
-                    int oa[D];
-                    oa[0] = a0;
-                    oa[1] = a1;
-                    if (D == 3) oa[D - 1] = a2;
-                    const real wx = Sx.w[0][a0], dwx = Sx.dw[0][a0];
-                    const real w = wx * wyz;
-                    real gw[D];
-                    gw[0] = dwx * wyz;
-                    gw[1] = wx * dwyz;
-                    if (D == 3) gw[D - 1] = wx * wydz;
-                    const real* nd = node_rec<real, D>(nbx, lds, gsrc, Sx.base, oa, I.n_grid);
-                    real pb[D];
-                    load_vec<real, D>(nd, pb);
-                    const real mbi = nd[3];
-                    real pmom = 0;
-#pragma unroll
-                    for (int r = 0; r < D; ++r) pmom += pb[r] * (h[r] + T.A[r][0] * d0[a0]);
-                    const real coef = mbi * T.m + pmom;
-                    smb += w * mbi;
-                    const real wd = w * d0[a0];
+                for (int a1 = 0; a1 < 3; ++a1) {
+                    const real* row = g0 + sy * a1 + (D == 3 ? sz * a2 : 0);
+                    const real d1 = (real(a1) - Sx.f[1]) * I.dx;
+                    const real d2 = D == 3 ? (real(a2) - Sx.f[D - 1]) * I.dx : real(0);
+                    const real wz = D == 3 ? sel3(Sx.w[D - 1], a2) : real(1);
+                    const real dwz = D == 3 ? sel3(Sx.dw[D - 1], a2) : real(0);
+                    const real wy = sel3(Sx.w[1], a1), dwy = sel3(Sx.dw[1], a1);
+                    const real wyz = wy * wz, dwyz = dwy * wz, wydz = wy * dwz;
+                    real h[D];   // m v + A dpos without its x term
 #pragma unroll
                     for (int r = 0; r < D; ++r) {
-                        xb[r] += coef * gw[r];
-                        U[r] += w * pb[r];
-                        V[r] += wd * pb[r];
+                        real u = mv[r];
+                        if (D == 3) u += T.A[r][D - 1] * d2;
+                        h[r] = u + T.A[r][1] * d1;
+                    }
+                    // row sums with the x factors of the weights
+                    real cdx = 0, cwx = 0, smw = 0, U[D], V[D];
+#pragma unroll
+                    for (int r = 0; r < D; ++r) U[r] = V[r] = real(0);
+#pragma unroll
+                    for (int a0 = 0; a0 < 3; ++a0) {
+                        const real* nd = row + 4 * a0;
+                        real pb[D];
+                        load_vec<real, D>(nd, pb);
+                        const real mbi = nd[3];
+                        // pb . (h + A[:, 0] dpos_x), as two dots so no product
+                        // of A with the x offsets has to stay live
+                        real ph = 0, pa = 0;
+#pragma unroll
+                        for (int r = 0; r < D; ++r) {
+                            ph += pb[r] * h[r];
+                            pa += pb[r] * T.A[r][0];
+                        }
+                        const real coef = mbi * T.m + (ph + d0[a0] * pa);
+                        cdx += coef * dwx[a0];
+                        cwx += coef * wx[a0];
+                        smw += wx[a0] * mbi;
+#pragma unroll
+                        for (int r = 0; r < D; ++r) {
+                            U[r] += wx[a0] * pb[r];
+                            V[r] += wd0[a0] * pb[r];
+                        }
+                    }
+                    xb[0] += wyz * cdx;
+                    xb[1] += dwyz * cwx;
+                    if (D == 3) xb[D - 1] += wydz * cwx;
+                    smb += wyz * smw;
+#pragma unroll
+                    for (int r = 0; r < D; ++r) {
+                        const real uw = wyz * U[r];
+                        S0[r] += uw;
+                        Ab[r][0] += wyz * V[r];
+                        Ab[r][1] += d1 * uw;
+                        if (D == 3) Ab[r][D - 1] += d2 * uw;
                     }
                 }
-#pragma unroll
-                for (int r = 0; r < D; ++r) {
-                    S0[r] += U[r];
-                    Ab[r][0] += V[r];
-                    Ab[r][1] += d1 * U[r];
-                    if (D == 3) Ab[r][D - 1] += d2 * U[r];
-                }
-            }
+        });
         real mb = smb + ddot<real, D>(Ab, q.C), vb[D];
 #pragma unroll
         for (int r = 0; r < D; ++r) {
