@@ -5,6 +5,7 @@ The knobs are options of the library:
   box_cap     largest per-block LDS staging box before per-wave boxes
   grid_wgs    workgroups of the grid kernels (they stride over active blocks)
   grid_threads threads per workgroup of the grid kernels (0: by stream count)
+  grid_parts  workgroups sharing one coarse block in the grid kernels (0: by stream count)
   graph       replay of captured HIP graphs instead of direct launches
   p2g_lds     LDS-staged scatter vs direct global atomics
   fuse_fwd    G2P of one step and P2G of the next in one kernel, or two
@@ -35,7 +36,7 @@ import time
 from typing import Callable, Dict, List, Sequence, Tuple
 
 DEFAULTS: Dict[str, int] = dict(sort_curve=0, box_cap=1024, grid_wgs=2048, graph=0, p2g_lds=1, fuse_fwd=1,
-                                fuse_adj=1, streams=0, grid_threads=0)
+                                fuse_adj=1, streams=0, grid_threads=0, grid_parts=0)
 SPACE: Dict[str, List[int]] = dict(
     sort_curve=[0, 1, 2],
     box_cap=[256, 512, 1024],
@@ -46,6 +47,7 @@ SPACE: Dict[str, List[int]] = dict(
     fuse_adj=[1, 0],
     streams=[0, 1, 2, 4],
     grid_threads=[0, 256, 512, 1024],
+    grid_parts=[0, 1, 2, 4],
 )
 CACHE_ENV = "MPM_MAG_TUNE_CACHE"
 

@@ -317,6 +317,13 @@ public:
             ++plan_gen_;   // baked into captured launches
             return MPM_MAG_OK;
         }
+        if (k == "grid_parts") {
+            if (value != 0 && (value < 1 || value > 8 || (value & (value - 1))))
+                return fail(MPM_MAG_EINVAL, "grid_parts must be 0, 1, 2, 4 or 8");
+            grid_parts_ = (int)value;
+            ++plan_gen_;   // baked into captured launches
+            return MPM_MAG_OK;
+        }
         if (k == "grid_store") {
             if (value < -1 || value > ((int64_t)1 << 30)) return fail(MPM_MAG_EINVAL, "grid_store must be -1, 0 or MiB");
             gs_budget_mib_ = value;   // applied at the next recorded rollout
@@ -371,6 +378,7 @@ public:
         MPM_HIP(hipMemsetAsync(acc_, 0, sizeof(double) * kAccCount * n_inst_, s));
         MPM_HIP(hipMemsetAsync(gm_, 0, sizeof(real) * 4 * G_, s));
         MPM_HIP(hipMemsetAsync(reg_count_, 0, sizeof(int) * n_cb_, s));
+        MPM_HIP(hipMemsetAsync(part_done_, 0, sizeof(int) * n_cb_, s));
         MPM_HIP(hipMemsetAsync(fb_used_, 0, sizeof(int) * n_cb_, s));
         MPM_HIP(hipMemsetAsync(active_, 0, sizeof(int) * 4 * kMaxChains, s));
         MPM_HIP(hipMemcpyAsync(bprog_, b_prog, sizeof(real) * S_tot_ * D, hipMemcpyDeviceToDevice, s));
@@ -613,6 +621,9 @@ private:
     int grid_threads() const { return grid_threads_ > 0 ? grid_threads_ : (n_chains() > 1 ? 256 : kGridThreadsMax); }
 
     int grid_blocks_of(int q) const { return (int)std::min<int64_t>(chains_[q].ncb, grid_wgs_); }
+    // workgroups sharing one coarse block in the grid gathers
+    int grid_parts() const { return grid_parts_ > 0 ? grid_parts_ : (n_chains() > 1 ? 2 : 1); }
+    int gather_blocks_of(int q) const { return (int)std::min<int64_t>(chains_[q].ncb * grid_parts(), grid_wgs_); }
 
     // copy of the chain's particle state (all components) from src to dst
     int copy_state(int q, hipStream_t cs, real* dst, const real* src)
@@ -645,7 +656,7 @@ private:
             r = launch(K_P2G, cs, nc, kBlock, k_p2g<real, D>, a, (const real*)st_, n, lf(n));
             if (r) return r;
         }
-        r = launch(K_GRID, cs, grid_blocks_of(q), grid_threads(), k_grid<real, D>, a, gv_, (real*)nullptr, lf(n),
+        r = launch(K_GRID, cs, gather_blocks_of(q), grid_threads(), k_grid<real, D>, a, gv_, (real*)nullptr, lf(n),
                    store_of(q, n, record));
         if (r) return r;
         if (n + 1 < T_ && fuse_fwd_) {
@@ -687,7 +698,7 @@ private:
         }
         // the step's grid goes to the dense ring for this pass and to the
         // segment store for the transposed steps
-        r = launch(K_GRID, cs, grid_blocks_of(q), grid_threads(), k_grid<real, D>, a, gv_slot(j), gm_slot(j), lf(n),
+        r = launch(K_GRID, cs, gather_blocks_of(q), grid_threads(), k_grid<real, D>, a, gv_slot(j), gm_slot(j), lf(n),
                    seg_store_of(q, j, n));
         if (r) return r;
         if (n + 1 >= s1) return MPM_MAG_OK;
@@ -739,7 +750,7 @@ private:
         Args<real> a = args_of(q);
         const int nc = chains_[q].nc;
         const int s0 = c * K_, s1 = std::min(T_, s0 + K_), j = n - s0;
-        int r = launch(K_GRID_ADJ, cs, grid_blocks_of(q), grid_threads(), k_grid_adj<real, D>, a, (const real*)gm_slot(j),
+        int r = launch(K_GRID_ADJ, cs, gather_blocks_of(q), grid_threads(), k_grid_adj<real, D>, a, (const real*)gm_slot(j),
                        gpm_, lst(n), n);
         if (r) return r;
         // the G2P transpose of step n - 1 needs its grid: the ring still holds
@@ -821,6 +832,8 @@ private:
         a.part = part_;
         a.box = box_;
         a.reg_count = reg_count_;
+        a.part_done = part_done_;
+        a.grid_parts = grid_parts();
         a.reg_list = reg_list_;
         a.fb_used = fb_used_;
         a.cb_inst = cb_inst_d_;
@@ -1401,6 +1414,7 @@ private:
         st |= dalloc(&part_, (size_t)n_chunks_ * kBoxCap * 4);
         st |= dalloc(&box_, (size_t)n_chunks_ * kWaves * 2);
         st |= dalloc(&reg_count_, (size_t)n_cb_);
+        st |= dalloc(&part_done_, (size_t)n_cb_);
         st |= dalloc(&reg_list_, (size_t)n_cb_ * Coarse<D>::cap);
         st |= dalloc(&fb_used_, (size_t)n_cb_);
         st |= dalloc(&cb_inst_d_, (size_t)n_cb_);
@@ -1433,6 +1447,7 @@ private:
                           hipMemcpyHostToDevice));
         MPM_HIP(hipMemcpy(cb_inst_d_, cb_inst_h_.data(), sizeof(int) * cb_inst_h_.size(), hipMemcpyHostToDevice));
         MPM_HIP(hipMemset(reg_count_, 0, sizeof(int) * n_cb_));
+        MPM_HIP(hipMemset(part_done_, 0, sizeof(int) * n_cb_));
         MPM_HIP(hipMemset(fb_used_, 0, sizeof(int) * n_cb_));
         MPM_HIP(hipMemset(active_, 0, sizeof(int) * 4 * kMaxChains));
         MPM_HIP(hipMemset(gm_, 0, sizeof(real) * 4 * G_));
@@ -1520,6 +1535,7 @@ private:
     real* part_ = nullptr;
     int4* box_ = nullptr;
     int* reg_count_ = nullptr;
+    int* part_done_ = nullptr;
     int* reg_list_ = nullptr;
     int* fb_used_ = nullptr;
     int* cb_inst_d_ = nullptr;
@@ -1574,7 +1590,7 @@ private:
     bool recorded_ = false, has_target_ = false;
     // options
     bool graph_ = false, timing_ = false, use_lds_ = true;
-    int box_cap_ = kBoxCap, grid_wgs_ = 2048, grid_threads_ = 0;
+    int box_cap_ = kBoxCap, grid_wgs_ = 2048, grid_threads_ = 0, grid_parts_ = 0;
     bool fuse_adj_ = true, fuse_fwd_ = true, lane_sort_ = true;
     std::vector<hipEvent_t> events_;
     size_t ev_used_ = 0;

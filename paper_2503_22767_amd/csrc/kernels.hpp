@@ -87,6 +87,7 @@ struct Args {
     int* reg_count;      // [n_coarse] boxes registered with each coarse block this phase
     int* reg_list;       // [n_coarse][cap] chunk ids
     int* fb_used;        // [n_coarse] nonzero when the dense fallback accumulator holds values of the block
+    int* part_done;      // [n_coarse] parts of the block whose gather has finished (grid kernels)
     const int* cb_inst;  // [n_coarse] instance of each coarse block
     int* active;         // [4]: coarse blocks activated per scatter list (P2G: 0, 3; G2P transpose: 1, 2)
     int* active_list;    // [4][n_coarse]
@@ -94,6 +95,7 @@ struct Args {
     int use_lds;
     int chunk_base;      // first chunk of the launch (launches may cover a range of instances)
     int box_cap;         // largest block staging box (nodes, <= kBoxCap)
+    int grid_parts;      // workgroups sharing one coarse block in the grid kernels (slabs along its last axis)
     const uint8_t* lperm;  // [nalloc]: lane t of chunk c works on slot c * kBlock + lperm[c * kBlock + t]
     uint16_t* trace;       // [n_steps][trace_nodes] branch decisions of the grid update, or nullptr
     int64_t trace_nodes;   // nodes of all instances (sum of n_grid^D)
@@ -505,15 +507,18 @@ __device__ __forceinline__ void scatter_box(const Args<real>& a, const InstDev<r
     }
 }
 
-// Gathers the boxes registered with coarse block b into the records of its
-// nodes (plus the dense fallback accumulator fb, which is cleared), then calls
-// node_fn(global node index, grid coords, summed[4]) for every node of the block
-// inside the grid and resets the registration count. The (box, node) pairs of
-// all registered boxes are enumerated flat across the workgroup so their loads
-// are independent; sums go through LDS in double.
+// Gathers the boxes registered with coarse block b into the records of the
+// nodes of its slab `part` (of a.grid_parts slabs along the block's last axis),
+// plus the dense fallback accumulator fb, which is cleared, then calls
+// node_fn(global node index, grid coords, block-local index, summed[4]) for
+// every node of the slab inside the grid. The (box, node) pairs of all
+// registered boxes are enumerated flat across the workgroup so their loads are
+// independent; sums go through LDS in double. The workgroups of one block's
+// slabs run independently (a heavy block's pairs no longer wait on one
+// workgroup); the last of them to finish resets the block's registration.
 template <typename real, int D, typename NodeFn>
-__device__ __forceinline__ void gather_coarse(const Args<real>& a, const InstDev<real>& I, int b, real* fb,
-                                              NodeFn node_fn)
+__device__ __forceinline__ void gather_coarse(const Args<real>& a, const InstDev<real>& I, int b, int part,
+                                              real* fb, NodeFn node_fn)
 {
     using CB = Coarse<D>;
     constexpr int U = 4;   // pairs in flight per thread
@@ -533,6 +538,15 @@ __device__ __forceinline__ void gather_coarse(const Args<real>& a, const InstDev
     const int lb = b - I.cb_off;
     const int bc[3] = {lb % I.nb, D == 3 ? (lb / I.nb) % I.nb : lb / I.nb, D == 3 ? lb / (I.nb * I.nb) : 0};
     int co[3] = {bc[0] * CB::edge, bc[1] * CB::edge, D == 3 ? bc[2] * CB::edge : 0};
+    // the slab: layers [sl0, sl0 + sl_n) of the last axis, block-local nodes [ln0, ln0 + n_slab)
+    const int sl_n = CB::edge / a.grid_parts, sl0 = part * sl_n;
+    const int n_slab = CB::nodes / a.grid_parts, ln0 = part * n_slab;
+    int clo[3], chi[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        clo[k] = k == D - 1 ? co[k] + sl0 : co[k];
+        chi[k] = k == D - 1 ? co[k] + sl0 + sl_n : co[k] + CB::edge;
+    }
     for (int j = t; j < cnt; j += blockDim.x) {
         const int id = a.reg_list[b * CB::cap + j];
         const int4 lo = a.box[2 * id], ex = a.box[2 * id + 1];
@@ -540,8 +554,8 @@ __device__ __forceinline__ void gather_coarse(const Args<real>& a, const InstDev
         int sz = 1;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            int l = k < D ? max(blo[k], co[k]) : 0;
-            int h = k < D ? min(blo[k] + bex[k], co[k] + CB::edge) : 1;
+            int l = k < D ? max(blo[k], clo[k]) : 0;
+            int h = k < D ? min(blo[k] + bex[k], chi[k]) : 1;
             int e = bex[k] > 0 ? max(0, h - l) : 0;
             s_ilo[j][k] = l;
             s_iext[j][k] = e;
@@ -553,7 +567,7 @@ __device__ __forceinline__ void gather_coarse(const Args<real>& a, const InstDev
         s_id[j] = id;
         s_off[j + 1] = sz;
     }
-    for (int i = t; i < CB::nodes; i += blockDim.x)
+    for (int i = ln0 + t; i < ln0 + n_slab; i += blockDim.x)
 #pragma unroll
         for (int q = 0; q < 4; ++q) s_acc[q][i] = 0.0;
     if (t == 0) s_off[0] = 0;
@@ -616,7 +630,7 @@ __device__ __forceinline__ void gather_coarse(const Args<real>& a, const InstDev
                 for (int q = 0; q < 4; ++q) atomicAdd(&s_acc[q][nl[u]], (double)v[u][q]);
     }
     __syncthreads();
-    for (int ln = t; ln < CB::nodes; ln += blockDim.x) {
+    for (int ln = ln0 + t; ln < ln0 + n_slab; ln += blockDim.x) {
         int g3[3];
         g3[0] = co[0] + ln % CB::edge;
         g3[1] = co[1] + (ln / CB::edge) % CB::edge;
@@ -638,8 +652,16 @@ __device__ __forceinline__ void gather_coarse(const Args<real>& a, const InstDev
     }
     __syncthreads();
     if (t == 0) {
-        a.reg_count[b] = 0;
-        if (fb_any) a.fb_used[b] = 0;
+        // every slab has consumed the registration (its loads have returned)
+        // before it counts itself done, so the last one may reset the block;
+        // the reset is read only by later kernels. Relaxed: an agent-scope
+        // release here would write back the L2 after every block.
+        const int done = __hip_atomic_fetch_add(&a.part_done[b], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (done == a.grid_parts - 1) {
+            a.part_done[b] = 0;
+            a.reg_count[b] = 0;
+            if (fb_any) a.fb_used[b] = 0;
+        }
     }
 }
 
@@ -1387,12 +1409,13 @@ void k_grid(Args<real> a, real* gv_out, real* gmd_out, int list, GridStore<real>
           gs.base[gs.idx + 1] = s1 < kStoreCountMax ? (int)s1 : kStoreCountMax;
       }
   }
-  for (int ai = blockIdx.x; ai < n_act; ai += gridDim.x) {
+  for (int wi = blockIdx.x; wi < n_act * a.grid_parts; wi += gridDim.x) {
+    const int ai = wi / a.grid_parts, part = wi - ai * a.grid_parts;
     const int b = a.active_list[list * a.n_coarse + ai];
     const InstDev<real>& I = a.inst[a.cb_inst[b]];
     real* keep = sbase >= 0 ? gs.data + (size_t)(sbase + ai) * Coarse<D>::nodes * 4 : nullptr;
-    if (keep && threadIdx.x == 0) gs.blk[sbase + ai] = b;
-    gather_coarse<real, D>(a, I, b, a.gm, [&](int64_t g, const int g3[3], int ln, const real node[4]) {
+    if (keep && part == 0 && threadIdx.x == 0) gs.blk[sbase + ai] = b;
+    gather_coarse<real, D>(a, I, b, part, a.gm, [&](int64_t g, const int g3[3], int ln, const real node[4]) {
         real v[D];
         int code = 0;   // branch decisions (the layout of mpm_mag_set_branch_trace)
         if (node[3] > real(0)) {
@@ -2065,10 +2088,11 @@ __global__ __launch_bounds__(kGridThreadsMax) __attribute__((amdgpu_waves_per_eu
 void k_grid_adj(Args<real> a, const real* __restrict__ gmd_in, real* __restrict__ gpm_out, int list, int step)
 {
   const int n_act = a.active[list];
-  for (int ai = blockIdx.x; ai < n_act; ai += gridDim.x) {
+  for (int wi = blockIdx.x; wi < n_act * a.grid_parts; wi += gridDim.x) {
+    const int ai = wi / a.grid_parts, part = wi - ai * a.grid_parts;
     const int b = a.active_list[list * a.n_coarse + ai];
     const InstDev<real>& I = a.inst[a.cb_inst[b]];
-    gather_coarse<real, D>(a, I, b, a.gbar, [&](int64_t g, const int g3[3], int, const real vb[4]) {
+    gather_coarse<real, D>(a, I, b, part, a.gbar, [&](int64_t g, const int g3[3], int, const real vb[4]) {
         real node[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) node[q] = gmd_in[4 * g + q];

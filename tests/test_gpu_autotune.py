@@ -11,7 +11,8 @@ pytestmark = pytest.mark.gpu
 
 OPTION_CASES = [("sort_curve", 1), ("sort_curve", 2), ("box_cap", 64), ("box_cap", 256),
                 ("grid_wgs", 16), ("graph", 1), ("fuse_fwd", 0), ("fuse_adj", 0), ("streams", 2),
-                ("lane_sort", 0), ("grid_store", 0), ("grid_threads", 256), ("grid_threads", 384), ("grid_threads", 1024)]
+                ("lane_sort", 0), ("grid_store", 0), ("grid_threads", 256), ("grid_threads", 384), ("grid_threads", 1024),
+                ("grid_parts", 1), ("grid_parts", 2), ("grid_parts", 4), ("grid_parts", 8)]
 
 
 def _case(dim):

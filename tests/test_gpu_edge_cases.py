@@ -63,7 +63,7 @@ def _status_of(fn):
     return M.OK
 
 
-def test_grid_threads_option_is_validated():
+def test_grid_threads_and_parts_options_are_validated():
     inst = _block(3, 4, floor=False)
     sim = M.MpmMag([inst.params], [len(inst.x0)], precision=4)
     try:
@@ -71,6 +71,10 @@ def test_grid_threads_option_is_validated():
             assert _status_of(lambda: sim.set_option("grid_threads", bad)) == M.EINVAL, bad
         for good in (0, 256, 384, 512, 1024):
             sim.set_option("grid_threads", good)
+        for bad in (3, 5, 16, -1):
+            assert _status_of(lambda: sim.set_option("grid_parts", bad)) == M.EINVAL, bad
+        for good in (0, 1, 2, 4, 8):
+            sim.set_option("grid_parts", good)
     finally:
         sim.close()
 
