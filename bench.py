@@ -438,6 +438,9 @@ def walker_codesign(max_iters=400, mass_eps=1e-3, lr=0.01):
                 break
             if cd.converged(at_final_beta=True):
                 break
+            if cd.iteration % 100 == 0:
+                log(f"[bench] walker co-design iteration {cd.iteration}, beta {cd.beta:g}, loss {cd.history[-1]:.4g}, "
+                    f"{(time.perf_counter() - t0) / cd.iteration * 1e3:.1f} ms per iteration")
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
     finally:
@@ -538,9 +541,16 @@ def main():
         f"{(held - base_bytes) / 1e9:.2f} GB for the reverse sweep, budget {opts.get('ckpt_budget', 0) / 1e9:.1f} GB)")
     t_step = timed(lambda: run_step(sim, tens, dloss), args.steps)
     log(f"[bench] fwd+adj step {t_step * 1e3:.1f} ms")
+    scat_bwd = sim.scatter_stats()   # the last call was a backward
     t_fwd = timed(lambda: run_step(sim, tens, dloss, record=False, backward=False), max(1, args.steps))
     log(f"[bench] plain fwd {t_fwd * 1e3:.1f} ms")
     t_rec = timed(lambda: run_step(sim, tens, dloss, record=True, backward=False), 1)
+    # scatter fallbacks over the whole recorded rollout, against the block and
+    # wave scatters it ran (one P2G per step)
+    scat = dict(forward=sim.scatter_stats(), backward=scat_bwd,
+                forward_block_scatters=wl.n_steps * sum(-(-int(i.n) // 256) for i in wl.instances),
+                forward_wave_scatters=wl.n_steps * sum(-(-int(i.n) // 64) for i in wl.instances))
+    log(f"[bench] scatter fallbacks {scat}")
     ps = wl.particle_steps()
     rec = dict(metric=METRIC, value=round(ps / t_step, 1), unit="particle-steps/s", n_gpus=1,
                steps=args.steps, warmup=args.warmup, ms_per_step=round(t_step * 1e3, 3),
@@ -552,7 +562,7 @@ def main():
                fwd_value=round(ps / t_fwd, 1), fwd_ms=round(t_fwd * 1e3, 3),
                adj_over_fwd=round((t_step - t_rec) / t_fwd, 3), fwdadj_over_fwd=round(t_step / t_fwd, 3),
                ckpt_budget_bytes=opts.get("ckpt_budget", 0), device_bytes=held,
-               reverse_sweep_bytes=held - base_bytes)
+               reverse_sweep_bytes=held - base_bytes, scatter_fallbacks=scat)
     if tuned is not None:
         rec["tuned_options"] = tuned["options"]
     if args.compare_separate or wl.name == "batch2d":

@@ -287,6 +287,23 @@ int64_t mpm_mag_noalloc_scratch_bytes(void);
 int mpm_mag_set_branch_trace(mpm_mag* h, uint16_t* trace, int64_t elems);
 int64_t mpm_mag_trace_nodes(const mpm_mag* h);
 
+/*
+ * Scatter fallback counts (instrumentation; the P2G scatter of Eqs. 14-15 and
+ * its transpose). A block of 256 particles sums its stencils in an LDS box and
+ * registers the box with the coarse grid blocks it overlaps; when the block's
+ * box is too large, each wave stages its own box, and when a wave's box is
+ * too large as well, or a coarse block's list of boxes is full, values go to
+ * global atomics instead. Results do not depend on which path is taken, only
+ * the speed does. Fills counts[k] for k < n with the counts of the last
+ * rollout or backward on h (0 for k >= 3):
+ *   counts[0]  waves that staged their own box (their block's was too large)
+ *   counts[1]  waves that added their values with global atomics
+ *   counts[2]  box registrations past a coarse block's list capacity
+ * The counts are read back when that call finished. EINVAL when h or counts
+ * is NULL or n < 0.
+ */
+int mpm_mag_scatter_stats(const mpm_mag* h, int64_t* counts, int n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -217,4 +217,10 @@ int mpm_mag_set_branch_trace(mpm_mag* h, uint16_t* trace, int64_t elems)
 
 int64_t mpm_mag_trace_nodes(const mpm_mag* h) { return h ? h->eng->trace_nodes() : 0; }
 
+int mpm_mag_scatter_stats(const mpm_mag* h, int64_t* counts, int n)
+{
+    if (!h || !counts || n < 0) return MPM_MAG_EINVAL;
+    return h->eng->scatter_stats(counts, n);
+}
+
 }  // extern "C"

@@ -29,6 +29,7 @@ constexpr int kErrStore = 8;   // a grid store entry to be read was not kept (in
 // consequence, e.g. an inverted F gives a non-finite stress one step later; the
 // earliest one is the cause reported.)
 constexpr unsigned long long kNoError = ~0ull;
+constexpr int kScatStats = 3;   // scatter fallback counters kept after the error word
 __device__ __forceinline__ void report_error(unsigned long long* word, int step, int phase, int flags)
 {
     const unsigned long long rank = (flags & kErrNonFinite) ? 0ull

@@ -49,6 +49,8 @@ public:
     virtual int64_t device_bytes() const = 0;
     virtual int set_trace(uint16_t* trace, int64_t elems) = 0;
     virtual int64_t trace_nodes() const = 0;
+    // scatter fallback counts of the last rollout or backward (kScatStats values)
+    virtual int scatter_stats(int64_t* out, int n) const = 0;
     int kernel_stats(int k, int64_t* launches, double* ms, double* bytes)
     {
         if (k == -1) {
@@ -355,6 +357,12 @@ public:
         return MPM_MAG_OK;
     }
     int64_t trace_nodes() const override { return trace_nodes_; }
+    int scatter_stats(int64_t* out, int n) const override
+    {
+        if (!out || n < 0) return MPM_MAG_EINVAL;
+        for (int k = 0; k < n; ++k) out[k] = (k < kScatStats && err_h_) ? (int64_t)err_h_[1 + k] : 0;
+        return MPM_MAG_OK;
+    }
 
     // --------------------------------------------------------------- rollout
     int rollout(hipStream_t s, const void* x0, const void* density, const void* br, const void* b_prog,
@@ -375,6 +383,7 @@ public:
             if (st) return st;
         }
         MPM_HIP(hipMemsetAsync(err_d_, 0xff, sizeof(*err_d_), s));   // kNoError
+        MPM_HIP(hipMemsetAsync(err_d_ + 1, 0, sizeof(*err_d_) * kScatStats, s));
         MPM_HIP(hipMemsetAsync(acc_, 0, sizeof(double) * kAccCount * n_inst_, s));
         MPM_HIP(hipMemsetAsync(gm_, 0, sizeof(real) * 4 * G_, s));
         MPM_HIP(hipMemsetAsync(reg_count_, 0, sizeof(int) * n_cb_, s));
@@ -439,6 +448,7 @@ public:
         if (!recorded_) return fail(MPM_MAG_ESTATE, "backward needs a successful record=1 rollout");
         if (!dloss) return fail(MPM_MAG_EINVAL, "dloss is required");
         MPM_HIP(hipMemsetAsync(err_d_, 0xff, sizeof(*err_d_), s));   // kNoError
+        MPM_HIP(hipMemsetAsync(err_d_ + 1, 0, sizeof(*err_d_) * kScatStats, s));
         MPM_HIP(hipMemsetAsync(gB_, 0, sizeof(double) * S_tot_ * D, s));
         MPM_HIP(hipMemcpyAsync(dloss_, dloss, sizeof(real) * n_inst_, hipMemcpyDeviceToDevice, s));
         MPM_HIP(hipMemsetAsync(active_, 0, sizeof(int) * 4 * kMaxChains, s));
@@ -822,6 +832,7 @@ private:
         a.gv = gv_;
         a.gbar = gbar_;
         a.err = err_d_;
+        a.scat_stats = err_d_ + 1;
         a.acc = acc_;
         a.loss_val = loss_val_;
         a.gB = gB_;
@@ -1053,7 +1064,7 @@ private:
 
     int finish(hipStream_t s)
     {
-        MPM_HIP(hipMemcpyAsync(err_h_, err_d_, sizeof(*err_d_), hipMemcpyDeviceToHost, s));
+        MPM_HIP(hipMemcpyAsync(err_h_, err_d_, sizeof(*err_d_) * (1 + kScatStats), hipMemcpyDeviceToHost, s));
         MPM_HIP(hipStreamSynchronize(s));
         if (timing_) {
             for (auto& p : pending_) {
@@ -1429,7 +1440,7 @@ private:
         st |= dalloc(&acc_, (size_t)kAccCount * n_inst_);
         st |= dalloc(&loss_val_, (size_t)n_inst_);
         st |= dalloc(&dloss_, (size_t)n_inst_);
-        st |= dalloc(&err_d_, 1);
+        st |= dalloc(&err_d_, 1 + kScatStats);   // error word, then the scatter fallback counts
         for (int b = 0; b < 2; ++b) {
             st |= dalloc(&keys_[b], (size_t)N_);
             st |= dalloc(&vals_[b], (size_t)N_);
@@ -1437,8 +1448,8 @@ private:
         st |= dalloc(&hist_, (size_t)256 * sort_blocks_);
         if (st) return ws_ ? MPM_MAG_ENOMEM : fail(MPM_MAG_ENOMEM, "device allocation failed");
         if (ws_)
-            err_h_ = &err_host_;   // a pageable word: no host allocation either
-        else if (hipHostMalloc((void**)&err_h_, sizeof(*err_h_)) != hipSuccess)
+            err_h_ = err_host_;   // pageable words: no host allocation either
+        else if (hipHostMalloc((void**)&err_h_, sizeof(*err_h_) * (1 + kScatStats)) != hipSuccess)
             return fail(MPM_MAG_ENOMEM, "pinned error word");
         MPM_HIP(hipMemcpy(inst_d_, inst_h_.data(), sizeof(InstDev<real>) * inst_h_.size(), hipMemcpyHostToDevice));
         MPM_HIP(hipMemcpy(chunks_d_, chunks_h_.data(), sizeof(ChunkDev) * chunks_h_.size(), hipMemcpyHostToDevice));
@@ -1574,7 +1585,7 @@ private:
     real* dloss_ = nullptr;   // copy of the upstream loss gradient (stable address for graphs)
     unsigned long long* err_d_ = nullptr;   // earliest failure of the call (report_error)
     unsigned long long* err_h_ = nullptr;
-    unsigned long long err_host_ = 0;   // error word copy of a handle on a workspace
+    unsigned long long err_host_[1 + kScatStats] = {};   // error word and counts of a handle on a workspace
     uint8_t* ws_ = nullptr;             // workspace the buffers are carved from, or nullptr
     size_t ws_bytes_ = 0, ws_used_ = 0;
     uint32_t* keys_[2] = {nullptr, nullptr};

@@ -75,6 +75,8 @@ struct Args {
     real* gv;            // [4 G] velocity after the grid operation
     real* gbar;          // [4 G] adjoint grid values
     unsigned long long* err;   // device error word (earliest failure; report_error)
+    unsigned long long* scat_stats;   // [3] scatter fallbacks: waves staged alone, waves on global atomics,
+                                      // box registrations past a coarse block's list
     double* acc;         // [n_inst][kAccCount]
     double* loss_val;    // [n_inst]
     double* gB;          // [S_tot][D] field-program gradient
@@ -194,6 +196,7 @@ __device__ __forceinline__ void register_box(const Args<real>& a, const InstDev<
         int slot = atomicAdd(&a.reg_count[cb], 1);
         if (slot == 0) a.active_list[phase * a.n_coarse + atomicAdd(&a.active[phase], 1)] = cb;
         if (!staged || slot >= CB::cap) a.fb_used[cb] = 1;   // values of this block go to fb
+        if (slot >= CB::cap) atomicAdd(&a.scat_stats[2], 1ull);
         if (slot < CB::cap) {
             a.reg_list[cb * CB::cap + slot] = id;
         } else if (staged) {
@@ -353,6 +356,7 @@ __device__ __forceinline__ void scatter_box(const Args<real>& a, const InstDev<r
     const bool block_mode = a.use_lds && vol <= a.box_cap;
     // this lane's staging box: the block's, or its wave's
     const bool staged = block_mode || (a.use_lds && wave_live && wvol <= kWaveBoxCap);
+    if (!block_mode && wave_live && (t & 63) == 0) atomicAdd(&a.scat_stats[staged ? 0 : 1], 1ull);
     int blo[3], bext[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {

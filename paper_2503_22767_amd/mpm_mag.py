@@ -137,6 +137,8 @@ def lib():
     L.mpm_mag_set_branch_trace.restype = C.c_int
     L.mpm_mag_trace_nodes.argtypes = [vp]
     L.mpm_mag_trace_nodes.restype = i64
+    L.mpm_mag_scatter_stats.argtypes = [vp, C.POINTER(i64), C.c_int]
+    L.mpm_mag_scatter_stats.restype = C.c_int
     _lib = L
     return L
 
@@ -251,6 +253,12 @@ class MpmMag:
 
     def trace_nodes(self) -> int:
         return int(lib().mpm_mag_trace_nodes(self._h))
+
+    def scatter_stats(self) -> dict:
+        """Scatter fallback counts of the last rollout or backward."""
+        out = (C.c_int64 * 3)()
+        self._check(lib().mpm_mag_scatter_stats(self._h, out, 3), "mpm_mag_scatter_stats")
+        return {"wave_boxes": int(out[0]), "atomic_waves": int(out[1]), "list_overflows": int(out[2])}
 
     def set_branch_trace(self, trace: Optional[torch.Tensor]):
         """Record the grid update's per-node branch decisions of the following

@@ -71,4 +71,5 @@ def test_create_rejects_bad_arguments_without_touching_the_device():
     assert L.mpm_mag_backward(None, None, None, None, None, None, None) == M.EINVAL
     assert L.mpm_mag_set_branch_trace(None, None, 0) == M.EINVAL
     assert L.mpm_mag_trace_nodes(None) == 0
+    assert L.mpm_mag_scatter_stats(None, None, 0) == M.EINVAL
     L.mpm_mag_destroy(None)

@@ -142,6 +142,42 @@ def test_backward_needs_a_recorded_rollout():
         sim.close()
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_scatter_fallback_counts(dim):
+    """The scatter's fallback counters: none on a compact block with the
+    default staging box; per-wave boxes when the block box is capped below the
+    block's stencils; every live wave on global atomics without LDS staging.
+    The results of the three settings agree with each other to rounding."""
+    # a block whose stencil box exceeds the smallest box cap (64 nodes)
+    size, n_grid = ((0.4, 0.3), 32) if dim == 2 else ((0.3, 0.2, 0.25), 16)
+    inst = W.make_tiny(seed=3, dim=dim, n_steps=6, loss_kind=W.LOSS_COM_DISP, floor=True, gravity=1.0, size=size,
+                       n_grid=n_grid, n_segments=2)
+    tens = M.instance_tensors([inst], dtype=torch.float64)
+    xs, counts = {}, {}
+    for name, opts in (("default", {}), ("box_cap", {"box_cap": 64}), ("no_lds", {"p2g_lds": 0})):
+        sim = M.MpmMag([inst.params], [inst.n], precision=8)
+        try:
+            for k, v in opts.items():
+                sim.set_option(k, v)
+            _, x = sim.rollout(*tens, record=True)
+            counts[name] = sim.scatter_stats()
+            xs[name] = x.cpu().numpy()
+            sim.backward(torch.ones(1, dtype=torch.float64, device="cuda"))
+            counts[name + " backward"] = sim.scatter_stats()
+        finally:
+            sim.close()
+    log("scatter fallbacks", dim, counts)
+    waves = -(-inst.n // 64)   # live waves of one scatter launch
+    assert counts["default"] == {"wave_boxes": 0, "atomic_waves": 0, "list_overflows": 0}
+    assert counts["box_cap"]["wave_boxes"] > 0 and counts["box_cap"]["atomic_waves"] == 0
+    assert counts["box_cap backward"]["wave_boxes"] > 0
+    # one forward scatter per step: T steps of the rollout, all waves on atomics
+    assert counts["no_lds"]["atomic_waves"] == inst.params["n_steps"] * waves, counts["no_lds"]
+    assert counts["no_lds"]["wave_boxes"] == 0
+    for name in ("box_cap", "no_lds"):
+        assert np.max(np.abs(xs[name] - xs["default"])) <= 1e-12
+
+
 def _two_blobs(dim, n_steps=16, seed=9):
     """One chunk (128 particles) made of two small blobs in opposite corners
     of the grid (16 nodes per axis in 3D, 64 in 2D): its box of stencil base
