@@ -405,7 +405,7 @@ def codesign(wl, iters=2):
                 ms_per_iteration=round(ms, 1), loss_history=hist)
 
 
-def walker_codesign(max_iters=400, mass_eps=1e-3, lr=0.01):
+def walker_codesign(max_iters=1000, mass_eps=1e-3, lr=0.01):
     """The co-design loop on the 2D walker (30,593 particles, 2,000 steps,
     floor contact, a harmonic stimulus, 8 magnetization regions by x slab,
     per-particle topology) with void particles' mass floored at mass_eps: beta
@@ -481,7 +481,7 @@ def main():
     ap.add_argument("--no-walker-codesign", action="store_true",
                     help="skip the walker co-design run through beta = 128 to convergence")
     ap.add_argument("--walker-codesign-only", action="store_true", help="run only the walker co-design leg")
-    ap.add_argument("--walker-max-iters", type=int, default=400)
+    ap.add_argument("--walker-max-iters", type=int, default=1000)
     ap.add_argument("--walker-lr", type=float, default=0.01)
     args = ap.parse_args()
     if args.gpus != 1:
