@@ -12,8 +12,14 @@ from paper_2503_22767_amd import mpm_mag as M
 
 
 def log(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+    """Progress and result lines: written at once, past pytest's capture
+    (conftest.progress), so long runs show progress."""
+    msg = " ".join(str(x) for x in a)
+    cf = sys.modules.get("conftest")
+    if cf is not None and hasattr(cf, "progress"):
+        cf.progress(msg)
+    else:
+        print(msg, flush=True)
 
 
 def gpu_run(instances, precision, record=True, backward=True, options=None, dloss=None, trace=False):
