@@ -90,12 +90,15 @@ ALU_PEAK_PACKED_TFLOPS = {4: 157.3, 8: 78.6}
 # HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE, then
 # WRITE_SIZE, on the quadruped workload, scaled by what the counters read for a
 # device-to-device copy of 1 GiB (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0). Valid
-# only for the kernel sources they were taken on (hash of csrc/).
+# only for that workload and for the kernel sources they were taken on (hash of
+# csrc/); other workloads report null.
 TRAFFIC = {
-    # (528477.1 KiB fetched x 2.0 + 257446.0 KiB written) x 1024, mean of 5 launches
-    "p2g_g2p_adj": 1345945798,
-    # (142450.5 x 2.0 + 221025.1) x 1024, mean of 21 launches (plain and recorded steps)
-    "g2p_p2g": 518068462,
+    "quadruped3d": {
+        # (528477.1 KiB fetched x 2.0 + 257446.0 KiB written) x 1024, mean of 5 launches
+        "p2g_g2p_adj": 1345945798,
+        # (142450.5 x 2.0 + 221025.1) x 1024, mean of 21 launches (plain and recorded steps)
+        "g2p_p2g": 518068462,
+    },
 }
 TRAFFIC_SRC_HASH = "cd67388059b314f1"
 
@@ -111,7 +114,7 @@ def csrc_hash():
     return h.hexdigest()[:16]
 
 
-def roofline(sim, tens, dloss, precision, streams=0):
+def roofline(sim, tens, dloss, precision, streams=0, workload=""):
     """One extra instrumented pass with per-launch HIP events on the library's
     stream. The dominant kernel (largest total time) is placed on the roofline
     by its arithmetic intensity against the ridge of the ALU and HBM peaks."""
@@ -137,8 +140,8 @@ def roofline(sim, tens, dloss, precision, streams=0):
     gbs = bpl / avg_s / 1e9
     tflops = fpl / avg_s / 1e12
     traffic = None
-    if dom in TRAFFIC and TRAFFIC_SRC_HASH == csrc_hash():
-        traffic = TRAFFIC[dom]
+    if dom in TRAFFIC.get(workload, {}) and TRAFFIC_SRC_HASH == csrc_hash():
+        traffic = TRAFFIC[workload][dom]
     if intensity > ridge:
         rl = dict(bound="alu", achieved=round(tflops, 2), peak=alu_peak, unit="TFLOP/s",
                   frac=round(tflops / alu_peak, 4), traffic=traffic,
@@ -571,7 +574,7 @@ def main():
         rec["batched_speedup"] = round(t_sep / t_step, 3)
         log(f"[bench] {len(wl.instances)} separate handles: {t_sep * 1e3:.1f} ms per fwd+adj pass")
     if not args.no_roofline:
-        rl, per_kernel = roofline(sim, tens, dloss, wl.precision, opts.get("streams", 0))
+        rl, per_kernel = roofline(sim, tens, dloss, wl.precision, opts.get("streams", 0), wl.name)
         rec["roofline"] = rl
         rec["kernels"] = {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                           for k, v in per_kernel.items()}

@@ -196,8 +196,8 @@ const char* mpm_mag_last_error(const mpm_mag* h);
  *                   run on several streams, 1024 on one
  *   "grid_parts"    workgroups that share one coarse grid block in the grid update and
  *                   its transpose, each taking a slab of the block along its last axis
- *                   (1, 2, 4 or 8; 0 (default): 2 when instance groups run on several
- *                   streams, 1 on one); results do not depend on it
+ *                   (1, 2, 4 or 8; 0 (default): 2 in 3D when instance groups run on
+ *                   several streams, else 1); results do not depend on it
  *   "streams"       instance groups advanced on separate streams, 0..8 (0: min(3, instances));
  *                   consecutive instances form a group; 1 runs everything on the call's stream
  *   "fuse_fwd"      1: G2P of step n and P2G of step n+1 in one kernel (default), 0: separate

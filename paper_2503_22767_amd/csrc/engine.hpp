@@ -632,7 +632,7 @@ private:
 
     int grid_blocks_of(int q) const { return (int)std::min<int64_t>(chains_[q].ncb, grid_wgs_); }
     // workgroups sharing one coarse block in the grid gathers
-    int grid_parts() const { return grid_parts_ > 0 ? grid_parts_ : (n_chains() > 1 ? 2 : 1); }
+    int grid_parts() const { return grid_parts_ > 0 ? grid_parts_ : (D == 3 && n_chains() > 1 ? 2 : 1); }
     int gather_blocks_of(int q) const { return (int)std::min<int64_t>(chains_[q].ncb * grid_parts(), grid_wgs_); }
 
     // copy of the chain's particle state (all components) from src to dst
