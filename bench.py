@@ -91,7 +91,7 @@ ALU_PEAK_PACKED_TFLOPS = {4: 157.3, 8: 78.6}
 # WRITE_SIZE, on the quadruped workload, scaled by what the counters read for a
 # device-to-device copy of 1 GiB (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0). Valid
 # only for that workload and for the kernel sources they were taken on (hash of
-# csrc/); other workloads report null.
+# csrc/device.hpp and csrc/kernels.hpp); other workloads report null.
 TRAFFIC = {
     "quadruped3d": {
         # (528477.1 KiB fetched x 2.0 + 257446.0 KiB written) x 1024, mean of 5 launches
@@ -100,17 +100,18 @@ TRAFFIC = {
         "g2p_p2g": 518068462,
     },
 }
-TRAFFIC_SRC_HASH = "cd67388059b314f1"
+TRAFFIC_SRC_HASH = "f8b3f1c8d5f14de7"
 
 
 def csrc_hash():
+    """Hash of the device kernels' sources (the particle and grid kernels and
+    their device helpers; host-side launch code is not part of it)."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2503_22767_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hpp", ".hip")):
-            h.update(f.encode())
-            h.update(open(os.path.join(d, f), "rb").read())
+    for f in ("device.hpp", "kernels.hpp"):
+        h.update(f.encode())
+        h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
 
