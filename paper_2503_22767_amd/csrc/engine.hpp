@@ -384,7 +384,7 @@ public:
         }
         MPM_HIP(hipMemsetAsync(err_d_, 0xff, sizeof(*err_d_), s));   // kNoError
         MPM_HIP(hipMemsetAsync(err_d_ + 1, 0, sizeof(*err_d_) * kScatStats, s));
-        MPM_HIP(hipMemsetAsync(acc_, 0, sizeof(double) * kAccCount * n_inst_, s));
+        MPM_HIP(hipMemsetAsync(acc_, 0, sizeof(double) * kAccCount * n_inst_ * kGbCopies, s));
         MPM_HIP(hipMemsetAsync(gm_, 0, sizeof(real) * 4 * G_, s));
         MPM_HIP(hipMemsetAsync(reg_count_, 0, sizeof(int) * n_cb_, s));
         MPM_HIP(hipMemsetAsync(part_done_, 0, sizeof(int) * n_cb_, s));
@@ -449,7 +449,7 @@ public:
         if (!dloss) return fail(MPM_MAG_EINVAL, "dloss is required");
         MPM_HIP(hipMemsetAsync(err_d_, 0xff, sizeof(*err_d_), s));   // kNoError
         MPM_HIP(hipMemsetAsync(err_d_ + 1, 0, sizeof(*err_d_) * kScatStats, s));
-        MPM_HIP(hipMemsetAsync(gB_, 0, sizeof(double) * S_tot_ * D, s));
+        MPM_HIP(hipMemsetAsync(gB_, 0, sizeof(double) * S_tot_ * D * kGbCopies, s));
         MPM_HIP(hipMemcpyAsync(dloss_, dloss, sizeof(real) * n_inst_, hipMemcpyDeviceToDevice, s));
         MPM_HIP(hipMemsetAsync(active_, 0, sizeof(int) * 4 * kMaxChains, s));
         int st = ensure_seg_store();
@@ -520,7 +520,7 @@ public:
         }
         if (g_b_prog) {
             int64_t nb = (int64_t)S_tot_ * D;
-            st = launch(K_OUT, s, (int)((nb + 255) / 256), 256, k_convert_out<real>, (const double*)gB_,
+            st = launch(K_OUT, s, (int)((nb + 255) / 256), 256, k_sum_copies_out<real>, (const double*)gB_,
                         (real*)g_b_prog, nb);
             if (st) return st;
         }
@@ -834,8 +834,10 @@ private:
         a.err = err_d_;
         a.scat_stats = err_d_ + 1;
         a.acc = acc_;
+        a.acc_stride = (int64_t)n_inst_ * kAccCount;
         a.loss_val = loss_val_;
         a.gB = gB_;
+        a.gB_stride = (int64_t)S_tot_ * D;
         a.gphi = gphi_;
         a.gbr = gbr_;
         a.corig = corig_;
@@ -1436,8 +1438,8 @@ private:
         st |= dalloc(&gv_, (size_t)4 * G_);
         st |= dalloc(&gbar_, (size_t)4 * G_);
         st |= dalloc(&bprog_, (size_t)S_tot_ * D);
-        st |= dalloc(&gB_, (size_t)S_tot_ * D);
-        st |= dalloc(&acc_, (size_t)kAccCount * n_inst_);
+        st |= dalloc(&gB_, (size_t)S_tot_ * D * kGbCopies);
+        st |= dalloc(&acc_, (size_t)kAccCount * n_inst_ * kGbCopies);
         st |= dalloc(&loss_val_, (size_t)n_inst_);
         st |= dalloc(&dloss_, (size_t)n_inst_);
         st |= dalloc(&err_d_, 1 + kScatStats);   // error word, then the scatter fallback counts

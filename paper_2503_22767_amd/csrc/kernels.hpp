@@ -62,6 +62,15 @@ template <int D> struct Coarse {
 };
 static_assert(Coarse<2>::cap <= kGridBlock && Coarse<3>::cap <= kGridBlock, "grid scan assumes cap <= block");
 
+// The field-program gradient and the per-instance loss sums are accumulated
+// by FP64 atomics, one per workgroup (and step). Every workgroup of an
+// instance adds to the same few values, so the atomics are spread over
+// kGbCopies copies (by chunk index) and the copies are summed in a fixed order
+// at the end: a single copy serialized several thousand atomics per value at
+// the L2, a quarter of the fused adjoint kernel's time.
+constexpr int kGbCopies = 64;
+
+
 template <typename real>
 struct Args {
     const InstDev<real>* inst;
@@ -77,9 +86,11 @@ struct Args {
     unsigned long long* err;   // device error word (earliest failure; report_error)
     unsigned long long* scat_stats;   // [3] scatter fallbacks: waves staged alone, waves on global atomics,
                                       // box registrations past a coarse block's list
-    double* acc;         // [n_inst][kAccCount]
+    double* acc;         // [kGbCopies][n_inst][kAccCount] per-instance sums; k_loss_finalize leaves the totals in copy 0
+    int64_t acc_stride;  // n_inst * kAccCount: distance between copies
     double* loss_val;    // [n_inst]
-    double* gB;          // [S_tot][D] field-program gradient
+    double* gB;          // [kGbCopies][S_tot][D] field-program gradient, summed over the copies at the end
+    int64_t gB_stride;   // S_tot * D: distance between copies
     real* gphi;          // [nalloc]
     real* gbr;           // [D][nalloc]
     const int4* corig;   // [n_chunks] origin cell of each chunk (positions are stored relative to it)
@@ -102,6 +113,13 @@ struct Args {
     uint16_t* trace;       // [n_steps][trace_nodes] branch decisions of the grid update, or nullptr
     int64_t trace_nodes;   // nodes of all instances (sum of n_grid^D)
 };
+
+// copy of the per-instance accumulators that chunk c adds to
+template <typename real>
+__device__ __forceinline__ double* acc_copy(const Args<real>& a, int c, int inst)
+{
+    return a.acc + (int64_t)(c % kGbCopies) * a.acc_stride + (int64_t)inst * kAccCount;
+}
 
 // Grid store: a step's active coarse blocks, each node's summed (momentum,
 // mass) record (4 values), packed step after step, so that the reverse sweep
@@ -1635,7 +1653,7 @@ __device__ __forceinline__ void traj_accumulate(const Args<real>& a, const InstD
     }
     double v1[1] = {traj};
     block_sum<1>(v1);
-    if (threadIdx.x == 0) unsafeAtomicAdd(&a.acc[inst * kAccCount + kAccTraj], v1[0]);
+    if (threadIdx.x == 0) unsafeAtomicAdd(&acc_copy(a, a.chunk_base + blockIdx.x, inst)[kAccTraj], v1[0]);
 }
 
 // G2P of one step (no scatter follows): the recompute of a stored segment,
@@ -1777,7 +1795,7 @@ __global__ __launch_bounds__(kBlock) void k_loss_sums(Args<real> a, const real* 
     }
     block_sum<5>(v);
     if (t == 0) {
-        double* acc = a.acc + ch.inst * kAccCount;
+        double* acc = acc_copy(a, a.chunk_base + blockIdx.x, ch.inst);
         unsafeAtomicAdd(&acc[kAccMass], v[0]);
         unsafeAtomicAdd(&acc[kAccS1], v[1]);
         unsafeAtomicAdd(&acc[kAccSq], v[2]);
@@ -1792,7 +1810,18 @@ __global__ void k_loss_finalize(Args<real> a, int n_inst, real* loss_out)
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_inst) return;
     const InstDev<real>& I = a.inst[k];
-    const double* acc = a.acc + k * kAccCount;
+    // sum the copies in copy order and leave the totals in copy 0, where the
+    // seed and the adjoint read them
+    double acc[kAccCount];
+    double* acc0 = a.acc + (int64_t)k * kAccCount;
+#pragma unroll
+    for (int j = 0; j < kAccCount; ++j) {
+        double s = 0.0;
+        for (int r = 0; r < kGbCopies; ++r) s += acc0[(int64_t)r * a.acc_stride + j];
+        acc[j] = s;
+    }
+#pragma unroll
+    for (int j = 0; j < kAccCount; ++j) acc0[j] = acc[j];
     double L = 0;
     switch (I.loss_kind) {
     case kFinalMse: L = acc[kAccCnt] > 0 ? acc[kAccSq] / acc[kAccCnt] : 0.0; break;
@@ -2366,7 +2395,10 @@ __device__ __forceinline__ void p2g_adj_phase(const Args<real>& a, const InstDev
     if (t == 0) {
         int seg = segment_of(step, I.seg_steps, I.n_seg, I.periodic);
 #pragma unroll
-        for (int k = 0; k < D; ++k) unsafeAtomicAdd(&a.gB[(int64_t)(I.seg_off + seg) * D + k], gBl[k]);
+        for (int k = 0; k < D; ++k)
+            unsafeAtomicAdd(&a.gB[(int64_t)((a.chunk_base + blockIdx.x) % kGbCopies) * a.gB_stride +
+                                  (int64_t)(I.seg_off + seg) * D + k],
+                            gBl[k]);
     }
 }
 
@@ -2528,11 +2560,15 @@ __global__ __launch_bounds__(kBlock) void k_scatter_out(Args<real> a, const int*
         for (int k = 0; k < D; ++k) g_br[q * D + k] = a.gbr[k * S + i];
 }
 
+// dst[k] = sum over the kGbCopies copies of src[k] (copies n apart), in copy order
 template <typename real>
-__global__ void k_convert_out(const double* src, real* dst, int64_t n)
+__global__ void k_sum_copies_out(const double* src, real* dst, int64_t n)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) dst[k] = (real)src[k];
+    if (k >= n) return;
+    double s = 0.0;
+    for (int r = 0; r < kGbCopies; ++r) s += src[(int64_t)r * n + k];
+    dst[k] = (real)s;
 }
 
 }  // namespace mpm
