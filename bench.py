@@ -94,13 +94,13 @@ ALU_PEAK_PACKED_TFLOPS = {4: 157.3, 8: 78.6}
 # csrc/device.hpp and csrc/kernels.hpp); other workloads report null.
 TRAFFIC = {
     "quadruped3d": {
-        # (528477.1 KiB fetched x 2.0 + 257446.0 KiB written) x 1024, mean of 5 launches
-        "p2g_g2p_adj": 1345945798,
-        # (142450.5 x 2.0 + 221025.1) x 1024, mean of 21 launches (plain and recorded steps)
-        "g2p_p2g": 518068462,
+        # (530089.6 KiB fetched x 2.0 + 257609.8 KiB written) x 1024, mean of 5 launches
+        "p2g_g2p_adj": 1349415974,
+        # (142473.6 x 2.0 + 221035.4) x 1024, mean of 21 launches (plain and recorded steps)
+        "g2p_p2g": 518126120,
     },
 }
-TRAFFIC_SRC_HASH = "f8b3f1c8d5f14de7"
+TRAFFIC_SRC_HASH = "b3c887fd5c3fa880"
 
 
 def csrc_hash():
