@@ -1438,7 +1438,8 @@ private:
         st |= dalloc(&gv_, (size_t)4 * G_);
         st |= dalloc(&gbar_, (size_t)4 * G_);
         st |= dalloc(&bprog_, (size_t)S_tot_ * D);
-        st |= dalloc(&gB_, (size_t)S_tot_ * D * kGbCopies);
+        // the program gradient's copies (a handle on static scratch runs no backward)
+        st |= dalloc(&gB_, ws_ ? (size_t)1 : (size_t)S_tot_ * D * kGbCopies);
         st |= dalloc(&acc_, (size_t)kAccCount * n_inst_ * kGbCopies);
         st |= dalloc(&loss_val_, (size_t)n_inst_);
         st |= dalloc(&dloss_, (size_t)n_inst_);
