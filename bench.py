@@ -90,8 +90,9 @@ ALU_PEAK_PACKED_TFLOPS = {4: 157.3, 8: 78.6}
 # HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE, then
 # WRITE_SIZE, on the quadruped workload, scaled by what the counters read for a
 # device-to-device copy of 1 GiB (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0). Valid
-# only for that workload and for the kernel sources they were taken on (hash of
-# csrc/device.hpp and csrc/kernels.hpp); other workloads report null.
+# only for that workload and for the kernel code they were taken on (hash of
+# csrc/device.hpp and csrc/kernels.hpp, comments left out); other workloads
+# report null.
 TRAFFIC = {
     "quadruped3d": {
         # (530089.6 KiB fetched x 2.0 + 257609.8 KiB written) x 1024, mean of 5 launches
@@ -100,18 +101,28 @@ TRAFFIC = {
         "g2p_p2g": 518126120,
     },
 }
-TRAFFIC_SRC_HASH = "b3c887fd5c3fa880"
+TRAFFIC_SRC_HASH = "74cbf943f8aa8c1f"
+
+
+def code_text(src):
+    """C++ source without its comments and with whitespace collapsed, so that
+    an edit of a comment does not count as a change of the code."""
+    import re
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
 
 
 def csrc_hash():
-    """Hash of the device kernels' sources (the particle and grid kernels and
-    their device helpers; host-side launch code is not part of it)."""
+    """Hash of the device kernels' code (the particle and grid kernels and
+    their device helpers, comments left out; host-side launch code is not part
+    of it)."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2503_22767_amd", "csrc")
     for f in ("device.hpp", "kernels.hpp"):
         h.update(f.encode())
-        h.update(open(os.path.join(d, f), "rb").read())
+        h.update(code_text(open(os.path.join(d, f)).read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -288,9 +288,11 @@ __device__ __forceinline__ void row_prefix_sums(int (&e)[NV])
 }
 
 // Adds NV values per stencil node of every active particle of the block to the
-// instance grid. The block's stencils are staged in LDS (double) over their
-// bounding box; each lane starts at a different stencil node so lanes of one
-// cell never hit one address together. The box is then written with plain
+// instance grid. The block's stencils are summed in LDS over their bounding
+// box: as 32-bit fixed point with a per-block scale per value slot (FP32
+// build), the lanes of a 16-lane row that share a stencil base combined first
+// by row prefix sums so that one lane per segment adds to a node; as doubles
+// (FP64 build), by segmented row sums. The box is then written with plain
 // stores to this chunk's slot of `part` and registered (one integer atomic per
 // coarse block it overlaps) so the grid update can gather it; no float atomics
 // touch HBM. When the block's box exceeds kBoxCap every wave stages its own box
