@@ -208,16 +208,26 @@ const char* mpm_mag_last_error(const mpm_mag* h);
  *                   cell (default), so the scatter's lanes that share a base stay
  *                   adjacent; 0: slot order. Results do not depend on it.
  *   "ckpt_every"    checkpoint spacing K (0: automatic); takes effect at the next recorded rollout
+ *   "ckpt_budget"   device bytes the recorded rollout may hold for the reverse sweep
+ *                   (checkpoints, segment stash, grid ring, grid and segment stores);
+ *                   a positive value replaces the instances' ckpt_budget_bytes, 0
+ *                   (default) keeps theirs. A budget below what the checkpoints,
+ *                   the stash and the ring need at spacing K makes the recorded
+ *                   rollout fail with ENOMEM; the grid store takes what is left.
+ *                   Takes effect at the next recorded rollout.
  *   "grid_store"    device memory for the grid store, in MiB: a recorded rollout keeps
- *                   each step's active grid blocks (velocity and summed momentum and
- *                   mass, 8 values per node), and backward rebuilds a checkpoint
- *                   segment's grids from it and recomputes only the segment's G2P
- *                   instead of the whole step. Segments the store cannot hold are
- *                   recomputed in full. -1 (default): sized from the last recorded
- *                   rollout's block count plus a tenth (an estimate from the particle
- *                   counts before the first), within the free device memory less an
- *                   eighth of the total; 0: off. Takes effect at the next recorded
- *                   rollout; results do not depend on it beyond summation order.
+ *                   each step's active coarse grid blocks (summed momentum and mass,
+ *                   4 values per node), and backward rebuilds a checkpoint segment's
+ *                   grids from it (the node velocity by the same grid operation) and
+ *                   recomputes only the segment's G2P instead of the whole step.
+ *                   Segments the store cannot hold are recomputed in full, their
+ *                   grids kept in a segment store. -1 (default): sized from the last
+ *                   recorded rollout's block count plus a tenth (an estimate from the
+ *                   particle counts before the first), within the checkpoint budget
+ *                   when there is one, else within the free device memory less an
+ *                   eighth of the total; a positive value caps it further; 0: off.
+ *                   Takes effect at the next recorded rollout; results do not depend
+ *                   on it beyond summation order.
  * Returns EINVAL for an unknown key or value.
  */
 int mpm_mag_set_option(mpm_mag* h, const char* key, int64_t value);
