@@ -303,8 +303,9 @@ int64_t mpm_mag_trace_nodes(const mpm_mag* h);
  * registers the box with the coarse grid blocks it overlaps; when the block's
  * box is too large, each wave stages its own box, and when a wave's box is
  * too large as well, or a coarse block's list of boxes is full, values go to
- * global atomics instead. Results do not depend on which path is taken, only
- * the speed does. Fills counts[k] for k < n with the counts of the last
+ * global atomics instead. The paths differ in speed, and in results only by
+ * rounding: the global atomics add in no fixed order, so a run that takes them
+ * need not repeat bit for bit. Fills counts[k] for k < n with the counts of the last
  * rollout or backward on h (0 for k >= 3):
  *   counts[0]  waves that staged their own box (their block's was too large)
  *   counts[1]  waves that added their values with global atomics
