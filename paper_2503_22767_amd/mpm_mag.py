@@ -16,7 +16,6 @@ loss.backward() yields d(loss)/d(density, br, b_prog).
 from __future__ import annotations
 
 import ctypes as C
-import math
 import os
 import sys
 from typing import Optional, Sequence
