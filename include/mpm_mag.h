@@ -124,8 +124,10 @@ typedef struct {
  * (host arrays). precision: 4 (FP32) or 8 (FP64). All instances must share dim
  * and n_steps. Allocates every device buffer of the plain rollout; checkpoint
  * storage of the recorded rollout is allocated on its first use.
- * Returns EINVAL for inconsistent descriptors, ENOMEM/EHIP on allocation failure;
- * *out is set only on success.
+ * Returns EINVAL for inconsistent descriptors or for grids that hold more than
+ * 2^31 - 1 nodes together (each instance's n_grid^dim rounded up to a multiple
+ * of 512: two 3D instances at n_grid = 1024 fit, three do not), ENOMEM/EHIP on
+ * allocation failure; *out is set only on success.
  */
 int mpm_mag_create(const mpm_mag_instance_desc* descs, int n_inst, const int64_t* n_particles,
                    int precision, mpm_mag** out);

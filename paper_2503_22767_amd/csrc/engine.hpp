@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -217,6 +218,10 @@ public:
             for (int b = 0; b < n_gb; ++b) gblock_h_.push_back(k);
             chunk += n_ch;
             grid += (int64_t)n_gb * kGridBlock;
+            // the instance grid offsets (InstDev::grid_off) and the coarse-block and
+            // trace tables are 32-bit; node indices in the kernels are 64-bit
+            if (grid > (int64_t)INT32_MAX)
+                return fail(MPM_MAG_EINVAL, "the instances' grids hold more than 2^31 - 1 nodes together");
             seg += d.n_segments;
             caller += np[k];
             int abits = 1;
@@ -227,7 +232,6 @@ public:
             if (d.ckpt_budget_bytes > 0 && (budget_desc_ == 0 || d.ckpt_budget_bytes < budget_desc_))
                 budget_desc_ = d.ckpt_budget_bytes;
         }
-        if (grid > ((int64_t)1 << 31) / 4) return fail(MPM_MAG_EINVAL, "total grid too large");
         caller_start_h_.push_back(caller);
         N_ = caller;
         n_chunks_ = (int)chunk;

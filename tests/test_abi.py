@@ -72,3 +72,25 @@ def test_create_rejects_bad_arguments_without_touching_the_device():
     assert L.mpm_mag_trace_nodes(None) == 0
     assert L.mpm_mag_scatter_stats(None, None, 0) == M.EINVAL
     L.mpm_mag_destroy(None)
+
+
+def test_create_rejects_grids_beyond_32bit_node_offsets():
+    """The kernels index the instance grids with 32-bit node offsets: three 3D
+    instances at n_grid = 1024 (3 * 2^30 nodes) are refused before any device
+    work, two would fit."""
+    from paper_2503_22767_amd import mpm_mag as M
+    L = M.lib()
+    h = ctypes.c_void_p()
+    descs = (M.InstanceDesc * 3)()
+    for d in descs:
+        d.dim = 3
+        d.n_grid = 1024
+        d.n_steps = 4
+        d.n_segments = 1
+        d.dt = 1e-4
+        d.particle_volume = 1e-9
+        d.mu0 = d.rho = d.E = 1.0
+        d.nu = 0.3
+    counts = (ctypes.c_int64 * 3)(100, 100, 100)
+    assert L.mpm_mag_create(descs, 3, counts, 4, ctypes.byref(h)) == M.EINVAL
+    assert b"2^31" in L.mpm_mag_last_error(None)

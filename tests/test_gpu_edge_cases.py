@@ -272,3 +272,68 @@ def test_coarse_block_list_overflow_matches_oracle():
     compare(got, ref, pos_tol=1e-10, grad_tol=1e-9, loss_tol=1e-9, label="crowded block fp64")
     got = gpu_run([inst], precision=4)
     compare(got, ref, pos_tol=1e-4, grad_tol=1e-3, label="crowded block fp32")
+
+
+def _grid_limit_instance(dim, n_grid, cells, far, steps, seed=11):
+    """A block of cells[k] cells per axis (2 particles per cell and axis) three
+    cells from the grid's low faces, or eight cells from its high faces, in a
+    grid of n_grid nodes per axis with walls one cell thick. The same seed gives
+    the same design, program and target offsets in both places."""
+    dx = 1.0 / n_grid
+    h = dx / 2
+    lo = n_grid - 8 - cells[0] if far else 3
+    corner = [lo * dx + 0.3 * h, lo * dx + 0.7 * h, lo * dx + 0.45 * h][:dim]
+    inst = W.make_tiny(seed=seed, dim=dim, n_grid=n_grid, n_steps=steps, size=[c * dx for c in cells][:dim],
+                       corner=corner, dt=1e-4 if n_grid > 64 else 1e-3, loss_kind=W.LOSS_FINAL_MSE, n_segments=2)
+    inst.params["wall_cells"] = 1
+    return inst
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_smallest_grid_matches_oracle(dim):
+    """n_grid = 8, the smallest grid the library accepts (one coarse block in 3D)."""
+    inst = _grid_limit_instance(dim, 8, (2, 2, 2), False, 30)
+    ref = oracle_run([inst])
+    compare(gpu_run([inst], precision=8), ref, pos_tol=1e-10, grad_tol=1e-9, loss_tol=1e-9, label=f"n_grid 8 d{dim}")
+    compare(gpu_run([inst], precision=4), ref, pos_tol=1e-4, grad_tol=1e-3, label=f"n_grid 8 d{dim} fp32")
+
+
+@pytest.mark.parametrize("far", [False, True], ids=["low_faces", "high_faces"])
+def test_largest_grid_2d_matches_oracle(far):
+    """n_grid = 1024, the largest grid, with the block near the low or the high
+    faces (node indices up to about 2^20)."""
+    inst = _grid_limit_instance(2, 1024, (12, 6), far, 30)
+    ref = oracle_run([inst])
+    compare(gpu_run([inst], precision=8), ref, pos_tol=1e-10, grad_tol=1e-9, loss_tol=1e-9,
+            label=f"n_grid 1024 d2 far={far}")
+    compare(gpu_run([inst], precision=4), ref, pos_tol=1e-4, grad_tol=1e-3, label=f"n_grid 1024 d2 far={far} fp32")
+
+
+def test_largest_grid_3d_is_translation_invariant():
+    """n_grid = 1024 in 3D: 2^30 nodes, about 140 GB of device grids in FP32 for
+    a recorded rollout and its adjoint. The oracle cannot hold such a grid, so
+    this checks a property instead: the same block moved by whole cells from
+    the low faces to the high ones (node indices near 2^30, value offsets past
+    2^32) moves, loses and differentiates the same. The two runs order and
+    chunk their particles differently along the Hilbert curve, so they agree to
+    rounding, not bit for bit."""
+    near = _grid_limit_instance(3, 1024, (8, 6, 6), False, 20)
+    far = _grid_limit_instance(3, 1024, (8, 6, 6), True, 20)
+    shift = far.x0 - near.x0
+    assert np.allclose(shift, shift[0]) and np.allclose(far.target - far.x0, near.target - near.x0, atol=1e-12)
+    a = gpu_run([near], precision=4)
+    log("n_grid 1024 d3: low faces done")
+    b = gpu_run([far], precision=4)
+    du_a, du_b = a["x"] - near.x0, b["x"] - far.x0
+    scale = float(np.max(np.abs(du_a)))
+    ex = float(np.max(np.abs(du_a - du_b)))
+    errs = {k: float(np.linalg.norm(a[k] - b[k]) / np.linalg.norm(a[k])) for k in ("g_density", "g_br", "g_b_prog")}
+    el = float(abs(a["loss"][0] - b["loss"][0]) / abs(a["loss"][0]))
+    log("n_grid 1024 d3 translation: max displacement", f"{scale:.3e}", "difference", f"{ex:.2e}", "loss", f"{el:.2e}",
+        {k: f"{v:.2e}" for k, v in errs.items()})
+    # x_final comes back as FP32 positions near 1.0 on the far side, whose ulp
+    # (6e-8) quantizes the displacement taken from them: allow 4 such ulps
+    assert scale > 0 and ex <= 1e-3 * scale + 4 * 2.0 ** -24, (ex, scale)
+    assert el <= 1e-4, el
+    for k, v in errs.items():
+        assert v <= 1e-3, (k, errs)
