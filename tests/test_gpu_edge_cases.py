@@ -337,3 +337,22 @@ def test_largest_grid_3d_is_translation_invariant():
     assert el <= 1e-4, el
     for k, v in errs.items():
         assert v <= 1e-3, (k, errs)
+
+
+def test_most_instances_per_handle_match_oracle():
+    """4096 instances in one handle, the most it accepts (each a 2D block of 16
+    particles with its own design and program, on its own 8^2 grid), advanced
+    as instance groups on streams; an evenly spread sample of them, the first
+    and the last included, against the oracle in FP64."""
+    n_inst = 4096
+    insts = [_grid_limit_instance(2, 8, (2, 2), False, 10, seed=1000 + k) for k in range(n_inst)]
+    got = gpu_run(insts, precision=8)
+    pick = sorted(set(range(0, n_inst, 97)) | {1, n_inst - 1})
+    ref = oracle_run([insts[k] for k in pick])
+    p_off = np.concatenate([[0], np.cumsum([i.n for i in insts])])
+    s_off = np.concatenate([[0], np.cumsum([i.params["n_segments"] for i in insts])])
+    part = np.concatenate([np.arange(p_off[k], p_off[k + 1]) for k in pick])
+    segs = np.concatenate([np.arange(s_off[k], s_off[k + 1]) for k in pick])
+    sub = dict(x=got["x"][part], loss=got["loss"][pick], g_density=got["g_density"][part], g_br=got["g_br"][part],
+               g_b_prog=got["g_b_prog"][segs])
+    compare(sub, ref, pos_tol=1e-10, grad_tol=1e-9, loss_tol=1e-9, label=f"{n_inst} instances, {len(pick)} sampled")
