@@ -39,11 +39,14 @@ def _inst(dim, case, seed):
                                mu=0.3, vel=[0.4, 0.0, 0.0]),
                           dict(kind=HS, a=z([hi[0] - dx, 0.0, 0.0]), b=[-1.0, 0.0, 0.0], mu=math.inf)],
     }
+    # the most an instance takes: one of each kind plus a second box, in this order
+    cases["four"] = cases["sphere_slide"] + cases["halfspace_tilted_moving"] + cases["box_attached_moving"] + \
+        cases["box_noslip"]
     p["obstacles"] = cases[case]
     return W.Instance(p, inst.x0, inst.density, inst.br, inst.b_prog, inst.target, inst.mask)
 
 
-CASES = ["sphere_slide", "halfspace_tilted_moving", "box_noslip", "box_attached_moving", "floor_and_two"]
+CASES = ["sphere_slide", "halfspace_tilted_moving", "box_noslip", "box_attached_moving", "floor_and_two", "four"]
 
 
 @pytest.mark.parametrize("dim", [2, 3])
