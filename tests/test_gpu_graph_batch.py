@@ -175,6 +175,26 @@ def test_instance_groups_on_streams_match_one_stream(streams):
     compare(g, ref, pos_tol=1e-4, grad_tol=1e-3, label=f"streams={streams} graph fp32")
 
 
+def test_most_instance_groups_match_one_stream():
+    """Eight instance groups, the most the library runs (more streams than the
+    device's hardware queues), over ten instances of different grids, losses
+    and boundaries: the one-stream results in FP64, and the oracle's, also under
+    graph replay."""
+    kinds = [W.LOSS_COM_DISP, W.LOSS_FINAL_MSE, W.LOSS_TIP_DISP, W.LOSS_TRAJ_VEL]
+    insts = [W.make_tiny(seed=90 + k, dim=2, n_steps=14, loss_kind=kinds[k % 4], floor=k % 2 == 0,
+                         gravity=1.0, clamp=k % 3 == 1, size=(0.25 + 0.02 * k, 0.15, 0.2),
+                         n_grid=16 + 8 * (k % 3), n_segments=2 + k % 3) for k in range(10)]
+    one = gpu_run(insts, precision=8, options={"streams": 1})
+    many = gpu_run(insts, precision=8, options={"streams": 8})
+    errs = _max_rel(many, one)
+    log("streams 8", {k: f"{v:.2e}" for k, v in errs.items()})
+    assert all(v <= 1e-12 for v in errs.values()), errs
+    ref = oracle_run(insts)
+    compare(many, ref, pos_tol=1e-10, grad_tol=1e-9, loss_tol=1e-9, label="streams=8 fp64")
+    g = gpu_run(insts, precision=4, options={"streams": 8, "graph": 1})
+    compare(g, ref, pos_tol=1e-4, grad_tol=1e-3, label="streams=8 graph fp32")
+
+
 def test_lane_order_leaves_fp32_results_unchanged():
     """The lane order of the particle kernels only changes which lane works on
     which particle: in FP32 the grid sums are exact integers, so positions and
