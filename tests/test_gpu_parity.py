@@ -12,7 +12,7 @@ import torch
 from paper_2503_22767_amd import mpm_mag as M
 from paper_2503_22767_amd import workloads as W
 
-from gpu_util import compare, gpu_run, log, oracle_run
+from gpu_util import branch_flips, compare, gpu_run, log, oracle_run
 
 pytestmark = pytest.mark.gpu
 
@@ -96,6 +96,22 @@ def test_quadruped3d_full_size_first_steps():
     ref = oracle_run(insts, ckpt_every=1)
     got = gpu_run(insts, precision=4)
     compare(got, ref, pos_tol=1e-4, grad_tol=1e-3, label="quadruped3d[:2] tasks 0,2 fp32")
+
+
+def test_quadruped3d_full_size_fp64_one_segment():
+    """The locomotion task at full size in FP64 over its first 64 steps (one
+    checkpoint segment) against the oracle deciding its own branches, at the
+    FP64 bars. Over fewer steps the body has barely moved (7e-7 after 8 steps)
+    and the centre-of-mass loss is a difference of nearly equal centres, whose
+    rounding alone gives relative errors of 5e-12 in the loss and 2e-9 in the
+    density gradient on both sides; after 64 steps the displacement is 1.7e-5."""
+    wl = W.make_quadruped3d(n_steps=64)
+    insts = wl.instances[:1]
+    ref = oracle_run(insts, record=True)
+    got = gpu_run(insts, precision=8, trace=True)
+    log("quadruped3d[:64] task 0 fp64: branch decisions differing from the oracle's",
+        branch_flips(got["trace"], ref["trace"]))
+    compare(got, ref, pos_tol=1e-10, grad_tol=1e-9, loss_tol=1e-9, label="quadruped3d[:64] task 0 fp64")
 
 
 def _cloud(dim, seed, n=700, n_grid=32, steps=12):
