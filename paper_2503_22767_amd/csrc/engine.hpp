@@ -630,8 +630,9 @@ private:
     // stream the largest workgroup gathers a coarse block's boxes in the fewest
     // rounds (quadruped: 38 us per launch at 1024 threads, 41 at 512, 59 at
     // 256); when instance groups overlap on several streams, one-wave-per-SIMD
-    // workgroups fit beside the particle kernels' blocks sooner (quadruped:
-    // 4.38e9 particle-steps/s at 256 threads, 4.20e9 at 1024).
+    // workgroups fit beside the particle kernels' blocks sooner (quadruped,
+    // three streams: 4.76e9 particle-steps/s at 256 threads, 4.65e9 at 512,
+    // 4.44e9 at 1024).
     int grid_threads() const { return grid_threads_ > 0 ? grid_threads_ : (n_chains() > 1 ? 256 : kGridThreadsMax); }
 
     int grid_blocks_of(int q) const { return (int)std::min<int64_t>(chains_[q].ncb, grid_wgs_); }
