@@ -420,6 +420,37 @@ def codesign(wl, iters=2):
                 ms_per_iteration=round(ms, 1), loss_history=hist)
 
 
+def long_horizon(n_steps=100000):
+    """The 2D walker (30,593 particles, FP32) over the paper's horizon of its 2D
+    crawlers and walkers, 10^5 steps (Sec. 4.2): one recorded rollout and its
+    adjoint (host clock), with the scatter fallbacks over the whole rollout.
+    Particles are sorted into chunks once per rollout, so this shows whether
+    the chunks' boxes stay compact as the body moves."""
+    inst = W.make_walker2d(n_steps=n_steps).instances[0]
+    sim = M.MpmMag([inst.params], [inst.n], precision=4)
+    try:
+        x0, density, br, b_prog, target, mask = M.instance_tensors([inst], dtype=torch.float32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss, x = sim.rollout(x0, density, br, b_prog, target, mask, record=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        fwd = sim.scatter_stats()
+        gd, gb, gp = sim.backward(torch.ones(1, device="cuda"))
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        bwd = sim.scatter_stats()
+        finite = bool(torch.isfinite(gd).all() and torch.isfinite(gb).all() and torch.isfinite(gp).all())
+        shift = (x.double().mean(0).cpu().numpy() - inst.x0.mean(0)) * inst.params["n_grid"]
+    finally:
+        sim.close()
+    ps = inst.n * n_steps
+    return dict(workload="walker2d", particles=inst.n, steps=n_steps, forward_s=round(t1 - t0, 3),
+                adjoint_s=round(t2 - t1, 3), fwdadj_value=round(ps / (t2 - t0), 1), unit="particle-steps/s",
+                centre_shift_cells=[round(float(v), 2) for v in shift], scatter_fallbacks_forward=fwd,
+                scatter_fallbacks_backward=bwd, gradients_finite=finite)
+
+
 def walker_codesign(max_iters=1000, mass_eps=1e-3, lr=0.01):
     """The co-design loop on the 2D walker (30,593 particles, 2,000 steps,
     floor contact, a harmonic stimulus, 8 magnetization regions by x slab,
@@ -496,6 +527,8 @@ def main():
     ap.add_argument("--no-walker-codesign", action="store_true",
                     help="skip the walker co-design run through beta = 128 to convergence")
     ap.add_argument("--walker-codesign-only", action="store_true", help="run only the walker co-design leg")
+    ap.add_argument("--no-long-horizon", action="store_true",
+                    help="skip the walker's rollout and adjoint over 10^5 steps")
     ap.add_argument("--walker-max-iters", type=int, default=1000)
     ap.add_argument("--walker-lr", type=float, default=0.01)
     args = ap.parse_args()
@@ -620,6 +653,9 @@ def main():
     if not args.no_walker_codesign:
         rec["walker_codesign"] = walker_codesign(args.walker_max_iters, lr=args.walker_lr)
         log(f"[bench] walker co-design {rec['walker_codesign']}")
+    if not args.no_long_horizon:
+        rec["long_horizon"] = long_horizon()
+        log(f"[bench] long horizon {rec['long_horizon']}")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         cb, insts, grads = cpu_baseline(wl.name, wl)
