@@ -420,6 +420,57 @@ def codesign(wl, iters=2):
                 ms_per_iteration=round(ms, 1), loss_history=hist)
 
 
+def codesign_solid_to_convergence(wl, max_iters):
+    """The workload's tasks co-designed as in the paper's 3D cases (Sec. 4.3):
+    magnetization magnitudes and orientations of 8 regions and each task's
+    harmonic stimulus, with the topology held solid (design density 1), until
+    the paper's convergence rule holds (or max_iters). Host clock around the
+    iterations."""
+    from paper_2503_22767_amd import codesign as CD
+    insts = wl.instances
+    x0 = insts[0].x0
+    if not all(np.array_equal(i.x0, x0) for i in insts):
+        return None
+    params = []
+    for i in insts:
+        p = dict(i.params)
+        p.update(n_segments=wl.n_steps, seg_steps=1, periodic=0)
+        params.append(p)
+    n, d = len(x0), insts[0].params["dim"]
+    h = insts[0].params["particle_volume"] ** (1.0 / d)
+    T, dt = wl.n_steps, insts[0].params["dt"]
+    region = np.clip(((x0[:, 0] - x0[:, 0].min()) / np.ptp(x0[:, 0]) * 8).astype(np.int32), 0, 7)
+    cfg = CD.CoDesignConfig(radius=1.5 * h, b_max=0.5, f_min=2.0 / (T * dt), f_max=20.0 / (T * dt), lr=0.01,
+                            bounds=CD.Bounds(phi=(1.0, 1.0)))
+    cd = CD.CoDesign(params, x0, cfg, region=region, n_regions=8,
+                     targets=[i.target if i.target is not None else i.x0 for i in insts],
+                     masks=[i.mask if i.mask is not None else np.ones(n, np.uint8) for i in insts],
+                     precision=wl.precision, seed=3, init={"phi": np.ones(n)})
+    err = None
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while cd.iteration < max_iters and not cd.converged():
+            try:
+                cd.step()
+            except M.MpmMagError as e:
+                err = f"iteration {cd.iteration}: {e}"
+                break
+            if cd.iteration % 10 == 0:
+                log(f"[bench] solid co-design iteration {cd.iteration}, loss {cd.history[-1]:.6g}, "
+                    f"{(time.perf_counter() - t0) / cd.iteration:.2f} s per iteration")
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        conv = cd.converged()
+    finally:
+        cd.close()
+    hist = cd.history
+    return dict(tasks=len(insts), particles_per_task=n, steps=T, regions=8, topology="held solid",
+                iterations=len(hist), converged=conv, s_per_iteration=round(el / max(1, len(hist)), 3),
+                loss_first=hist[0] if hist else None, loss_last=hist[-1] if hist else None, error=err,
+                loss_every_10=[float(f"{v:.5g}") for v in hist[::10]])
+
+
 def long_horizon(n_steps=100000):
     """The 2D walker (30,593 particles, FP32) over the paper's horizon of its 2D
     crawlers and walkers, 10^5 steps (Sec. 4.2): one recorded rollout and its
@@ -527,6 +578,10 @@ def main():
     ap.add_argument("--no-walker-codesign", action="store_true",
                     help="skip the walker co-design run through beta = 128 to convergence")
     ap.add_argument("--walker-codesign-only", action="store_true", help="run only the walker co-design leg")
+    ap.add_argument("--codesign-converge", type=int, default=0, metavar="MAX",
+                    help="also co-design the workload's tasks with the topology held solid (the paper's 3D "
+                         "cases) until the convergence rule holds, at most MAX iterations (off by default: "
+                         "minutes on the quadruped)")
     ap.add_argument("--no-long-horizon", action="store_true",
                     help="skip the walker's rollout and adjoint over 10^5 steps")
     ap.add_argument("--walker-max-iters", type=int, default=1000)
@@ -650,6 +705,9 @@ def main():
         if cd is not None:
             rec["codesign"] = cd
             log(f"[bench] co-design {cd}")
+    if args.codesign_converge > 0:
+        rec["codesign_converge"] = codesign_solid_to_convergence(wl, args.codesign_converge)
+        log(f"[bench] solid co-design {rec['codesign_converge']}")
     if not args.no_walker_codesign:
         rec["walker_codesign"] = walker_codesign(args.walker_max_iters, lr=args.walker_lr)
         log(f"[bench] walker co-design {rec['walker_codesign']}")
