@@ -420,12 +420,15 @@ def codesign(wl, iters=2):
                 ms_per_iteration=round(ms, 1), loss_history=hist)
 
 
-def codesign_solid_to_convergence(wl, max_iters):
-    """The workload's tasks co-designed as in the paper's 3D cases (Sec. 4.3):
-    magnetization magnitudes and orientations of 8 regions and each task's
-    harmonic stimulus, with the topology held solid (design density 1), until
-    the paper's convergence rule holds (or max_iters). Host clock around the
-    iterations."""
+def codesign_to_convergence(wl, max_iters, topology=False, mass_eps=1e-3):
+    """The workload's tasks co-designed until the paper's convergence rule
+    holds (or max_iters): magnetization magnitudes and orientations of 8
+    regions and each task's harmonic stimulus, from a solid design (density 1).
+    Without topology the density stays at 1, as in the paper's 3D cases (Sec.
+    4.3); with it the per-particle topology is optimized too, under the beta
+    continuation, with void particles' mass floored at mass_eps, and the rule
+    is taken over the iterations at the capped sharpness. Host clock around
+    the iterations."""
     from paper_2503_22767_amd import codesign as CD
     insts = wl.instances
     x0 = insts[0].x0
@@ -435,13 +438,15 @@ def codesign_solid_to_convergence(wl, max_iters):
     for i in insts:
         p = dict(i.params)
         p.update(n_segments=wl.n_steps, seg_steps=1, periodic=0)
+        if topology:
+            p.update(mass_eps=mass_eps)
         params.append(p)
     n, d = len(x0), insts[0].params["dim"]
     h = insts[0].params["particle_volume"] ** (1.0 / d)
     T, dt = wl.n_steps, insts[0].params["dt"]
     region = np.clip(((x0[:, 0] - x0[:, 0].min()) / np.ptp(x0[:, 0]) * 8).astype(np.int32), 0, 7)
     cfg = CD.CoDesignConfig(radius=1.5 * h, b_max=0.5, f_min=2.0 / (T * dt), f_max=20.0 / (T * dt), lr=0.01,
-                            bounds=CD.Bounds(phi=(1.0, 1.0)))
+                            bounds=CD.Bounds() if topology else CD.Bounds(phi=(1.0, 1.0)))
     cd = CD.CoDesign(params, x0, cfg, region=region, n_regions=8,
                      targets=[i.target if i.target is not None else i.x0 for i in insts],
                      masks=[i.mask if i.mask is not None else np.ones(n, np.uint8) for i in insts],
@@ -450,22 +455,24 @@ def codesign_solid_to_convergence(wl, max_iters):
     try:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        while cd.iteration < max_iters and not cd.converged():
+        while cd.iteration < max_iters and not cd.converged(at_final_beta=topology):
             try:
                 cd.step()
             except M.MpmMagError as e:
                 err = f"iteration {cd.iteration}: {e}"
                 break
             if cd.iteration % 10 == 0:
-                log(f"[bench] solid co-design iteration {cd.iteration}, loss {cd.history[-1]:.6g}, "
+                log(f"[bench] co-design to convergence, iteration {cd.iteration}, beta {cd.beta:g}, "
+                    f"loss {cd.history[-1]:.6g}, "
                     f"{(time.perf_counter() - t0) / cd.iteration:.2f} s per iteration")
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        conv = cd.converged()
+        conv = cd.converged(at_final_beta=topology)
     finally:
         cd.close()
     hist = cd.history
-    return dict(tasks=len(insts), particles_per_task=n, steps=T, regions=8, topology="held solid",
+    return dict(tasks=len(insts), particles_per_task=n, steps=T, regions=8,
+                topology=f"optimized from solid, mass floor {mass_eps}" if topology else "held solid",
                 iterations=len(hist), converged=conv, s_per_iteration=round(el / max(1, len(hist)), 3),
                 loss_first=hist[0] if hist else None, loss_last=hist[-1] if hist else None, error=err,
                 loss_every_10=[float(f"{v:.5g}") for v in hist[::10]])
@@ -579,9 +586,11 @@ def main():
                     help="skip the walker co-design run through beta = 128 to convergence")
     ap.add_argument("--walker-codesign-only", action="store_true", help="run only the walker co-design leg")
     ap.add_argument("--codesign-converge", type=int, default=0, metavar="MAX",
-                    help="also co-design the workload's tasks with the topology held solid (the paper's 3D "
-                         "cases) until the convergence rule holds, at most MAX iterations (off by default: "
-                         "minutes on the quadruped)")
+                    help="also co-design the workload's tasks from a solid design, with the topology held solid "
+                         "(the paper's 3D cases), until the convergence rule holds, at most MAX iterations (off by "
+                         "default: minutes on the quadruped)")
+    ap.add_argument("--codesign-converge-topology", action="store_true",
+                    help="with --codesign-converge: optimize the per-particle topology too, from a solid start")
     ap.add_argument("--no-long-horizon", action="store_true",
                     help="skip the walker's rollout and adjoint over 10^5 steps")
     ap.add_argument("--walker-max-iters", type=int, default=1000)
@@ -706,8 +715,9 @@ def main():
             rec["codesign"] = cd
             log(f"[bench] co-design {cd}")
     if args.codesign_converge > 0:
-        rec["codesign_converge"] = codesign_solid_to_convergence(wl, args.codesign_converge)
-        log(f"[bench] solid co-design {rec['codesign_converge']}")
+        rec["codesign_converge"] = codesign_to_convergence(wl, args.codesign_converge,
+                                                           topology=args.codesign_converge_topology)
+        log(f"[bench] co-design to convergence {rec['codesign_converge']}")
     if not args.no_walker_codesign:
         rec["walker_codesign"] = walker_codesign(args.walker_max_iters, lr=args.walker_lr)
         log(f"[bench] walker co-design {rec['walker_codesign']}")
